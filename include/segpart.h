@@ -1,0 +1,257 @@
+/*
+ * segpart.h -- C ABI of libsegpart, a single-GPU (AMD MI355X, gfx950) time
+ * stepper for the eigenfunction-segregation method of Elliott & Ranner,
+ * "A computational approach to an optimal partition problem on surfaces"
+ * (arXiv 1408.2355).
+ *
+ * The method (Section 2 of the paper) looks for m nonnegative functions u_i
+ * on a triangulated closed surface Gamma_h, each of unit L2 norm, that
+ * minimise sum_i int |grad u_i|^2 plus the segregation penalty
+ * (1/eps^2) int sum_i sum_{j!=i} u_i^2 u_j^2.  It runs the operator-splitting
+ * gradient flow of Algorithm 2.2: per time step tau,
+ *   1. heat step   (M + tau A) u~_i = M u_i            (implicit Euler, P1 FEM)
+ *   2. node step   u^_i = u~_i exp(-(2 tau/eps^2)(S - u~_i^2)),  S = sum_j u~_j^2
+ *   3. normalise   u_i = u^_i / ||u^_i||_{L2(Gamma_h)}
+ * and reads off the eigenvalue estimates lambda_i = u_i^T A u_i / u_i^T M u_i
+ * (Section 3.2), S_eps (equation Seps-u), E = sum lambda_i + S_eps, and the
+ * partition {v_i > 0}, v_i = u_i - sum_{j!=i} u_j (equation vi).
+ *
+ * Conventions shared by every entry point:
+ *  - Every int-returning call returns SP_OK (0) or a negative status below;
+ *    no C++ exception crosses the ABI.  sp_last_error() gives the message of
+ *    the last failure on the calling thread.
+ *  - Pointers named d_* are device pointers (HIP global memory on the current
+ *    device); all other array pointers are host pointers.  The caller owns
+ *    every buffer it passes; the library copies inputs during the call and
+ *    never keeps a caller pointer after returning (except the async call,
+ *    whose buffers must stay valid until its stream passes the call).
+ *  - Vertex numbering is always the caller's: the library may renumber
+ *    vertices internally for locality and undoes it on output.
+ *  - A batch holds n_restarts independent restarts.  Restart r has m[r] >= 1
+ *    components and its own eps[r] > 0; all restarts of a batch share the
+ *    mesh and tau.  State arrays u0 / u are float64 with shape
+ *    [sum_r m[r]][n_vert]: restart r's components are the m[r] consecutive
+ *    rows starting at sum_{s<r} m[s], one component per row.
+ *  - Per-component outputs (lambda) have length sum_r m[r] in the same
+ *    order; per-restart outputs (s_eps, energy) have length n_restarts;
+ *    labels are int32 [n_restarts][n_vert].
+ */
+#ifndef SEGPART_H
+#define SEGPART_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SP_VERSION_MAJOR 1
+#define SP_VERSION_MINOR 0
+
+enum sp_status {
+  SP_OK = 0,
+  SP_EINVAL = -1,    /* invalid argument (sizes, m < 1, eps <= 0, tau <= 0, NaN input,
+                        a component of u0 with zero L2 norm, bad stage id ...)   */
+  SP_EMESH = -2,     /* not a closed triangulated surface: index out of range, zero-area
+                        triangle, an edge not shared by exactly two triangles      */
+  SP_ENOMEM = -3,    /* host or device allocation failed, or the server's HBM budget
+                        cannot hold the request                                    */
+  SP_EDEVICE = -4,   /* HIP runtime error (no device, launch failure ...)          */
+  SP_ENOCONV = -5,   /* a linear solve reached its iteration cap before its
+                        tolerance; all outputs were still written                   */
+  SP_EAGAIN = -6,    /* server: the request has not finished yet                   */
+  SP_ENOTFOUND = -7  /* server: unknown or already fetched ticket                  */
+};
+
+/* Message of the last failure on this thread ("" if none).  Never NULL. */
+const char* sp_last_error(void);
+/* Library version; either pointer may be NULL. */
+int sp_version(int* major, int* minor);
+
+/* ------------------------------------------------------------------ mesh --
+ * The triangulated surface Gamma_h of Section 2.1: vertices on the smooth
+ * surface, flat triangles, P1 space S_h.  Creating a mesh validates it,
+ * assembles the consistent mass matrix M (int phi_z phi_w) and the stiffness
+ * matrix A (int grad phi_z . grad phi_w) on the GPU and keeps them there.
+ */
+typedef struct sp_mesh sp_mesh;
+
+/* xyz: host float64 [n_vert][3]; tri: host int32 [n_tri][3] vertex indices.
+ * Errors: SP_EINVAL (n_vert < 3, n_tri < 1, NULL), SP_EMESH (see above),
+ * SP_ENOMEM, SP_EDEVICE.  On success *out owns device memory until
+ * sp_mesh_destroy. */
+int sp_mesh_create(int64_t n_vert, const double* xyz, int64_t n_tri, const int32_t* tri,
+                   sp_mesh** out);
+/* Sizes of a mesh: vertices, triangles, stored nonzeros of M (and of A, same
+ * pattern), and |Gamma_h| = sum of triangle areas.  NULL outputs are skipped. */
+int sp_mesh_info(const sp_mesh* mesh, int64_t* n_vert, int64_t* n_tri, int64_t* nnz,
+                 double* area);
+enum { SP_MAT_M = 0, SP_MAT_A = 1 };
+/* Copy M (which = SP_MAT_M) or A (SP_MAT_A) out as CSR in the caller's vertex
+ * numbering, columns sorted within each row.  row_ptr [n_vert + 1] int64,
+ * col [nnz] int32, val [nnz] float64 (host). */
+int sp_mesh_export(const sp_mesh* mesh, int32_t which, int64_t* row_ptr, int32_t* col,
+                   double* val);
+/* Frees the mesh.  Every state, solve and server request using it must be
+ * finished first.  NULL is ignored. */
+void sp_mesh_destroy(sp_mesh* mesh);
+
+/* ------------------------------------------------------------- parameters --
+ * precision SP_FP64: every vector and reduction in float64, plain Jacobi-
+ * preconditioned CG on (M + tau A) per column.
+ * precision SP_MIXED: float64 outer iterative refinement (residual
+ * r = b - (M + tau A) x in float64, x += d) around float32 Jacobi-CG inner
+ * solves for d; the M-norm, the node step and the energies stay float64.
+ */
+enum { SP_FP64 = 0, SP_MIXED = 1 };
+
+typedef struct {
+  double tau;           /* time step, > 0 (Algorithm 2.2)                           */
+  int64_t n_steps;      /* > 0: run exactly this many steps.  0: run until E changes
+                           by less than stop_tol between two energy checks, per
+                           restart (Section 2.2), at most max_steps                 */
+  double stop_tol;      /* stopping threshold on |E_k - E_{k-energy_every}| (paper: 1e-6) */
+  int64_t max_steps;    /* cap for n_steps == 0                                      */
+  int64_t energy_every; /* energy cadence in steps (paper: M_tau with M_tau tau = 0.1);
+                           0 = energy only at the end (not allowed with n_steps == 0) */
+  int32_t precision;    /* SP_FP64 or SP_MIXED                                       */
+  double cg_rtol;       /* per column stop when ||b - (M+tau A) x||_2 <= cg_rtol ||M u||_2 */
+  int32_t cg_max_iter;  /* cap on CG iterations per solve (per inner solve in SP_MIXED) */
+  double inner_rtol;    /* SP_MIXED: relative residual reduction of each float32 solve */
+  int32_t max_outer;    /* SP_MIXED: cap on refinement sweeps per time step          */
+  int32_t check_every;  /* CG iterations between host-side convergence polls; 0 = no
+                           polling (cg_max_iter device iterations are enqueued and the
+                           kernels exit at once after convergence)                  */
+  int32_t reserved;
+} sp_params;
+
+/* Fill *p with defaults for time step tau: n_steps 100, stop_tol 1e-6,
+ * max_steps 10^6, energy_every = round(0.1 / tau), SP_MIXED, cg_rtol 1e-10,
+ * cg_max_iter 500, inner_rtol 1e-5, max_outer 8, check_every 8. */
+void sp_params_default(sp_params* p, double tau);
+
+typedef struct {
+  int64_t steps_done;      /* time steps taken (max over restarts)                   */
+  int64_t cg_iters;        /* CG iterations, summed over steps (and sweeps), counting
+                              the slowest column of each solve                        */
+  int64_t outer_sweeps;    /* SP_MIXED refinement sweeps summed over steps            */
+  int64_t col_iters_max;   /* largest per-column CG iteration total                  */
+  double seconds;          /* wall time of the call                                   */
+  int32_t converged;       /* 1 if every solve met its tolerance                      */
+  int32_t reserved;
+} sp_stats;
+
+/* ------------------------------------------------------------- batch solve --
+ * Run a batch of restarts for prm->n_steps steps (or to the stop rule) and
+ * return the final state and its energies and labels.
+ * m [n_restarts], eps [n_restarts], u0 [sum m][n_vert] (host, not normalised:
+ * each component is first scaled to unit L2 norm, as the random start of
+ * Section 2.2 does).  Outputs, each nullable: u_out like u0; labels and
+ * labels_argmax [n_restarts][n_vert] (v-partition with -1 = void, and argmax
+ * of u); lambda [sum m]; s_eps, energy [n_restarts]; stats.
+ * Returns SP_ENOCONV (after writing outputs) if some CG solve hit its cap. */
+int sp_solve(const sp_mesh* mesh, const sp_params* prm, int32_t n_restarts, const int32_t* m,
+             const double* eps, const double* u0, double* u_out, int32_t* labels,
+             int32_t* labels_argmax, double* lambda, double* s_eps, double* energy,
+             sp_stats* stats);
+
+/* Device-pointer form: inputs and outputs in device memory, all work enqueued
+ * on hip_stream (a hipStream_t passed as void*; NULL = default stream).  m and
+ * eps stay host arrays.  With prm->check_every == 0 and n_steps > 0 the call
+ * returns without waiting for the GPU; otherwise it synchronises the stream
+ * when it polls convergence.  Work buffers are allocated and freed by the
+ * call (freed after the stream is synchronised).  Nullable outputs as in
+ * sp_solve.  Stop mode (n_steps == 0) is not available here (SP_EINVAL). */
+int sp_solve_async(const sp_mesh* mesh, const sp_params* prm, int32_t n_restarts,
+                   const int32_t* m, const double* eps, const double* d_u0, double* d_u_out,
+                   int32_t* d_labels, int32_t* d_labels_argmax, double* d_lambda,
+                   double* d_s_eps, double* d_energy, void* hip_stream);
+
+/* ------------------------------------------------------------ step state --
+ * A batch kept on the device between calls: stepping, single stages of
+ * Algorithm 2.2, energies, checkpoint and restore.  A state is used by one
+ * thread at a time. */
+typedef struct sp_state sp_state;
+
+/* u0 as in sp_solve (normalised on upload).  hip_stream as in
+ * sp_solve_async (NULL: the library creates its own stream). */
+int sp_state_create(const sp_mesh* mesh, const sp_params* prm, int32_t n_restarts,
+                    const int32_t* m, const double* eps, const double* u0, void* hip_stream,
+                    sp_state** out);
+/* Advance every restart by k >= 1 full time steps (steps 1-3 of Algorithm
+ * 2.2), with energies at the cadence of prm->energy_every.  Synchronous.
+ * Returns SP_ENOCONV if a solve hit its cap (the steps were still taken). */
+int sp_state_step(sp_state* st, int64_t k);
+
+/* One stage of Algorithm 2.2 applied in place to the current state:
+ * SP_STAGE_HEAT  u <- (M + tau A)^{-1} M u         (step 1)
+ * SP_STAGE_NODE  u <- u exp(-(2 tau/eps^2)(S - u^2)) (step 2)
+ * SP_STAGE_NORM  u <- u / ||u||_{L2(Gamma_h)}       (step 3)
+ * The step counter is not advanced. */
+enum { SP_STAGE_HEAT = 1, SP_STAGE_NODE = 2, SP_STAGE_NORM = 3 };
+int sp_state_stage(sp_state* st, int32_t stage);
+
+/* Evaluate lambda [sum m], s_eps and energy [n_restarts] of the current state
+ * now (float64 on the GPU).  Nullable outputs. */
+int sp_state_energy(sp_state* st, double* lambda, double* s_eps, double* energy);
+/* Copy the current state out ([sum m][n_vert], host) and the step counter. */
+int sp_state_read(sp_state* st, double* u, int64_t* step);
+/* Overwrite the state (checkpoint restore / parity set-up) and step counter;
+ * normalise != 0 scales each component to unit L2 norm first. */
+int sp_state_write(sp_state* st, const double* u, int64_t step, int32_t normalise);
+/* Labels of the current state, [n_restarts][n_vert] each (nullable). */
+int sp_state_labels(sp_state* st, int32_t* labels, int32_t* labels_argmax);
+/* Energy history of restart r: up to cap (step, E) pairs, oldest first;
+ * *count receives the number available. */
+int sp_state_history(sp_state* st, int32_t r, int64_t cap, int64_t* steps, double* energies,
+                     int64_t* count);
+int sp_state_stats(sp_state* st, sp_stats* stats);
+/* Kernel timing with HIP events on the state's stream, for the dominant
+ * kernel class of the time step (the CG matrix product).  enable != 0 starts
+ * recording (and clears the totals). */
+int sp_state_profile(sp_state* st, int32_t enable);
+/* Launch count and summed duration (ms) of the CG matrix-product kernel since
+ * profiling was enabled, plus its algorithmic bytes per launch (float32
+ * vectors in SP_MIXED, float64 in SP_FP64). */
+int sp_state_kernel_time(sp_state* st, int64_t* launches, double* total_ms,
+                         double* bytes_per_launch);
+void sp_state_destroy(sp_state* st);
+
+/* --------------------------------------------------------------- serving --
+ * A request loop on one GPU.  Requests (a mesh, parameters, restarts and
+ * u0) are queued; a scheduler thread admits them into column slots of
+ * per-(mesh, tau, precision) batches while the HBM budget allows, advances
+ * every resident batch one time step per round, and retires requests as they
+ * finish, so requests that arrive while others run join the running batch
+ * (continuous batching).  Thread-safe. */
+typedef struct sp_server sp_server;
+
+/* hbm_budget_bytes: cap on device memory for request state (matrices of
+ * resident meshes are counted too).  max_batch_columns: column capacity of
+ * one batch (0 = default 4096). */
+int sp_server_create(int64_t hbm_budget_bytes, int32_t max_batch_columns, sp_server** out);
+/* Queue a request (inputs copied; prm->n_steps must be > 0).  Returns at once
+ * with a ticket.  SP_ENOMEM if the request alone exceeds the budget. */
+int sp_server_submit(sp_server* srv, const sp_mesh* mesh, const sp_params* prm,
+                     int32_t n_restarts, const int32_t* m, const double* eps, const double* u0,
+                     int64_t* ticket);
+/* *done = 1 once the request finished (results ready to fetch). */
+int sp_server_poll(sp_server* srv, int64_t ticket, int32_t* done);
+/* Block until the request finished or timeout_s elapsed (SP_EAGAIN). */
+int sp_server_wait(sp_server* srv, int64_t ticket, double timeout_s);
+/* Copy out and release a finished request's results (nullable outputs, layouts
+ * as in sp_solve) and its latency (finish - submit, seconds).  SP_EAGAIN if
+ * not finished, SP_ENOTFOUND for an unknown ticket. */
+int sp_server_fetch(sp_server* srv, int64_t ticket, double* u_out, int32_t* labels,
+                    double* lambda, double* s_eps, double* energy, double* latency_s);
+/* Latency percentiles over finished requests, achieved component-DOF updates
+ * per second since the first submit, and the number of finished requests. */
+int sp_server_stats(sp_server* srv, double* p50_s, double* p99_s, double* cdof_per_s,
+                    int64_t* completed);
+/* Stops the scheduler (abandoning unfinished requests) and frees everything. */
+void sp_server_destroy(sp_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SEGPART_H */

@@ -1,0 +1,401 @@
+// extern "C" entry points of libsegpart (declared in include/segpart.h).
+// Every call catches all exceptions and turns them into a status code plus a
+// thread-local message.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+
+#include "engine.h"
+#include "server.h"
+
+struct sp_mesh {
+  std::unique_ptr<sp::Mesh> m;
+};
+
+struct sp_state {
+  sp::Mesh* mesh = nullptr;
+  std::unique_ptr<sp::Solver> solver;
+};
+
+struct sp_server {
+  std::unique_ptr<sp::Server> srv;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+template <class F>
+int guard(F&& f) {
+  try {
+    g_err.clear();
+    sp::reap_deferred();
+    return f();
+  } catch (const sp::Error& e) {
+    g_err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return SP_ENOMEM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return SP_EDEVICE;
+  } catch (...) {
+    g_err = "unknown error";
+    return SP_EDEVICE;
+  }
+}
+
+sp::BatchSpec make_spec(int32_t nres, const int32_t* m, const double* eps) {
+  sp::validate_batch(nres, m, eps);
+  sp::BatchSpec s;
+  s.m.assign(m, m + nres);
+  s.eps.assign(eps, eps + nres);
+  return s;
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sp_last_error(void) { return g_err.c_str(); }
+
+int sp_version(int* major, int* minor) {
+  if (major) *major = SP_VERSION_MAJOR;
+  if (minor) *minor = SP_VERSION_MINOR;
+  return SP_OK;
+}
+
+void sp_params_default(sp_params* p, double tau) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->tau = tau;
+  p->n_steps = 100;
+  p->stop_tol = 1e-6;
+  p->max_steps = 1000000;
+  p->energy_every = tau > 0 ? std::max<int64_t>(1, std::llround(0.1 / tau)) : 1;
+  p->precision = SP_MIXED;
+  p->cg_rtol = 1e-10;
+  p->cg_max_iter = 500;
+  p->inner_rtol = 1e-5;
+  p->max_outer = 8;
+  p->check_every = 8;
+}
+
+int sp_mesh_create(int64_t n_vert, const double* xyz, int64_t n_tri, const int32_t* tri,
+                   sp_mesh** out) {
+  return guard([&] {
+    SP_REQUIRE(out != nullptr, SP_EINVAL, "NULL out");
+    *out = nullptr;
+    std::unique_ptr<sp_mesh> h(new sp_mesh());
+    h->m.reset(sp::mesh_create(n_vert, xyz, n_tri, tri));
+    *out = h.release();
+    return SP_OK;
+  });
+}
+
+int sp_mesh_info(const sp_mesh* mesh, int64_t* n_vert, int64_t* n_tri, int64_t* nnz,
+                 double* area) {
+  return guard([&] {
+    SP_REQUIRE(mesh && mesh->m, SP_EINVAL, "NULL mesh");
+    if (n_vert) *n_vert = mesh->m->n;
+    if (n_tri) *n_tri = mesh->m->nt;
+    if (nnz) *nnz = mesh->m->nnz;
+    if (area) *area = mesh->m->area;
+    return SP_OK;
+  });
+}
+
+int sp_mesh_export(const sp_mesh* mesh, int32_t which, int64_t* row_ptr, int32_t* col,
+                   double* val) {
+  return guard([&] {
+    SP_REQUIRE(mesh && mesh->m, SP_EINVAL, "NULL mesh");
+    SP_REQUIRE(which == SP_MAT_M || which == SP_MAT_A, SP_EINVAL, "which must be SP_MAT_M or SP_MAT_A");
+    SP_REQUIRE(row_ptr && col && val, SP_EINVAL, "NULL output");
+    const sp::Mesh& m = *mesh->m;
+    const size_t cnt = size_t(m.W) * m.n;
+    std::vector<double> v(cnt);
+    const sp::DevBuf<double>& src = which == SP_MAT_M ? m.M64 : m.A64;
+    SP_HIP(hipMemcpy(v.data(), src.p, cnt * sizeof(double), hipMemcpyDeviceToHost));
+    std::vector<std::pair<int32_t, double>> row;
+    int64_t pos = 0;
+    row_ptr[0] = 0;
+    for (int64_t r = 0; r < m.n; ++r) {
+      const int64_t i = m.iperm[r];
+      row.clear();
+      for (int k = 0; k < m.W; ++k) {
+        const int32_t c = m.h_cols[size_t(k) * m.n + i];
+        if (k > 0 && c == i) continue;  // padding slot
+        row.push_back({m.perm[c], v[size_t(k) * m.n + i]});
+      }
+      std::sort(row.begin(), row.end());
+      for (auto& e : row) {
+        col[pos] = e.first;
+        val[pos] = e.second;
+        ++pos;
+      }
+      row_ptr[r + 1] = pos;
+    }
+    return SP_OK;
+  });
+}
+
+void sp_mesh_destroy(sp_mesh* mesh) { delete mesh; }
+
+int sp_solve(const sp_mesh* mesh, const sp_params* prm, int32_t n_restarts, const int32_t* m,
+             const double* eps, const double* u0, double* u_out, int32_t* labels,
+             int32_t* labels_argmax, double* lambda, double* s_eps, double* energy,
+             sp_stats* stats) {
+  return guard([&] {
+    const double t0 = now_s();
+    SP_REQUIRE(mesh && mesh->m && prm, SP_EINVAL, "NULL mesh or params");
+    sp::BatchSpec spec = make_spec(n_restarts, m, eps);
+    sp::Solver S(mesh->m.get(), *prm, spec, nullptr);  // private stream
+    S.upload_host(u0, true);
+    if (prm->n_steps > 0)
+      S.step(prm->n_steps);
+    else
+      S.run_to_stop();
+    S.energy_to_host(lambda, s_eps, energy);
+    if (labels || labels_argmax) S.labels_host(labels, labels_argmax);
+    if (u_out) S.download_host(u_out);
+    sp_stats st = S.stats();
+    st.seconds = now_s() - t0;
+    if (stats) *stats = st;
+    return st.converged ? SP_OK : SP_ENOCONV;
+  });
+}
+
+int sp_solve_async(const sp_mesh* mesh, const sp_params* prm, int32_t n_restarts,
+                   const int32_t* m, const double* eps, const double* d_u0, double* d_u_out,
+                   int32_t* d_labels, int32_t* d_labels_argmax, double* d_lambda,
+                   double* d_s_eps, double* d_energy, void* hip_stream) {
+  return guard([&] {
+    SP_REQUIRE(mesh && mesh->m && prm, SP_EINVAL, "NULL mesh or params");
+    SP_REQUIRE(prm->n_steps > 0, SP_EINVAL, "sp_solve_async needs n_steps > 0");
+    sp::BatchSpec spec = make_spec(n_restarts, m, eps);
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);  // NULL = default stream
+    auto* S = new sp::Solver(mesh->m.get(), *prm, spec, &s);
+    int rc = SP_OK;
+    try {
+      S->record_history = false;
+      S->upload_device(d_u0, true, false);
+      S->step(prm->n_steps);
+      S->energy();
+      const int R = S->R(), nres = S->nres();
+      if (d_lambda)
+        SP_HIP(hipMemcpyAsync(d_lambda, S->d_lam(), R * sizeof(double), hipMemcpyDeviceToDevice, s));
+      if (d_s_eps)
+        SP_HIP(hipMemcpyAsync(d_s_eps, S->d_seps(), nres * sizeof(double), hipMemcpyDeviceToDevice, s));
+      if (d_energy)
+        SP_HIP(hipMemcpyAsync(d_energy, S->d_energy(), nres * sizeof(double), hipMemcpyDeviceToDevice,
+                              s));
+      if (d_labels || d_labels_argmax) S->labels_device(d_labels, d_labels_argmax);
+      if (d_u_out) S->download_device(d_u_out);
+    } catch (...) {
+      delete S;
+      throw;
+    }
+    // The solver's buffers must outlive the enqueued work: free them from a
+    // host callback once the stream reaches this point.
+    S->detach();
+    hipError_t e = hipLaunchHostFunc(
+        s, [](void* p) { sp::defer_delete(static_cast<sp::Solver*>(p)); }, S);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipStreamSynchronize(s);
+      delete S;
+      throw sp::Error(SP_EDEVICE, std::string("hipLaunchHostFunc: ") + hipGetErrorString(e));
+    }
+    return rc;
+  });
+}
+
+int sp_state_create(const sp_mesh* mesh, const sp_params* prm, int32_t n_restarts,
+                    const int32_t* m, const double* eps, const double* u0, void* hip_stream,
+                    sp_state** out) {
+  return guard([&] {
+    SP_REQUIRE(out != nullptr, SP_EINVAL, "NULL out");
+    *out = nullptr;
+    SP_REQUIRE(mesh && mesh->m && prm, SP_EINVAL, "NULL mesh or params");
+    sp::BatchSpec spec = make_spec(n_restarts, m, eps);
+    std::unique_ptr<sp_state> st(new sp_state());
+    st->mesh = mesh->m.get();
+    hipStream_t hs = reinterpret_cast<hipStream_t>(hip_stream);
+    st->solver.reset(new sp::Solver(mesh->m.get(), *prm, spec, hs ? &hs : nullptr));
+    st->solver->upload_host(u0, true);
+    *out = st.release();
+    return SP_OK;
+  });
+}
+
+int sp_state_step(sp_state* st, int64_t k) {
+  return guard([&] {
+    SP_REQUIRE(st && st->solver, SP_EINVAL, "NULL state");
+    SP_REQUIRE(k >= 1, SP_EINVAL, "k must be >= 1");
+    st->solver->step(k);
+    st->solver->sync();
+    return st->solver->converged() ? SP_OK : SP_ENOCONV;
+  });
+}
+
+int sp_state_stage(sp_state* st, int32_t stage) {
+  return guard([&] {
+    SP_REQUIRE(st && st->solver, SP_EINVAL, "NULL state");
+    switch (stage) {
+      case SP_STAGE_HEAT: st->solver->stage_heat(); break;
+      case SP_STAGE_NODE: st->solver->stage_node(); break;
+      case SP_STAGE_NORM: st->solver->stage_norm(); break;
+      default: throw sp::Error(SP_EINVAL, "unknown stage");
+    }
+    st->solver->sync();
+    return SP_OK;
+  });
+}
+
+int sp_state_energy(sp_state* st, double* lambda, double* s_eps, double* energy) {
+  return guard([&] {
+    SP_REQUIRE(st && st->solver, SP_EINVAL, "NULL state");
+    st->solver->energy_to_host(lambda, s_eps, energy);
+    return SP_OK;
+  });
+}
+
+int sp_state_read(sp_state* st, double* u, int64_t* step) {
+  return guard([&] {
+    SP_REQUIRE(st && st->solver, SP_EINVAL, "NULL state");
+    if (u) st->solver->download_host(u);
+    if (step) *step = st->solver->steps_done();
+    return SP_OK;
+  });
+}
+
+int sp_state_write(sp_state* st, const double* u, int64_t step, int32_t normalise) {
+  return guard([&] {
+    SP_REQUIRE(st && st->solver, SP_EINVAL, "NULL state");
+    SP_REQUIRE(step >= 0, SP_EINVAL, "step must be >= 0");
+    st->solver->upload_host(u, normalise != 0);
+    st->solver->set_steps_done(step);
+    return SP_OK;
+  });
+}
+
+int sp_state_labels(sp_state* st, int32_t* labels, int32_t* labels_argmax) {
+  return guard([&] {
+    SP_REQUIRE(st && st->solver, SP_EINVAL, "NULL state");
+    st->solver->labels_host(labels, labels_argmax);
+    return SP_OK;
+  });
+}
+
+int sp_state_history(sp_state* st, int32_t r, int64_t cap, int64_t* steps, double* energies,
+                     int64_t* count) {
+  return guard([&] {
+    SP_REQUIRE(st && st->solver, SP_EINVAL, "NULL state");
+    const auto& h = st->solver->history();
+    SP_REQUIRE(r >= 0 && r < int32_t(h.size()), SP_EINVAL, "restart index out of range");
+    const auto& v = h[r];
+    if (count) *count = int64_t(v.size());
+    for (int64_t i = 0; i < cap && i < int64_t(v.size()); ++i) {
+      if (steps) steps[i] = v[i].first;
+      if (energies) energies[i] = v[i].second;
+    }
+    return SP_OK;
+  });
+}
+
+int sp_state_stats(sp_state* st, sp_stats* stats) {
+  return guard([&] {
+    SP_REQUIRE(st && st->solver && stats, SP_EINVAL, "NULL state or stats");
+    *stats = st->solver->stats();
+    return SP_OK;
+  });
+}
+
+int sp_state_profile(sp_state* st, int32_t enable) {
+  return guard([&] {
+    SP_REQUIRE(st && st->solver, SP_EINVAL, "NULL state");
+    st->solver->profile(enable != 0);
+    return SP_OK;
+  });
+}
+
+int sp_state_kernel_time(sp_state* st, int64_t* launches, double* total_ms,
+                         double* bytes_per_launch) {
+  return guard([&] {
+    SP_REQUIRE(st && st->solver, SP_EINVAL, "NULL state");
+    st->solver->kernel_time(launches, total_ms, bytes_per_launch);
+    return SP_OK;
+  });
+}
+
+void sp_state_destroy(sp_state* st) { delete st; }
+
+int sp_server_create(int64_t hbm_budget_bytes, int32_t max_batch_columns, sp_server** out) {
+  return guard([&] {
+    SP_REQUIRE(out != nullptr, SP_EINVAL, "NULL out");
+    *out = nullptr;
+    SP_REQUIRE(hbm_budget_bytes > 0, SP_EINVAL, "hbm budget must be > 0");
+    SP_REQUIRE(max_batch_columns >= 0, SP_EINVAL, "max_batch_columns must be >= 0");
+    std::unique_ptr<sp_server> h(new sp_server());
+    h->srv.reset(new sp::Server(hbm_budget_bytes, max_batch_columns ? max_batch_columns : 4096));
+    *out = h.release();
+    return SP_OK;
+  });
+}
+
+int sp_server_submit(sp_server* srv, const sp_mesh* mesh, const sp_params* prm,
+                     int32_t n_restarts, const int32_t* m, const double* eps, const double* u0,
+                     int64_t* ticket) {
+  return guard([&] {
+    SP_REQUIRE(srv && srv->srv && mesh && mesh->m && prm && ticket, SP_EINVAL, "NULL argument");
+    sp::validate_params(*prm);
+    SP_REQUIRE(prm->n_steps > 0, SP_EINVAL, "server requests need n_steps > 0");
+    sp::BatchSpec spec = make_spec(n_restarts, m, eps);
+    *ticket = srv->srv->submit(mesh->m.get(), *prm, spec, u0);
+    return SP_OK;
+  });
+}
+
+int sp_server_poll(sp_server* srv, int64_t ticket, int32_t* done) {
+  return guard([&] {
+    SP_REQUIRE(srv && srv->srv && done, SP_EINVAL, "NULL argument");
+    *done = srv->srv->poll(ticket) ? 1 : 0;
+    return SP_OK;
+  });
+}
+
+int sp_server_wait(sp_server* srv, int64_t ticket, double timeout_s) {
+  return guard([&] {
+    SP_REQUIRE(srv && srv->srv, SP_EINVAL, "NULL server");
+    return srv->srv->wait(ticket, timeout_s) ? SP_OK : SP_EAGAIN;
+  });
+}
+
+int sp_server_fetch(sp_server* srv, int64_t ticket, double* u_out, int32_t* labels,
+                    double* lambda, double* s_eps, double* energy, double* latency_s) {
+  return guard([&] {
+    SP_REQUIRE(srv && srv->srv, SP_EINVAL, "NULL server");
+    return srv->srv->fetch(ticket, u_out, labels, lambda, s_eps, energy, latency_s);
+  });
+}
+
+int sp_server_stats(sp_server* srv, double* p50_s, double* p99_s, double* cdof_per_s,
+                    int64_t* completed) {
+  return guard([&] {
+    SP_REQUIRE(srv && srv->srv, SP_EINVAL, "NULL server");
+    srv->srv->stats(p50_s, p99_s, cdof_per_s, completed);
+    return SP_OK;
+  });
+}
+
+void sp_server_destroy(sp_server* srv) { delete srv; }
+
+}  // extern "C"

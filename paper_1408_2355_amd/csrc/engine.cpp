@@ -1,0 +1,589 @@
+// Orchestration of the time step of Algorithm 2.2 for a batch of restarts.
+//
+// Step 1 (heat): per column, Jacobi-preconditioned CG on (M + tau A) x = M u
+// started from x0 = u (so r0 = -tau A u).  SP_FP64 runs the CG in float64;
+// SP_MIXED runs float32 CG inner solves inside float64 iterative refinement.
+// Each column keeps its own CG scalars and stops on its own test
+// ||r||_2 <= cg_rtol ||M u||_2, so a column's arithmetic does not depend on
+// which other columns share the launch.  The host launches iterations in
+// chunks of check_every and polls one device counter between chunks; the
+// kernels of an iteration after global convergence exit at once.
+// Step 2 (node step) and step 3 (L2 normalisation) follow; energies at the
+// cadence energy_every (Section 2.2 checks the energy every M_tau steps).
+#include "engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace sp {
+
+namespace {
+constexpr int kTargetBlocks = 2048;
+enum { CF_BB, CF_RZ, CF_TOL2, CF_ALPHA, CF_BETA, CF_RRO, CF_NRM, CF_COEF, CF_N };
+enum { CI_ACT, CI_ACTO, CI_ITERS, CI_SWEEPS, CI_SEGLO, CI_SEGLEN, CI_LIVE, CI_N };
+}  // namespace
+
+void validate_params(const sp_params& p) {
+  SP_REQUIRE(std::isfinite(p.tau) && p.tau > 0, SP_EINVAL, "params: tau must be > 0");
+  SP_REQUIRE(p.precision == SP_FP64 || p.precision == SP_MIXED, SP_EINVAL,
+             "params: precision must be SP_FP64 or SP_MIXED");
+  SP_REQUIRE(p.n_steps >= 0, SP_EINVAL, "params: n_steps must be >= 0");
+  SP_REQUIRE(p.energy_every >= 0, SP_EINVAL, "params: energy_every must be >= 0");
+  SP_REQUIRE(p.n_steps > 0 || p.energy_every > 0, SP_EINVAL,
+             "params: stop mode (n_steps == 0) needs energy_every > 0");
+  SP_REQUIRE(p.n_steps > 0 || (std::isfinite(p.stop_tol) && p.stop_tol > 0), SP_EINVAL,
+             "params: stop_tol must be > 0");
+  SP_REQUIRE(p.n_steps > 0 || p.max_steps > 0, SP_EINVAL, "params: max_steps must be > 0");
+  SP_REQUIRE(std::isfinite(p.cg_rtol) && p.cg_rtol > 0 && p.cg_rtol < 1, SP_EINVAL,
+             "params: cg_rtol must be in (0, 1)");
+  SP_REQUIRE(p.cg_max_iter >= 1, SP_EINVAL, "params: cg_max_iter must be >= 1");
+  SP_REQUIRE(p.check_every >= 0, SP_EINVAL, "params: check_every must be >= 0");
+  if (p.precision == SP_MIXED) {
+    SP_REQUIRE(std::isfinite(p.inner_rtol) && p.inner_rtol > 0 && p.inner_rtol < 1, SP_EINVAL,
+               "params: inner_rtol must be in (0, 1)");
+    SP_REQUIRE(p.max_outer >= 1, SP_EINVAL, "params: max_outer must be >= 1");
+  }
+}
+
+void validate_batch(int32_t nres, const int32_t* m, const double* eps) {
+  SP_REQUIRE(nres >= 1, SP_EINVAL, "batch: n_restarts must be >= 1");
+  SP_REQUIRE(m && eps, SP_EINVAL, "batch: NULL m or eps");
+  int64_t R = 0;
+  for (int32_t r = 0; r < nres; ++r) {
+    SP_REQUIRE(m[r] >= 1, SP_EINVAL, "batch: m must be >= 1 (restart " + std::to_string(r) + ")");
+    SP_REQUIRE(std::isfinite(eps[r]) && eps[r] > 0, SP_EINVAL,
+               "batch: eps must be > 0 (restart " + std::to_string(r) + ")");
+    R += m[r];
+  }
+  SP_REQUIRE(R <= (1 << 24), SP_EINVAL, "batch: too many components");
+}
+
+Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hipStream_t* stream,
+               int min_columns, int min_restarts)
+    : mesh_(mesh), prm_(prm), spec_(spec) {
+  validate_params(prm_);
+  SP_REQUIRE(mesh_ != nullptr, SP_EINVAL, "NULL mesh");
+  const int nres = int(spec_.m.size());
+  SP_REQUIRE(nres >= 1 || min_columns > 0, SP_EINVAL, "batch: no restarts");
+  for (int x : spec_.m) R_ += x;
+  rp_ = ((std::max(std::max(R_, min_columns), 1) + 3) / 4) * 4;
+  nres_p_ = std::max(std::max(nres, min_restarts), 1);
+  if (stream) {
+    s_ = *stream;
+  } else {
+    SP_HIP(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
+    own_stream_ = true;
+  }
+  try {
+    km_ = mesh_->tau_mats(prm_.tau);
+    const int n = int(mesh_->n);
+    const size_t nv = size_t(n) * rp_;
+    Tile t = make_tile(n, rp_, 64, kTargetBlocks);
+    tt_ = make_tile(int(mesh_->nt), nres_p_, 256, kTargetBlocks);
+    u_.alloc(nv);
+    r64_.alloc(nv);
+    if (prm_.precision == SP_FP64) {
+      p64_.alloc(nv);
+      q64_.alloc(nv);
+    } else {
+      d32_.alloc(nv);
+      r32_.alloc(nv);
+      p32_.alloc(nv);
+      q32_.alloc(nv);
+    }
+    part_.alloc(3 * size_t(t.nchunk) * rp_);
+    part_s_.alloc(size_t(tt_.nchunk) * nres_p_);
+    colf_.alloc(size_t(CF_N) * rp_ + nres_p_);
+    coli_.alloc(size_t(CI_N) * rp_ + 3 * size_t(nres_p_));
+    ring_.alloc(2 * kRing);
+    stat_.alloc(4);
+    lam_.alloc(rp_);
+    seps_.alloc(nres_p_);
+    energy_.alloc(nres_p_);
+    SP_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_poll_), 64, hipHostMallocDefault));
+
+    k::fill_f64(u_.p, 0.0, nv, s_);
+    k::fill_f64(r64_.p, 0.0, nv, s_);
+    k::fill_f64(colf_.p, 0.0, colf_.n, s_);
+    k::fill_i32(coli_.p, 0, coli_.n, s_);
+    k::fill_i32(ring_.p, 0, ring_.n, s_);
+    k::fill_f64(reinterpret_cast<double*>(stat_.p), 0.0, stat_.n, s_);
+    k::fill_f64(lam_.p, 0.0, lam_.n, s_);
+    k::fill_f64(seps_.p, 0.0, seps_.n, s_);
+    k::fill_f64(energy_.p, 0.0, energy_.n, s_);
+
+    StepArgs& a = args_;
+    a.t = t;
+    a.W = mesh_->W;
+    a.cols = mesh_->cols.p;
+    a.M64 = mesh_->M64.p;
+    a.A64 = mesh_->A64.p;
+    a.K64 = km_->K64.p;
+    a.dinv64 = km_->dinv64.p;
+    a.K32 = km_->K32.p;
+    a.dinv32 = km_->dinv32.p;
+    a.tau = prm_.tau;
+    a.rtol2 = prm_.cg_rtol * prm_.cg_rtol;
+    a.inner_rtol2 = prm_.inner_rtol * prm_.inner_rtol;
+    double* cf = colf_.p;
+    int* ci = coli_.p;
+    a.cg.bb = cf + CF_BB * rp_;
+    a.cg.rz = cf + CF_RZ * rp_;
+    a.cg.tol2 = cf + CF_TOL2 * rp_;
+    a.cg.alpha = cf + CF_ALPHA * rp_;
+    a.cg.beta = cf + CF_BETA * rp_;
+    a.cg.rr_o = cf + CF_RRO * rp_;
+    a.cg.nrm = cf + CF_NRM * rp_;
+    a.ct.coef = cf + CF_COEF * rp_;
+    a.ct.res_ieps2 = cf + CF_N * rp_;
+    a.cg.act = ci + CI_ACT * rp_;
+    a.cg.act_o = ci + CI_ACTO * rp_;
+    a.cg.iters = ci + CI_ITERS * rp_;
+    a.cg.sweeps = ci + CI_SWEEPS * rp_;
+    a.ct.seg_lo = ci + CI_SEGLO * rp_;
+    a.ct.seg_len = ci + CI_SEGLEN * rp_;
+    a.ct.live = ci + CI_LIVE * rp_;
+    a.ct.res_lo = ci + CI_N * rp_;
+    a.ct.res_len = ci + CI_N * rp_ + nres_p_;
+    a.ct.res_live = ci + CI_N * rp_ + 2 * nres_p_;
+    a.ct.nres = nres;  // 0 for an empty server batch
+    a.ct.nres_p = nres_p_;
+    a.part = part_.p;
+    a.ring = ring_.p;
+    a.oring = ring_.p + kRing;
+    a.stat = stat_.p;
+
+    // column tables: restart r owns columns [lo_r, lo_r + m_r)
+    h_seg_lo_.assign(rp_, 0);
+    h_seg_len_.assign(rp_, 0);
+    h_live_.assign(rp_, 0);
+    h_coef_.assign(rp_, 0.0);
+    h_res_lo_.assign(nres_p_, 0);
+    h_res_len_.assign(nres_p_, 0);
+    h_res_live_.assign(nres_p_, 0);
+    h_res_ieps2_.assign(nres_p_, 0.0);
+    int lo = 0;
+    for (int r = 0; r < nres; ++r) {
+      const int m = spec_.m[r];
+      const double e = spec_.eps[r];
+      for (int j = 0; j < m; ++j) {
+        h_seg_lo_[lo + j] = lo;
+        h_seg_len_[lo + j] = m;
+        h_live_[lo + j] = 1;
+        h_coef_[lo + j] = 2.0 * prm_.tau / (e * e);
+      }
+      h_res_lo_[r] = lo;
+      h_res_len_[r] = m;
+      h_res_live_[r] = 1;
+      h_res_ieps2_[r] = 1.0 / (e * e);
+      lo += m;
+    }
+    push_tables();
+    hist_.assign(nres, {});
+  } catch (...) {
+    if (h_poll_) (void)hipHostFree(h_poll_);
+    h_poll_ = nullptr;
+    if (own_stream_) {
+      (void)hipStreamSynchronize(s_);
+      (void)hipStreamDestroy(s_);
+    }
+    throw;
+  }
+}
+
+Solver::~Solver() {
+  if (!detached_ || own_stream_) (void)hipStreamSynchronize(s_);
+  for (auto& e : ev_) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  if (h_poll_) (void)hipHostFree(h_poll_);
+  if (own_stream_) (void)hipStreamDestroy(s_);
+}
+
+void Solver::push_tables() {
+  const int nres = args_.ct.nres;
+  args_.ct.nres = nres;
+  SP_HIP(hipMemcpyAsync(const_cast<int*>(args_.ct.seg_lo), h_seg_lo_.data(), rp_ * sizeof(int),
+                        hipMemcpyHostToDevice, s_));
+  SP_HIP(hipMemcpyAsync(const_cast<int*>(args_.ct.seg_len), h_seg_len_.data(), rp_ * sizeof(int),
+                        hipMemcpyHostToDevice, s_));
+  SP_HIP(hipMemcpyAsync(const_cast<int*>(args_.ct.live), h_live_.data(), rp_ * sizeof(int),
+                        hipMemcpyHostToDevice, s_));
+  SP_HIP(hipMemcpyAsync(const_cast<double*>(args_.ct.coef), h_coef_.data(), rp_ * sizeof(double),
+                        hipMemcpyHostToDevice, s_));
+  SP_HIP(hipMemcpyAsync(const_cast<int*>(args_.ct.res_lo), h_res_lo_.data(), nres_p_ * sizeof(int),
+                        hipMemcpyHostToDevice, s_));
+  SP_HIP(hipMemcpyAsync(const_cast<int*>(args_.ct.res_len), h_res_len_.data(), nres_p_ * sizeof(int),
+                        hipMemcpyHostToDevice, s_));
+  SP_HIP(hipMemcpyAsync(const_cast<int*>(args_.ct.res_live), h_res_live_.data(),
+                        nres_p_ * sizeof(int), hipMemcpyHostToDevice, s_));
+  SP_HIP(hipMemcpyAsync(const_cast<double*>(args_.ct.res_ieps2), h_res_ieps2_.data(),
+                        nres_p_ * sizeof(double), hipMemcpyHostToDevice, s_));
+  // the host vectors may change right after: wait for the copies
+  SP_HIP(hipStreamSynchronize(s_));
+}
+
+void Solver::set_columns(const std::vector<int>& seg_lo, const std::vector<int>& seg_len,
+                         const std::vector<double>& coef, const std::vector<int>& live,
+                         const std::vector<int>& res_lo, const std::vector<int>& res_len,
+                         const std::vector<double>& res_ieps2) {
+  SP_REQUIRE(int(seg_lo.size()) == rp_ && int(res_lo.size()) <= nres_p_, SP_EINVAL,
+             "set_columns: table sizes");
+  h_seg_lo_ = seg_lo;
+  h_seg_len_ = seg_len;
+  h_coef_ = coef;
+  h_live_ = live;
+  std::fill(h_res_lo_.begin(), h_res_lo_.end(), 0);
+  std::fill(h_res_len_.begin(), h_res_len_.end(), 0);
+  std::fill(h_res_ieps2_.begin(), h_res_ieps2_.end(), 0.0);
+  std::fill(h_res_live_.begin(), h_res_live_.end(), 0);
+  for (size_t r = 0; r < res_lo.size(); ++r) {
+    h_res_lo_[r] = res_lo[r];
+    h_res_len_[r] = res_len[r];
+    h_res_ieps2_[r] = res_ieps2[r];
+    h_res_live_[r] = res_len[r] > 0;
+  }
+  args_.ct.nres = int(res_lo.size());
+  push_tables();
+}
+
+void Solver::set_restart_live(int r, bool live) {
+  SP_REQUIRE(r >= 0 && r < args_.ct.nres, SP_EINVAL, "restart index");
+  const int lo = h_res_lo_[r], m = h_res_len_[r];
+  for (int j = 0; j < m; ++j) h_live_[lo + j] = live ? 1 : 0;
+  h_res_live_[r] = live ? 1 : 0;
+  push_tables();
+}
+
+int Solver::poll(const int* dev_counter) {
+  SP_HIP(hipMemcpyAsync(h_poll_, dev_counter, sizeof(int), hipMemcpyDeviceToHost, s_));
+  SP_HIP(hipStreamSynchronize(s_));
+  return h_poll_[0];
+}
+
+void Solver::sync() { SP_HIP(hipStreamSynchronize(s_)); }
+
+void Solver::upload_host(const double* u0, bool normalise) {
+  SP_REQUIRE(u0 != nullptr, SP_EINVAL, "NULL u0");
+  const size_t cnt = size_t(R_) * mesh_->n;
+  for (size_t i = 0; i < cnt; ++i)
+    SP_REQUIRE(std::isfinite(u0[i]), SP_EINVAL, "u0 holds a non-finite value");
+  DevBuf<double> tmp(cnt);
+  SP_HIP(hipMemcpyAsync(tmp.p, u0, cnt * sizeof(double), hipMemcpyHostToDevice, s_));
+  k::pack(args_.t, 0, R_, tmp.p, mesh_->perm_d.p, u_.p, s_);
+  if (normalise) {
+    normalise_columns();
+  }
+  SP_HIP(hipStreamSynchronize(s_));
+}
+
+void Solver::upload_device(const double* d_u0, bool normalise, bool check_norms) {
+  SP_REQUIRE(d_u0 != nullptr, SP_EINVAL, "NULL u0");
+  k::pack(args_.t, 0, R_, d_u0, mesh_->perm_d.p, u_.p, s_);
+  if (normalise) {
+    if (check_norms) {
+      normalise_columns();
+    } else {
+      k::norm_dot(args_, u_.p, s_);
+      k::red_norm(args_, s_);
+      k::scale(args_, u_.p, u_.p, s_);
+    }
+  }
+}
+
+void Solver::normalise_columns() {
+  k::norm_dot(args_, u_.p, s_);
+  k::red_norm(args_, s_);
+  std::vector<double> nrm(rp_);
+  SP_HIP(hipMemcpyAsync(nrm.data(), args_.cg.nrm, rp_ * sizeof(double), hipMemcpyDeviceToHost, s_));
+  SP_HIP(hipStreamSynchronize(s_));
+  for (int c = 0; c < rp_; ++c)
+    if (h_live_[c])
+      SP_REQUIRE(std::isfinite(nrm[c]) && nrm[c] > 0, SP_EINVAL,
+                 "a component of u0 has zero (or non-finite) L2 norm (column " +
+                     std::to_string(c) + ")");
+  k::scale(args_, u_.p, u_.p, s_);
+}
+
+void Solver::pack_range(int c_lo, int Rq, const double* d_src) {
+  SP_REQUIRE(c_lo >= 0 && Rq >= 0 && c_lo + Rq <= rp_, SP_EINVAL, "column range");
+  k::pack(args_.t, c_lo, Rq, d_src, mesh_->perm_d.p, u_.p, s_);
+}
+
+void Solver::unpack_range(int c_lo, int Rq, double* d_dst) {
+  SP_REQUIRE(c_lo >= 0 && Rq >= 0 && c_lo + Rq <= rp_, SP_EINVAL, "column range");
+  k::unpack(args_.t, c_lo, Rq, u_.p, mesh_->perm_d.p, d_dst, s_);
+}
+
+void Solver::normalise_range(int c_lo, int Rq) {
+  std::vector<int> saved = h_live_;
+  for (int c = 0; c < rp_; ++c) h_live_[c] = (c >= c_lo && c < c_lo + Rq) ? saved[c] : 0;
+  push_tables();
+  try {
+    normalise_columns();
+  } catch (...) {
+    h_live_ = saved;
+    push_tables();
+    throw;
+  }
+  h_live_ = saved;
+  push_tables();
+}
+
+void Solver::download_host(double* u) {
+  const size_t cnt = size_t(R_) * mesh_->n;
+  DevBuf<double> tmp(cnt);
+  k::unpack(args_.t, 0, R_, u_.p, mesh_->perm_d.p, tmp.p, s_);
+  SP_HIP(hipMemcpyAsync(u, tmp.p, cnt * sizeof(double), hipMemcpyDeviceToHost, s_));
+  SP_HIP(hipStreamSynchronize(s_));
+}
+
+void Solver::download_device(double* d_u) {
+  k::unpack(args_.t, 0, R_, u_.p, mesh_->perm_d.p, d_u, s_);
+}
+
+void Solver::heat_fp64() {
+  k::fill_i32(ring_.p, 0, ring_.n, s_);
+  k::init_fp64(args_, u_.p, r64_.p, p64_.p, s_);
+  k::red_init_fp64(args_, s_);
+  int last = 0;
+  for (int it = 0; it < prm_.cg_max_iter; ++it) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (prof_) {
+      if (ev_used_ == ev_.size()) {
+        if (ev_.size() >= 8192) prof_flush();
+        if (ev_used_ == ev_.size()) {
+          hipEvent_t a, b;
+          SP_HIP(hipEventCreate(&a));
+          SP_HIP(hipEventCreate(&b));
+          ev_.push_back({a, b});
+        }
+      }
+      e0 = ev_[ev_used_].first;
+      e1 = ev_[ev_used_].second;
+      ++ev_used_;
+    }
+    k::cg_iter<double>(args_, it, u_.p, r64_.p, p64_.p, q64_.p, km_->K64.p, km_->dinv64.p, s_, e0, e1);
+    last = it + 1;
+    if (prm_.check_every > 0 && last % prm_.check_every == 0 && last < prm_.cg_max_iter)
+      if (poll(ring_.p + last % kRing) == 0) break;
+  }
+  k::flag_nonconv(args_, ring_.p + last % kRing, s_);
+}
+
+void Solver::heat_mixed() {
+  k::fill_i32(ring_.p, 0, ring_.n, s_);
+  k::init_outer(args_, u_.p, r64_.p, s_);
+  k::red_outer_init(args_, s_);
+  int olast = 0;
+  for (int o = 0; o < prm_.max_outer; ++o) {
+    k::inner_init(args_, o, r64_.p, d32_.p, r32_.p, p32_.p, s_);
+    k::red_inner_init(args_, o, s_);
+    for (int it = 0; it < prm_.cg_max_iter; ++it) {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (prof_) {
+        if (ev_used_ == ev_.size()) {
+          if (ev_.size() >= 8192) prof_flush();
+          if (ev_used_ == ev_.size()) {
+            hipEvent_t a, b;
+            SP_HIP(hipEventCreate(&a));
+            SP_HIP(hipEventCreate(&b));
+            ev_.push_back({a, b});
+          }
+        }
+        e0 = ev_[ev_used_].first;
+        e1 = ev_[ev_used_].second;
+        ++ev_used_;
+      }
+      k::cg_iter<float>(args_, it, d32_.p, r32_.p, p32_.p, q32_.p, km_->K32.p, km_->dinv32.p, s_,
+                        e0, e1);
+      const int last = it + 1;
+      if (prm_.check_every > 0 && last % prm_.check_every == 0 && last < prm_.cg_max_iter)
+        if (poll(ring_.p + last % kRing) == 0) break;
+    }
+    k::outer_update(args_, o, u_.p, r64_.p, d32_.p, s_);
+    k::red_outer(args_, o, s_);
+    olast = o + 1;
+    if (prm_.check_every > 0 && olast < prm_.max_outer)
+      if (poll(args_.oring + olast % kRing) == 0) break;
+  }
+  k::flag_nonconv(args_, args_.oring + olast % kRing, s_);
+}
+
+void Solver::stage_heat() {
+  if (prm_.precision == SP_FP64)
+    heat_fp64();
+  else
+    heat_mixed();
+}
+
+void Solver::node_to_r() { k::nodal(args_, u_.p, r64_.p, s_); }
+
+void Solver::norm_dot_scale(const double* v) {
+  k::norm_dot(args_, v, s_);
+  k::red_norm(args_, s_);
+  k::scale(args_, v, u_.p, s_);
+}
+
+void Solver::stage_node() {
+  node_to_r();
+  k::fill_f64(args_.cg.nrm, 1.0, rp_, s_);
+  k::scale(args_, r64_.p, u_.p, s_);
+}
+
+void Solver::stage_norm() { norm_dot_scale(u_.p); }
+
+void Solver::energy() {
+  if (args_.ct.nres == 0) return;
+  k::energy_rq(args_, u_.p, s_);
+  k::energy_seps(args_, tt_, mesh_->tri.p, mesh_->tarea.p, u_.p, part_s_.p, s_);
+  k::red_energy(args_, tt_, part_s_.p, lam_.p, seps_.p, energy_.p, s_);
+}
+
+void Solver::energy_to_host(double* lam, double* seps, double* E) {
+  energy();
+  if (lam) SP_HIP(hipMemcpyAsync(lam, lam_.p, R_ * sizeof(double), hipMemcpyDeviceToHost, s_));
+  const int nres = int(spec_.m.size());
+  if (seps) SP_HIP(hipMemcpyAsync(seps, seps_.p, nres * sizeof(double), hipMemcpyDeviceToHost, s_));
+  if (E) SP_HIP(hipMemcpyAsync(E, energy_.p, nres * sizeof(double), hipMemcpyDeviceToHost, s_));
+  SP_HIP(hipStreamSynchronize(s_));
+}
+
+void Solver::step(int64_t k) {
+  SP_REQUIRE(k >= 0, SP_EINVAL, "step count must be >= 0");
+  const int nres = int(spec_.m.size());
+  std::vector<double> E(nres);
+  for (int64_t i = 0; i < k; ++i) {
+    stage_heat();
+    node_to_r();
+    norm_dot_scale(r64_.p);
+    ++steps_done_;
+    if (prm_.energy_every > 0 && steps_done_ % prm_.energy_every == 0) {
+      if (record_history) {
+        energy_to_host(nullptr, nullptr, E.data());
+        for (int r = 0; r < nres; ++r)
+          if (h_res_live_[r]) hist_[r].push_back({steps_done_, E[r]});
+      } else {
+        energy();
+      }
+    }
+  }
+}
+
+void Solver::run_to_stop() {
+  const int nres = int(spec_.m.size());
+  std::vector<double> E(nres), Eprev(nres);
+  energy_to_host(nullptr, nullptr, Eprev.data());
+  for (int r = 0; r < nres; ++r) hist_[r].push_back({steps_done_, Eprev[r]});
+  restart_steps.assign(nres, 0);
+  int running = nres;
+  const int64_t every = prm_.energy_every;
+  while (running > 0 && steps_done_ < prm_.max_steps) {
+    const int64_t k = std::min<int64_t>(every - steps_done_ % every, prm_.max_steps - steps_done_);
+    step(k);
+    if (steps_done_ % every != 0) break;  // hit max_steps between checks
+    for (int r = 0; r < nres; ++r) {
+      if (!h_res_live_[r]) continue;
+      E[r] = hist_[r].back().second;
+      restart_steps[r] = steps_done_;
+      if (std::fabs(E[r] - Eprev[r]) < prm_.stop_tol) {
+        set_restart_live(r, false);
+        --running;
+      }
+      Eprev[r] = E[r];
+    }
+  }
+  for (int r = 0; r < nres; ++r)
+    if (h_res_live_[r]) restart_steps[r] = steps_done_;
+  // make every restart visible again for the final energies and labels
+  for (int r = 0; r < nres; ++r) h_res_live_[r] = 1;
+  for (int c = 0; c < R_; ++c) h_live_[c] = 1;
+  push_tables();
+}
+
+void Solver::labels_device(int32_t* d_lab, int32_t* d_lab_am) {
+  if (args_.ct.nres == 0) return;
+  k::labels(args_, u_.p, mesh_->perm_d.p, d_lab, d_lab_am, s_);
+}
+
+void Solver::labels_host(int32_t* lab, int32_t* lab_am) {
+  const size_t cnt = size_t(spec_.m.size()) * mesh_->n;
+  DevBuf<int32_t> a(lab ? cnt : 0), b(lab_am ? cnt : 0);
+  k::labels(args_, u_.p, mesh_->perm_d.p, a.p, b.p, s_);
+  if (lab) SP_HIP(hipMemcpyAsync(lab, a.p, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, s_));
+  if (lab_am) SP_HIP(hipMemcpyAsync(lab_am, b.p, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, s_));
+  SP_HIP(hipStreamSynchronize(s_));
+}
+
+sp_stats Solver::stats() {
+  long long st[4] = {0, 0, 0, 0};
+  std::vector<int> it(rp_);
+  SP_HIP(hipMemcpyAsync(st, stat_.p, sizeof(st), hipMemcpyDeviceToHost, s_));
+  SP_HIP(hipMemcpyAsync(it.data(), args_.cg.iters, rp_ * sizeof(int), hipMemcpyDeviceToHost, s_));
+  SP_HIP(hipStreamSynchronize(s_));
+  sp_stats out{};
+  out.steps_done = steps_done_;
+  out.cg_iters = st[0];
+  out.outer_sweeps = st[1];
+  out.col_iters_max = it.empty() ? 0 : *std::max_element(it.begin(), it.end());
+  out.converged = st[2] == 0;
+  return out;
+}
+
+bool Solver::converged() { return stats().converged != 0; }
+
+void Solver::prof_flush() {
+  if (ev_used_ == 0) return;
+  SP_HIP(hipStreamSynchronize(s_));
+  for (size_t i = 0; i < ev_used_; ++i) {
+    float ms = 0.f;
+    SP_HIP(hipEventElapsedTime(&ms, ev_[i].first, ev_[i].second));
+    prof_ms_ += ms;
+    ++prof_launches_;
+  }
+  ev_used_ = 0;
+}
+
+void Solver::profile(bool on) {
+  prof_flush();
+  prof_ = on;
+  prof_launches_ = 0;
+  prof_ms_ = 0.0;
+}
+
+void Solver::kernel_time(int64_t* launches, double* ms, double* bytes_per_launch) {
+  prof_flush();
+  if (launches) *launches = prof_launches_;
+  if (ms) *ms = prof_ms_;
+  if (bytes_per_launch) {
+    // minimum traffic of one q = K p launch over all live columns: read p and
+    // write q once per element, plus the matrix (column indices and values)
+    int live = 0;
+    for (int c = 0; c < rp_; ++c) live += h_live_[c];
+    const double s = prm_.precision == SP_FP64 ? 8.0 : 4.0;
+    *bytes_per_launch = double(mesh_->n) * (double(live) * 2.0 * s + double(mesh_->W) * (4.0 + s));
+  }
+}
+
+namespace {
+std::mutex g_dead_mu;
+std::vector<Solver*> g_dead;
+}  // namespace
+
+void defer_delete(Solver* s) {
+  std::lock_guard<std::mutex> g(g_dead_mu);
+  g_dead.push_back(s);
+}
+
+void reap_deferred() {
+  std::vector<Solver*> v;
+  {
+    std::lock_guard<std::mutex> g(g_dead_mu);
+    v.swap(g_dead);
+  }
+  for (Solver* s : v) delete s;
+}
+
+}  // namespace sp

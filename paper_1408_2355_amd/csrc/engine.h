@@ -1,0 +1,149 @@
+// Batch solver: device state of a batch of restarts and the orchestration of
+// one time step of Algorithm 2.2 (heat solve, node step, normalisation),
+// energies and labels.
+#pragma once
+
+#include <utility>
+#include <vector>
+
+#include "kernels.h"
+
+namespace sp {
+
+struct BatchSpec {
+  std::vector<int> m;       // components per restart
+  std::vector<double> eps;  // eps per restart
+};
+
+void validate_params(const sp_params& p);
+void validate_batch(int32_t nres, const int32_t* m, const double* eps);
+
+class Solver {
+ public:
+  // stream == nullptr: the solver creates and owns a stream; otherwise it
+  // uses *stream (which may be the legacy default stream 0).  min_columns /
+  // min_restarts reserve extra column and restart slots (server batches
+  // start with an empty spec and fill slots later).
+  Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hipStream_t* stream,
+         int min_columns = 0, int min_restarts = 0);
+  ~Solver();
+  Solver(const Solver&) = delete;
+  Solver& operator=(const Solver&) = delete;
+
+  // Initial state [R][n] (caller numbering) from host or device memory;
+  // normalise = scale every live component to unit L2 norm.
+  void upload_host(const double* u0, bool normalise);
+  void upload_device(const double* d_u0, bool normalise, bool check_norms);
+  void download_host(double* u);      // [R][n] host
+  void download_device(double* d_u);  // [R][n] device
+
+  // Algorithm 2.2: k full steps (energies at the prm.energy_every cadence,
+  // recorded in the history).
+  void step(int64_t k);
+  // Run until every restart met the stop rule (n_steps == 0) or max_steps.
+  void run_to_stop();
+  void stage_heat();
+  void stage_node();
+  void stage_norm();
+  // Energies of the current state into device arrays (lam [rp], seps/E [nres]).
+  void energy();
+  void energy_to_host(double* lam, double* seps, double* E);
+  void labels_device(int32_t* d_lab, int32_t* d_lab_am);
+  void labels_host(int32_t* lab, int32_t* lab_am);
+
+  // column/restart activity (continuous batching, stop rule)
+  void set_restart_live(int r, bool live);
+  void sync();
+  hipStream_t stream() const { return s_; }
+
+  int R() const { return R_; }
+  int rp() const { return rp_; }
+  int nres() const { return int(spec_.m.size()); }
+  int64_t n() const { return mesh_->n; }
+  int64_t steps_done() const { return steps_done_; }
+  void set_steps_done(int64_t k) { steps_done_ = k; }
+  const std::vector<std::vector<std::pair<int64_t, double>>>& history() const { return hist_; }
+  sp_stats stats();
+  bool converged();
+
+  // event timing of the CG matrix-product kernel
+  void profile(bool on);
+  void kernel_time(int64_t* launches, double* ms, double* bytes_per_launch);
+
+  const double* d_lam() const { return lam_.p; }
+  const double* d_seps() const { return seps_.p; }
+  const double* d_energy() const { return energy_.p; }
+  double* d_u() { return u_.p; }
+  const Tile& tile() const { return args_.t; }
+  const sp_params& params() const { return prm_; }
+  Mesh* mesh() const { return mesh_; }
+
+  // Re-seat a restart's columns (server slots): new m/eps tables must keep
+  // the column layout; used by the server which owns one solver per batch.
+  void set_columns(const std::vector<int>& seg_lo, const std::vector<int>& seg_len,
+                   const std::vector<double>& coef, const std::vector<int>& live,
+                   const std::vector<int>& res_lo, const std::vector<int>& res_len,
+                   const std::vector<double>& res_ieps2);
+  void normalise_columns();  // normalise live columns of the current state in place
+
+  // Column range [c_lo, c_lo + Rq) of the state from/to caller layout [Rq][n]
+  // on the device (server slots).
+  void pack_range(int c_lo, int Rq, const double* d_src);
+  void unpack_range(int c_lo, int Rq, double* d_dst);
+  // Normalise only columns [c_lo, c_lo + Rq); throws SP_EINVAL on a zero norm.
+  void normalise_range(int c_lo, int Rq);
+  // Skip the stream synchronisation in the destructor (work already done).
+  void detach() { detached_ = true; }
+
+  bool record_history = true;          // copy energies to the host at the cadence
+  std::vector<int64_t> restart_steps;  // per restart: steps taken (stop mode)
+
+ private:
+  void heat_fp64();
+  void heat_mixed();
+  void node_to_r();
+  void norm_dot_scale(const double* v);
+  int poll(const int* dev_counter);
+  void push_tables();
+
+  Mesh* mesh_;
+  TauMats* km_;
+  sp_params prm_;
+  BatchSpec spec_;
+  int R_ = 0, rp_ = 0, nres_p_ = 0;
+  hipStream_t s_ = nullptr;
+  bool own_stream_ = false;
+  bool detached_ = false;
+
+  DevBuf<double> u_, r64_, p64_, q64_;
+  DevBuf<float> d32_, r32_, p32_, q32_;
+  DevBuf<double> part_, part_s_;
+  DevBuf<double> colf_;  // 8 x rp column doubles + nres_p restart doubles
+  DevBuf<int> coli_;     // 7 x rp column ints + 3 x nres_p restart ints
+  DevBuf<int> ring_;     // 2 x kRing
+  DevBuf<long long> stat_;
+  DevBuf<double> lam_, seps_, energy_;
+  int* h_poll_ = nullptr;
+
+  std::vector<int> h_seg_lo_, h_seg_len_, h_live_, h_res_lo_, h_res_len_, h_res_live_;
+  std::vector<double> h_coef_, h_res_ieps2_;
+
+  StepArgs args_{};
+  Tile tt_{};
+  int64_t steps_done_ = 0;
+  std::vector<std::vector<std::pair<int64_t, double>>> hist_;
+
+  bool prof_ = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_;
+  size_t ev_used_ = 0;
+  int64_t prof_launches_ = 0;
+  double prof_ms_ = 0.0;
+  void prof_flush();
+};
+
+// Solvers whose work was enqueued asynchronously are freed later, from an
+// ordinary API call (never from inside a stream callback).
+void defer_delete(Solver* s);
+void reap_deferred();
+
+}  // namespace sp

@@ -1,0 +1,123 @@
+// Internal types of libsegpart (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "segpart.h"
+
+namespace sp {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define SP_HIP(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      throw ::sp::Error(SP_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define SP_REQUIRE(cond, code, msg) \
+  do {                              \
+    if (!(cond)) throw ::sp::Error((code), (msg)); \
+  } while (0)
+
+// Owning device allocation.
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t count) { alloc(count); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t count) {
+    release();
+    if (count == 0) return;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      throw Error(SP_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    n = count;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  size_t bytes() const { return n * sizeof(T); }
+};
+
+// Row x column tiling of an [n][rp] column-interleaved array for the
+// row-parallel kernels.  A thread owns 4 consecutive columns of one row; a
+// 256-thread workgroup covers tr rows x tg column groups per pass and walks a
+// chunk of ch rows; per-column partial sums are written per chunk.
+struct Tile {
+  int n = 0;       // rows
+  int rp = 0;      // padded columns (multiple of 4)
+  int G = 0;       // column groups (rp / 4)
+  int tg = 1;      // column groups per tile (power of two, <= 64)
+  int tr = 256;    // rows per pass (256 / tg)
+  int ch = 256;    // rows per chunk (multiple of tr)
+  int nchunk = 1;  // chunks
+  int nct = 1;     // column tiles
+  int nblk = 1;    // workgroups
+};
+Tile make_tile(int n, int rp, int tg_cap, int target_blocks);
+
+// Per-time-step matrices for one tau: K = M + tau A in float64 and float32,
+// and the inverse diagonals used by the Jacobi preconditioner.
+struct TauMats {
+  double tau = 0;
+  DevBuf<double> K64, dinv64;
+  DevBuf<float> K32, dinv32;
+};
+
+struct Mesh {
+  int64_t n = 0, nt = 0, nnz = 0;
+  int W = 0;           // ELL width (max row length); slot 0 holds the diagonal
+  double area = 0;
+  std::vector<int32_t> perm;   // perm[new] = caller index
+  std::vector<int32_t> iperm;  // iperm[caller] = new
+  std::vector<int32_t> h_cols; // [W][n] host copy of the pattern (new numbering)
+  DevBuf<int32_t> cols;        // [W][n]; padding slots repeat the row index, value 0
+  DevBuf<double> M64, A64;     // [W][n]
+  DevBuf<int32_t> tri;         // [nt][3] (new numbering, sorted for locality)
+  DevBuf<double> tarea;        // [nt]
+  DevBuf<int32_t> perm_d, iperm_d;
+  int device = 0;
+  std::mutex mu;
+  std::vector<std::unique_ptr<TauMats>> kcache;
+  TauMats* tau_mats(double tau);
+};
+
+Mesh* mesh_create(int64_t n, const double* xyz, int64_t nt, const int32_t* tri);
+
+// Kernel launchers (kernels.hip).
+struct ColTables;  // forward
+namespace k {
+void assemble(const Mesh& m, const double* xyz_new, const int32_t* inc_ptr, const int32_t* inc,
+              hipStream_t s);
+void tau_mats(const Mesh& m, TauMats& t, hipStream_t s);
+void fill_i32(int32_t* p, int32_t v, size_t n, hipStream_t s);
+void fill_f64(double* p, double v, size_t n, hipStream_t s);
+}  // namespace k
+
+}  // namespace sp

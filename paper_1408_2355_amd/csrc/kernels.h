@@ -1,0 +1,99 @@
+// Launchers of the time-step kernels (kernels.hip).  All arrays are device
+// pointers.  Vector layout: [n][rp] row-major (the rp values of one vertex
+// are contiguous; column c is one component of one restart).
+#pragma once
+
+#include "internal.h"
+
+namespace sp {
+
+constexpr int kRing = 4;  // slots of the per-iteration active-column counters
+
+// Per-column tables of a batch (device).
+struct ColTab {
+  const int* seg_lo = nullptr;   // first column of the column's restart
+  const int* seg_len = nullptr;  // m of the column's restart
+  const double* coef = nullptr;  // 2 tau / eps^2 of the column's restart
+  const int* live = nullptr;     // 1 = column belongs to a running restart
+  const int* res_lo = nullptr;   // per restart: first column (for the energy)
+  const int* res_len = nullptr;  // per restart: m
+  const double* res_ieps2 = nullptr;  // per restart: 1 / eps^2
+  const int* res_live = nullptr;      // per restart: running
+  int nres = 0;
+  int nres_p = 0;  // padded restart count used by the triangle tiling
+};
+
+// Per-column CG scalars (device).
+struct CgCols {
+  double* bb;     // ||b||^2 = ||M u||^2
+  double* rz;     // r . z
+  double* tol2;   // squared absolute stopping threshold of the current solve
+  double* alpha;
+  double* beta;
+  double* rr_o;   // outer residual norm^2 (mixed)
+  double* nrm;    // M-norms (normalisation)
+  int* act;       // column active in the current (inner) CG
+  int* act_o;     // column active in the outer refinement (mixed)
+  int* iters;     // CG iterations taken (cumulative)
+  int* sweeps;    // outer sweeps taken (cumulative)
+};
+
+struct StepArgs {
+  Tile t;
+  int W;
+  const int* cols;
+  const double* M64;
+  const double* A64;
+  const double* K64;
+  const double* dinv64;
+  const float* K32;
+  const float* dinv32;
+  double tau;
+  double rtol2;        // cg_rtol^2
+  double inner_rtol2;  // inner_rtol^2
+  ColTab ct;
+  CgCols cg;
+  double* part;        // [3][nchunk][rp] partial sums
+  int* ring;           // [kRing] inner active counts
+  int* oring;          // [kRing] outer active counts
+  long long* stat;     // [0] CG iterations with work, [1] outer sweeps, [2] cap hit
+};
+
+namespace k {
+void flag_nonconv(const StepArgs& a, const int* counter, hipStream_t s);
+// float64 CG (plain form): x is the state u itself.
+void init_fp64(const StepArgs& a, const double* u, double* r, double* p, hipStream_t s);
+void red_init_fp64(const StepArgs& a, hipStream_t s);
+// one CG iteration on type T vectors (float64 plain or float32 inner)
+template <typename T>
+void cg_iter(const StepArgs& a, int it, T* x, T* r, T* p, T* q, const T* K, const T* dinv,
+             hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+// mixed precision refinement
+void init_outer(const StepArgs& a, const double* u, double* r64, hipStream_t s);
+void red_outer_init(const StepArgs& a, hipStream_t s);
+void inner_init(const StepArgs& a, int o, const double* r64, float* d, float* r, float* p,
+                hipStream_t s);
+void red_inner_init(const StepArgs& a, int o, hipStream_t s);
+void outer_update(const StepArgs& a, int o, double* u, double* r64, const float* d, hipStream_t s);
+void red_outer(const StepArgs& a, int o, hipStream_t s);
+// node step and normalisation
+void nodal(const StepArgs& a, const double* u, double* out, hipStream_t s);
+void norm_dot(const StepArgs& a, const double* v, hipStream_t s);
+void red_norm(const StepArgs& a, hipStream_t s);
+void scale(const StepArgs& a, const double* v, double* u, hipStream_t s);
+// energies
+void energy_rq(const StepArgs& a, const double* u, hipStream_t s);
+void energy_seps(const StepArgs& a, const Tile& tt, const int32_t* tri, const double* tarea,
+                 const double* u, double* part_s, hipStream_t s);
+void red_energy(const StepArgs& a, const Tile& tt, const double* part_s, double* lam,
+                double* seps, double* energy, hipStream_t s);
+// labels and layout changes
+void labels(const StepArgs& a, const double* u, const int32_t* perm, int32_t* lab,
+            int32_t* lab_am, hipStream_t s);
+void pack(const Tile& t, int c_lo, int Rq, const double* u0, const int32_t* perm, double* u,
+          hipStream_t s);
+void unpack(const Tile& t, int c_lo, int Rq, const double* u, const int32_t* perm, double* out,
+            hipStream_t s);
+}  // namespace k
+
+}  // namespace sp

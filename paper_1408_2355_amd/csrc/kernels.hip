@@ -1,0 +1,1048 @@
+// HIP kernels of the segregation time step for CDNA4 (gfx950).
+//
+// Vector layout: [n][rp], the rp column values of one vertex contiguous, so a
+// 64-lane wavefront reading one row reads one long contiguous run.  Matrices
+// are ELL, slot-major ([W][n]), slot 0 = diagonal.  The work is bound by HBM
+// bandwidth: no MFMA (there is no dense contraction on this path).
+//
+// Row-parallel kernels use the Tile mapping of internal.h: each thread owns 4
+// consecutive columns of a row; per-column dot products are reduced inside
+// the workgroup (fixed tree order) and written as one partial per row chunk;
+// small column-parallel kernels add the chunk partials in chunk order.  All
+// reductions are float64 and deterministic for a fixed tiling.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "kernels.h"
+
+namespace sp {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+template <typename T>
+struct V4 {
+  T v[4];
+};
+
+__device__ __forceinline__ V4<double> ld4(const double* p) {
+  const double2* q = reinterpret_cast<const double2*>(p);
+  double2 a = q[0], b = q[1];
+  return {{a.x, a.y, b.x, b.y}};
+}
+__device__ __forceinline__ V4<float> ld4(const float* p) {
+  float4 a = *reinterpret_cast<const float4*>(p);
+  return {{a.x, a.y, a.z, a.w}};
+}
+__device__ __forceinline__ void st4(double* p, const V4<double>& x) {
+  double2* q = reinterpret_cast<double2*>(p);
+  q[0] = make_double2(x.v[0], x.v[1]);
+  q[1] = make_double2(x.v[2], x.v[3]);
+}
+__device__ __forceinline__ void st4(float* p, const V4<float>& x) {
+  *reinterpret_cast<float4*>(p) = make_float4(x.v[0], x.v[1], x.v[2], x.v[3]);
+}
+
+// Logical (chunk, column tile) of this workgroup.  Workgroups are handed to
+// the 8 XCDs round-robin by id; remap so every XCD gets one contiguous range
+// of logical blocks (neighbouring row chunks of one column tile), which keeps
+// the gathered neighbour rows in that XCD's L2.
+__device__ __forceinline__ void tile_block(const Tile& t, int& chunk, int& ct) {
+  int b = blockIdx.x, nb = t.nblk;
+  int q = nb >> 3, rem = nb & 7;
+  int x = b & 7, k = b >> 3;
+  int L = x * q + min(x, rem) + k;
+  chunk = L % t.nchunk;
+  ct = L / t.nchunk;
+}
+
+__device__ __forceinline__ size_t part_off(const Tile& t, int d) {
+  return size_t(d) * size_t(t.nchunk) * size_t(t.rp);
+}
+
+// Reduce ND x 4 per-thread sums over the tr rows of the workgroup (tree,
+// fixed order) and store them as the chunk's partials.
+template <int ND>
+__device__ void block_store(const Tile& t, double (&s)[ND][4], double* part, int chunk, int ct) {
+  __shared__ double red[kBlock * 4];
+  const int tid = threadIdx.x, rl = tid / t.tg, gl = tid % t.tg;
+  const int g = ct * t.tg + gl;
+  for (int d = 0; d < ND; ++d) {
+    for (int j = 0; j < 4; ++j) red[tid * 4 + j] = s[d][j];
+    for (int st = t.tr >> 1; st >= 1; st >>= 1) {
+      __syncthreads();
+      if (rl < st)
+        for (int j = 0; j < 4; ++j) red[tid * 4 + j] += red[(tid + st * t.tg) * 4 + j];
+    }
+    __syncthreads();
+    if (rl == 0 && g < t.G)
+      for (int j = 0; j < 4; ++j)
+        part[part_off(t, d) + size_t(chunk) * t.rp + 4 * g + j] = red[tid * 4 + j];
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ double sum_chunks(const double* p, int nchunk, int rp, int c) {
+  double s = 0.0;
+  for (int ch = 0; ch < nchunk; ++ch) s += p[size_t(ch) * rp + c];
+  return s;
+}
+
+// Count the columns for which flag is set, into *counter (one atomic per wave).
+__device__ __forceinline__ void count_active(int flag, int* counter) {
+  unsigned long long bal = __ballot(flag);
+  if ((threadIdx.x & 63) == 0 && bal) atomicAdd(counter, __popcll(bal));
+}
+
+// --------------------------------------------------------------- assembly --
+// One thread per row.  P1 element matrices on a flat triangle with corners
+// x0, x1, x2 and edges e_a opposite corner a (e0 = x2 - x1, e1 = x0 - x2,
+// e2 = x1 - x0):
+//   mass       |T|/12 (1 + delta_ab)
+//   stiffness  (e_a . e_b) / (4 |T|)     (the gradient of corner a's hat
+//              function is the in-plane rotation of e_a over 2|T|)
+// Contributions are added in the fixed incident-triangle order of the row.
+__global__ __launch_bounds__(kBlock) void k_assemble(int n, int W, const int* __restrict__ cols,
+                                                     const double* __restrict__ xyz,
+                                                     const int* __restrict__ tri,
+                                                     const int* __restrict__ inc_ptr,
+                                                     const int* __restrict__ inc,
+                                                     double* __restrict__ M, double* __restrict__ A,
+                                                     double* __restrict__ tarea) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = 0; k < W; ++k) {
+    M[size_t(k) * n + i] = 0.0;
+    A[size_t(k) * n + i] = 0.0;
+  }
+  for (int e = inc_ptr[i]; e < inc_ptr[i + 1]; ++e) {
+    const int code = inc[e], t = code / 3, a = code % 3;
+    int v[3];
+    double x[3][3];
+    for (int c = 0; c < 3; ++c) {
+      v[c] = tri[3 * t + c];
+      for (int d = 0; d < 3; ++d) x[c][d] = xyz[3 * size_t(v[c]) + d];
+    }
+    double ed[3][3];
+    for (int d = 0; d < 3; ++d) {
+      ed[0][d] = x[2][d] - x[1][d];
+      ed[1][d] = x[0][d] - x[2][d];
+      ed[2][d] = x[1][d] - x[0][d];
+    }
+    // (x1 - x0) x (x2 - x0) = e2 x (-e1)
+    double cx = -(ed[2][1] * ed[1][2] - ed[2][2] * ed[1][1]);
+    double cy = -(ed[2][2] * ed[1][0] - ed[2][0] * ed[1][2]);
+    double cz = -(ed[2][0] * ed[1][1] - ed[2][1] * ed[1][0]);
+    double area = 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
+    if (a == 0) tarea[t] = area;
+    for (int b = 0; b < 3; ++b) {
+      int slot = 0;
+      for (int k = 0; k < W; ++k)
+        if (cols[size_t(k) * n + i] == v[b]) { slot = k; break; }
+      double dot = ed[a][0] * ed[b][0] + ed[a][1] * ed[b][1] + ed[a][2] * ed[b][2];
+      M[size_t(slot) * n + i] += area * (a == b ? 2.0 : 1.0) / 12.0;
+      A[size_t(slot) * n + i] += dot / (4.0 * area);
+    }
+  }
+}
+
+__global__ void k_tau_mats(size_t total, int n, double tau, const double* __restrict__ M,
+                           const double* __restrict__ A, double* __restrict__ K64,
+                           float* __restrict__ K32, double* __restrict__ dinv64,
+                           float* __restrict__ dinv32) {
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  double k = M[i] + tau * A[i];
+  K64[i] = k;
+  K32[i] = float(k);
+  if (i < size_t(n)) {
+    double d = 1.0 / k;
+    dinv64[i] = d;
+    dinv32[i] = float(d);
+  }
+}
+
+// Marks a solve that ended with columns still active (iteration cap hit).
+__global__ void k_flag_nonconv(const int* counter, long long* stat) {
+  if (threadIdx.x == 0 && *counter != 0) stat[2] = 1;
+}
+
+template <typename T>
+__global__ void k_fill(T* p, T v, size_t n) {
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ------------------------------------------------------------- float64 CG --
+// r0 = b - K u = M u - (M + tau A) u = -tau A u (no cancellation), z0 = D r0,
+// p0 = z0; partials ||M u||^2, r.z, r.r.
+__global__ __launch_bounds__(kBlock) void k_init_fp64(StepArgs a, const double* __restrict__ u,
+                                                      double* __restrict__ r,
+                                                      double* __restrict__ p) {
+  const Tile& t = a.t;
+  int chunk, ct;
+  tile_block(t, chunk, ct);
+  const int rl = threadIdx.x / t.tg, g = ct * t.tg + threadIdx.x % t.tg;
+  double s[3][4] = {};
+  if (g < t.G) {
+    const int c0 = 4 * g;
+    double lv[4];
+    for (int j = 0; j < 4; ++j) lv[j] = a.ct.live[c0 + j] ? 1.0 : 0.0;
+    const int r1 = min(chunk * t.ch + t.ch, t.n);
+    for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
+      double au[4] = {}, mu[4] = {};
+      for (int k = 0; k < a.W; ++k) {
+        const size_t o = size_t(k) * t.n + row;
+        const int c = a.cols[o];
+        const double va = a.A64[o], vm = a.M64[o];
+        V4<double> x = ld4(u + size_t(c) * t.rp + c0);
+        for (int j = 0; j < 4; ++j) {
+          au[j] = fma(va, x.v[j], au[j]);
+          mu[j] = fma(vm, x.v[j], mu[j]);
+        }
+      }
+      const double di = a.dinv64[row];
+      V4<double> rv, pv;
+      for (int j = 0; j < 4; ++j) {
+        rv.v[j] = -a.tau * au[j] * lv[j];
+        pv.v[j] = di * rv.v[j];
+        s[0][j] += mu[j] * mu[j] * lv[j];
+        s[1][j] += rv.v[j] * pv.v[j];
+        s[2][j] += rv.v[j] * rv.v[j];
+      }
+      st4(r + size_t(row) * t.rp + c0, rv);
+      st4(p + size_t(row) * t.rp + c0, pv);
+    }
+  }
+  block_store<3>(t, s, a.part, chunk, ct);
+}
+
+__global__ void k_red_init_fp64(StepArgs a) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  int act = 0;
+  if (c < a.t.rp) {
+    const Tile& t = a.t;
+    double bb = sum_chunks(a.part + part_off(t, 0), t.nchunk, t.rp, c);
+    double rz = sum_chunks(a.part + part_off(t, 1), t.nchunk, t.rp, c);
+    double rr = sum_chunks(a.part + part_off(t, 2), t.nchunk, t.rp, c);
+    a.cg.bb[c] = bb;
+    a.cg.rz[c] = rz;
+    a.cg.tol2[c] = a.rtol2 * bb;
+    act = (a.ct.live[c] && rr > a.rtol2 * bb) ? 1 : 0;
+    a.cg.act[c] = act;
+    a.cg.alpha[c] = 0.0;
+    a.cg.beta[c] = 0.0;
+  }
+  count_active(act, a.ring + 0);
+}
+
+// q = K p, partial p.q (per column).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_spmm(StepArgs a, int slot, const T* __restrict__ K,
+                                                    const T* __restrict__ p, T* __restrict__ q) {
+  if (a.ring[slot] == 0) return;
+  const Tile& t = a.t;
+  int chunk, ct;
+  tile_block(t, chunk, ct);
+  const int rl = threadIdx.x / t.tg, g = ct * t.tg + threadIdx.x % t.tg;
+  double s[1][4] = {};
+  if (g < t.G) {
+    const int c0 = 4 * g;
+    const int any = a.cg.act[c0] | a.cg.act[c0 + 1] | a.cg.act[c0 + 2] | a.cg.act[c0 + 3];
+    if (any) {
+      const int r1 = min(chunk * t.ch + t.ch, t.n);
+      for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
+        V4<T> acc = {}, pd = {};
+        for (int k = 0; k < a.W; ++k) {
+          const size_t o = size_t(k) * t.n + row;
+          const int c = a.cols[o];
+          const T v = K[o];
+          V4<T> x = ld4(p + size_t(c) * t.rp + c0);
+          if (k == 0) pd = x;
+          for (int j = 0; j < 4; ++j) acc.v[j] = fma(v, x.v[j], acc.v[j]);
+        }
+        st4(q + size_t(row) * t.rp + c0, acc);
+        for (int j = 0; j < 4; ++j) s[0][j] += double(pd.v[j]) * double(acc.v[j]);
+      }
+    }
+  }
+  block_store<1>(t, s, a.part, chunk, ct);
+}
+
+__global__ void k_red_alpha(StepArgs a, int slot, int next) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.ring[next] = 0;
+  if (a.ring[slot] == 0) return;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.t.rp) return;
+  double al = 0.0;
+  if (a.cg.act[c]) {
+    double pq = sum_chunks(a.part, a.t.nchunk, a.t.rp, c);
+    if (pq > 0.0) al = a.cg.rz[c] / pq;
+  }
+  a.cg.alpha[c] = al;
+}
+
+// x += alpha p, r -= alpha q, z = D r; partials r.z and r.r.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_update(StepArgs a, int slot, T* __restrict__ x,
+                                                      T* __restrict__ r, const T* __restrict__ p,
+                                                      const T* __restrict__ q,
+                                                      const T* __restrict__ dinv) {
+  if (a.ring[slot] == 0) return;
+  const Tile& t = a.t;
+  int chunk, ct;
+  tile_block(t, chunk, ct);
+  const int rl = threadIdx.x / t.tg, g = ct * t.tg + threadIdx.x % t.tg;
+  double s[2][4] = {};
+  if (g < t.G) {
+    const int c0 = 4 * g;
+    int act[4];
+    T al[4];
+    int any = 0;
+    for (int j = 0; j < 4; ++j) {
+      act[j] = a.cg.act[c0 + j];
+      al[j] = T(a.cg.alpha[c0 + j]);
+      any |= act[j];
+    }
+    if (any) {
+      const int r1 = min(chunk * t.ch + t.ch, t.n);
+      for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
+        const size_t o = size_t(row) * t.rp + c0;
+        V4<T> xv = ld4(x + o), rv = ld4(r + o);
+        const V4<T> pv = ld4(p + o), qv = ld4(q + o);
+        const T di = dinv[row];
+        for (int j = 0; j < 4; ++j) {
+          if (act[j]) {
+            xv.v[j] = fma(al[j], pv.v[j], xv.v[j]);
+            rv.v[j] = fma(-al[j], qv.v[j], rv.v[j]);
+            const double rd = double(rv.v[j]);
+            s[0][j] += rd * double(di * rv.v[j]);
+            s[1][j] += rd * rd;
+          }
+        }
+        st4(x + o, xv);
+        st4(r + o, rv);
+      }
+    }
+  }
+  block_store<2>(t, s, a.part, chunk, ct);
+}
+
+__global__ void k_red_beta(StepArgs a, int slot, int next) {
+  if (a.ring[slot] == 0) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.stat[0] += 1;  // an iteration that did work
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  int still = 0;
+  if (c < a.t.rp && a.cg.act[c]) {
+    const Tile& t = a.t;
+    double rzn = sum_chunks(a.part + part_off(t, 0), t.nchunk, t.rp, c);
+    double rr = sum_chunks(a.part + part_off(t, 1), t.nchunk, t.rp, c);
+    a.cg.iters[c] += 1;
+    if (rr <= a.cg.tol2[c] || !(rr == rr)) {
+      a.cg.act[c] = 0;
+      a.cg.beta[c] = 0.0;
+    } else {
+      a.cg.beta[c] = rzn / a.cg.rz[c];
+      a.cg.rz[c] = rzn;
+      still = 1;
+    }
+  }
+  count_active(still, a.ring + next);
+}
+
+// p = D r + beta p
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_update_p(StepArgs a, int next, T* __restrict__ p,
+                                                        const T* __restrict__ r,
+                                                        const T* __restrict__ dinv) {
+  if (a.ring[next] == 0) return;
+  const Tile& t = a.t;
+  int chunk, ct;
+  tile_block(t, chunk, ct);
+  const int rl = threadIdx.x / t.tg, g = ct * t.tg + threadIdx.x % t.tg;
+  if (g >= t.G) return;
+  const int c0 = 4 * g;
+  int act[4];
+  T be[4];
+  int any = 0;
+  for (int j = 0; j < 4; ++j) {
+    act[j] = a.cg.act[c0 + j];
+    be[j] = T(a.cg.beta[c0 + j]);
+    any |= act[j];
+  }
+  if (!any) return;
+  const int r1 = min(chunk * t.ch + t.ch, t.n);
+  for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
+    const size_t o = size_t(row) * t.rp + c0;
+    V4<T> pv = ld4(p + o);
+    const V4<T> rv = ld4(r + o);
+    const T di = dinv[row];
+    for (int j = 0; j < 4; ++j)
+      if (act[j]) pv.v[j] = fma(be[j], pv.v[j], di * rv.v[j]);
+    st4(p + o, pv);
+  }
+}
+
+// ------------------------------------------------- mixed-precision refinement --
+// Outer residual r64 = -tau A u (float64), partials ||M u||^2 and ||r64||^2.
+__global__ __launch_bounds__(kBlock) void k_init_outer(StepArgs a, const double* __restrict__ u,
+                                                       double* __restrict__ r64) {
+  const Tile& t = a.t;
+  int chunk, ct;
+  tile_block(t, chunk, ct);
+  const int rl = threadIdx.x / t.tg, g = ct * t.tg + threadIdx.x % t.tg;
+  double s[2][4] = {};
+  if (g < t.G) {
+    const int c0 = 4 * g;
+    double lv[4];
+    for (int j = 0; j < 4; ++j) lv[j] = a.ct.live[c0 + j] ? 1.0 : 0.0;
+    const int r1 = min(chunk * t.ch + t.ch, t.n);
+    for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
+      double au[4] = {}, mu[4] = {};
+      for (int k = 0; k < a.W; ++k) {
+        const size_t o = size_t(k) * t.n + row;
+        const int c = a.cols[o];
+        const double va = a.A64[o], vm = a.M64[o];
+        V4<double> x = ld4(u + size_t(c) * t.rp + c0);
+        for (int j = 0; j < 4; ++j) {
+          au[j] = fma(va, x.v[j], au[j]);
+          mu[j] = fma(vm, x.v[j], mu[j]);
+        }
+      }
+      V4<double> rv;
+      for (int j = 0; j < 4; ++j) {
+        rv.v[j] = -a.tau * au[j] * lv[j];
+        s[0][j] += mu[j] * mu[j] * lv[j];
+        s[1][j] += rv.v[j] * rv.v[j];
+      }
+      st4(r64 + size_t(row) * t.rp + c0, rv);
+    }
+  }
+  block_store<2>(t, s, a.part, chunk, ct);
+}
+
+__global__ void k_red_outer_init(StepArgs a) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  int act = 0;
+  if (c < a.t.rp) {
+    const Tile& t = a.t;
+    double bb = sum_chunks(a.part + part_off(t, 0), t.nchunk, t.rp, c);
+    double rr = sum_chunks(a.part + part_off(t, 1), t.nchunk, t.rp, c);
+    a.cg.bb[c] = bb;
+    a.cg.rr_o[c] = rr;
+    act = (a.ct.live[c] && rr > a.rtol2 * bb) ? 1 : 0;
+    a.cg.act_o[c] = act;
+    a.cg.act[c] = 0;
+  }
+  count_active(act, a.oring + 0);
+}
+
+// Start of an inner float32 solve K d = r64: d = 0, r = float(r64), p = D r.
+__global__ __launch_bounds__(kBlock) void k_inner_init(StepArgs a, int oslot,
+                                                       const double* __restrict__ r64,
+                                                       float* __restrict__ d,
+                                                       float* __restrict__ r,
+                                                       float* __restrict__ p) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.ring[0] = 0;
+  if (a.oring[oslot] == 0) return;
+  const Tile& t = a.t;
+  int chunk, ct;
+  tile_block(t, chunk, ct);
+  const int rl = threadIdx.x / t.tg, g = ct * t.tg + threadIdx.x % t.tg;
+  double s[2][4] = {};
+  if (g < t.G) {
+    const int c0 = 4 * g;
+    int act[4];
+    for (int j = 0; j < 4; ++j) act[j] = a.cg.act_o[c0 + j];
+    const int r1 = min(chunk * t.ch + t.ch, t.n);
+    for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
+      const size_t o = size_t(row) * t.rp + c0;
+      const V4<double> rd = ld4(r64 + o);
+      const float di = a.dinv32[row];
+      V4<float> rv, pv, dv = {};
+      for (int j = 0; j < 4; ++j) {
+        rv.v[j] = act[j] ? float(rd.v[j]) : 0.0f;
+        pv.v[j] = di * rv.v[j];
+        s[0][j] += double(rv.v[j]) * double(pv.v[j]);
+        s[1][j] += double(rv.v[j]) * double(rv.v[j]);
+      }
+      st4(d + o, dv);
+      st4(r + o, rv);
+      st4(p + o, pv);
+    }
+  }
+  block_store<2>(t, s, a.part, chunk, ct);
+}
+
+__global__ void k_red_inner_init(StepArgs a, int oslot, int onext) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.oring[onext] = 0;
+  if (a.oring[oslot] == 0) return;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  int act = 0;
+  if (c < a.t.rp) {
+    const Tile& t = a.t;
+    double rz = sum_chunks(a.part + part_off(t, 0), t.nchunk, t.rp, c);
+    double rr = sum_chunks(a.part + part_off(t, 1), t.nchunk, t.rp, c);
+    a.cg.rz[c] = rz;
+    // stop the inner solve once its residual drops by inner_rtol, or below a
+    // quarter of the outer target (no point solving further than needed)
+    a.cg.tol2[c] = fmax(a.inner_rtol2 * rr, 0.0625 * a.rtol2 * a.cg.bb[c]);
+    act = (a.cg.act_o[c] && rr > 0.0) ? 1 : 0;
+    a.cg.act[c] = act;
+    a.cg.alpha[c] = 0.0;
+    a.cg.beta[c] = 0.0;
+  }
+  count_active(act, a.ring + 0);
+}
+
+// x64 += d; r64 -= K64 d (float64 product of the float32 correction);
+// partial ||r64||^2.
+__global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot,
+                                                         double* __restrict__ u,
+                                                         double* __restrict__ r64,
+                                                         const float* __restrict__ d) {
+  if (a.oring[oslot] == 0) return;
+  const Tile& t = a.t;
+  int chunk, ct;
+  tile_block(t, chunk, ct);
+  const int rl = threadIdx.x / t.tg, g = ct * t.tg + threadIdx.x % t.tg;
+  double s[1][4] = {};
+  if (g < t.G) {
+    const int c0 = 4 * g;
+    int act[4], any = 0;
+    for (int j = 0; j < 4; ++j) {
+      act[j] = a.cg.act_o[c0 + j];
+      any |= act[j];
+    }
+    if (any) {
+      const int r1 = min(chunk * t.ch + t.ch, t.n);
+      for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
+        double kd[4] = {};
+        float dd[4] = {};
+        for (int k = 0; k < a.W; ++k) {
+          const size_t o = size_t(k) * t.n + row;
+          const int c = a.cols[o];
+          const double v = a.K64[o];
+          V4<float> x = ld4(d + size_t(c) * t.rp + c0);
+          if (k == 0)
+            for (int j = 0; j < 4; ++j) dd[j] = x.v[j];
+          for (int j = 0; j < 4; ++j) kd[j] = fma(v, double(x.v[j]), kd[j]);
+        }
+        const size_t o = size_t(row) * t.rp + c0;
+        V4<double> uv = ld4(u + o), rv = ld4(r64 + o);
+        for (int j = 0; j < 4; ++j) {
+          if (act[j]) {
+            uv.v[j] += double(dd[j]);
+            rv.v[j] -= kd[j];
+            s[0][j] += rv.v[j] * rv.v[j];
+          }
+        }
+        st4(u + o, uv);
+        st4(r64 + o, rv);
+      }
+    }
+  }
+  block_store<1>(t, s, a.part, chunk, ct);
+}
+
+__global__ void k_red_outer(StepArgs a, int oslot, int onext) {
+  if (a.oring[oslot] == 0) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.stat[1] += 1;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  int still = 0;
+  if (c < a.t.rp && a.cg.act_o[c]) {
+    double rr = sum_chunks(a.part, a.t.nchunk, a.t.rp, c);
+    a.cg.rr_o[c] = rr;
+    a.cg.sweeps[c] += 1;
+    if (rr <= a.rtol2 * a.cg.bb[c] || !(rr == rr))
+      a.cg.act_o[c] = 0;
+    else
+      still = 1;
+  }
+  count_active(still, a.oring + onext);
+}
+
+// -------------------------------------------------------------- node step --
+// Step 2 of Algorithm 2.2 in its practical form: S = sum_j u~_j^2 over the
+// restart's components, u^_i = u~_i exp(-(2 tau/eps^2)(S - u~_i^2)).
+__global__ __launch_bounds__(kBlock) void k_nodal(StepArgs a, const double* __restrict__ u,
+                                                  double* __restrict__ out) {
+  const Tile& t = a.t;
+  int chunk, ct;
+  tile_block(t, chunk, ct);
+  const int rl = threadIdx.x / t.tg, g = ct * t.tg + threadIdx.x % t.tg;
+  if (g >= t.G) return;
+  const int c0 = 4 * g;
+  int lo[4], len[4], lv[4];
+  double cf[4];
+  for (int j = 0; j < 4; ++j) {
+    lo[j] = a.ct.seg_lo[c0 + j];
+    len[j] = a.ct.seg_len[c0 + j];
+    lv[j] = a.ct.live[c0 + j];
+    cf[j] = a.ct.coef[c0 + j];
+  }
+  if (!(lv[0] | lv[1] | lv[2] | lv[3])) return;
+  const int r1 = min(chunk * t.ch + t.ch, t.n);
+  for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
+    const double* ur = u + size_t(row) * t.rp;
+    V4<double> uv = ld4(ur + c0), ov = uv;
+    double S = 0.0;
+    int cur = -1;
+    for (int j = 0; j < 4; ++j) {
+      if (!lv[j]) continue;
+      if (lo[j] != cur) {
+        cur = lo[j];
+        S = 0.0;
+        for (int i = 0; i < len[j]; ++i) {
+          const double w = ur[lo[j] + i];
+          S = fma(w, w, S);
+        }
+      }
+      const double x = uv.v[j];
+      ov.v[j] = x * exp(-cf[j] * (S - x * x));
+    }
+    st4(out + size_t(row) * t.rp + c0, ov);
+  }
+}
+
+// ---------------------------------------------------------- normalisation --
+__global__ __launch_bounds__(kBlock) void k_norm_dot(StepArgs a, const double* __restrict__ v) {
+  const Tile& t = a.t;
+  int chunk, ct;
+  tile_block(t, chunk, ct);
+  const int rl = threadIdx.x / t.tg, g = ct * t.tg + threadIdx.x % t.tg;
+  double s[1][4] = {};
+  if (g < t.G) {
+    const int c0 = 4 * g;
+    int lv[4], any = 0;
+    for (int j = 0; j < 4; ++j) {
+      lv[j] = a.ct.live[c0 + j];
+      any |= lv[j];
+    }
+    if (any) {
+      const int r1 = min(chunk * t.ch + t.ch, t.n);
+      for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
+        double mv[4] = {};
+        V4<double> vd = {};
+        for (int k = 0; k < a.W; ++k) {
+          const size_t o = size_t(k) * t.n + row;
+          const int c = a.cols[o];
+          const double w = a.M64[o];
+          V4<double> x = ld4(v + size_t(c) * t.rp + c0);
+          if (k == 0) vd = x;
+          for (int j = 0; j < 4; ++j) mv[j] = fma(w, x.v[j], mv[j]);
+        }
+        for (int j = 0; j < 4; ++j)
+          if (lv[j]) s[0][j] += vd.v[j] * mv[j];
+      }
+    }
+  }
+  block_store<1>(t, s, a.part, chunk, ct);
+}
+
+__global__ void k_red_norm(StepArgs a) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.t.rp) return;
+  double nv = 1.0;
+  if (a.ct.live[c]) nv = sqrt(sum_chunks(a.part, a.t.nchunk, a.t.rp, c));
+  a.cg.nrm[c] = nv;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scale(StepArgs a, const double* __restrict__ v,
+                                                  double* __restrict__ u) {
+  const Tile& t = a.t;
+  int chunk, ct;
+  tile_block(t, chunk, ct);
+  const int rl = threadIdx.x / t.tg, g = ct * t.tg + threadIdx.x % t.tg;
+  if (g >= t.G) return;
+  const int c0 = 4 * g;
+  int lv[4], any = 0;
+  double inv[4];
+  for (int j = 0; j < 4; ++j) {
+    lv[j] = a.ct.live[c0 + j];
+    any |= lv[j];
+    inv[j] = 1.0 / a.cg.nrm[c0 + j];
+  }
+  if (!any) return;
+  const int r1 = min(chunk * t.ch + t.ch, t.n);
+  for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
+    const size_t o = size_t(row) * t.rp + c0;
+    const V4<double> vv = ld4(v + o);
+    V4<double> uv = ld4(u + o);
+    for (int j = 0; j < 4; ++j)
+      if (lv[j]) uv.v[j] = vv.v[j] * inv[j];
+    st4(u + o, uv);
+  }
+}
+
+// ---------------------------------------------------------------- energies --
+// Rayleigh quotient parts u.Au and u.Mu per column.
+__global__ __launch_bounds__(kBlock) void k_energy_rq(StepArgs a, const double* __restrict__ u) {
+  const Tile& t = a.t;
+  int chunk, ct;
+  tile_block(t, chunk, ct);
+  const int rl = threadIdx.x / t.tg, g = ct * t.tg + threadIdx.x % t.tg;
+  double s[2][4] = {};
+  if (g < t.G) {
+    const int c0 = 4 * g;
+    int lv[4], any = 0;
+    for (int j = 0; j < 4; ++j) {
+      lv[j] = a.ct.seg_len[c0 + j] > 0;
+      any |= lv[j];
+    }
+    if (any) {
+      const int r1 = min(chunk * t.ch + t.ch, t.n);
+      for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
+        double au[4] = {}, mu[4] = {};
+        V4<double> ud = {};
+        for (int k = 0; k < a.W; ++k) {
+          const size_t o = size_t(k) * t.n + row;
+          const int c = a.cols[o];
+          const double va = a.A64[o], vm = a.M64[o];
+          V4<double> x = ld4(u + size_t(c) * t.rp + c0);
+          if (k == 0) ud = x;
+          for (int j = 0; j < 4; ++j) {
+            au[j] = fma(va, x.v[j], au[j]);
+            mu[j] = fma(vm, x.v[j], mu[j]);
+          }
+        }
+        for (int j = 0; j < 4; ++j)
+          if (lv[j]) {
+            s[0][j] += ud.v[j] * au[j];
+            s[1][j] += ud.v[j] * mu[j];
+          }
+      }
+    }
+  }
+  block_store<2>(t, s, a.part, chunk, ct);
+}
+
+// S_eps element kernel.  On a triangle T the P1 functions are u_i = sum_p
+// a_ip b_p in the barycentric coordinates b_p, and
+//   int_T b^alpha = 2|T| alpha! / (|alpha| + 2)!.
+// For symmetric 3x3 G, H the quartic moment
+//   B(G, H) = (360/|T|) sum_{pqrs} G_pq H_rs int_T b_p b_q b_r b_s
+// equals, summing over the 24 permutations of the four slots,
+//   S_G S_H + tr_G S_H + S_G tr_H + tr_G tr_H + 2 <G,H> + 4 g.h
+//     + 4 dG.h + 4 g.dH + 6 dG.dH
+// with S = 1^T X 1, tr = trace, g = G 1, h = H 1, dX = diag X.  Then
+//   int_T sum_{i != j} u_i^2 u_j^2 = (2|T|/360) sum_i B(G_{<i}, a_i a_i^T),
+//   G_{<i} = sum_{j<i} a_j a_j^T,
+// a sum of nonnegative terms for nonnegative u (no cancellation).  Each
+// thread takes one (triangle, restart); the restart's m vertex triples are
+// read straight from the [n][rp] state (consecutive restarts are adjacent in
+// memory).  Partials per (triangle chunk, restart).
+__global__ __launch_bounds__(kBlock) void k_energy_seps(StepArgs a, Tile tt,
+                                                        const int* __restrict__ tri,
+                                                        const double* __restrict__ tarea,
+                                                        const double* __restrict__ u,
+                                                        double* __restrict__ part_s) {
+  int chunk, ct;
+  tile_block(tt, chunk, ct);
+  const int tid = threadIdx.x, rl = tid / tt.tg, gl = tid % tt.tg;
+  const int r = ct * tt.tg + gl;
+  double acc_all = 0.0;
+  if (r < a.ct.nres) {
+    const int lo = a.ct.res_lo[r], m = a.ct.res_len[r];
+    const int r1 = min(chunk * tt.ch + tt.ch, tt.n);
+    for (int tr_ = chunk * tt.ch + rl; tr_ < r1; tr_ += tt.tr) {
+      const double* u0 = u + size_t(tri[3 * tr_ + 0]) * a.t.rp + lo;
+      const double* u1 = u + size_t(tri[3 * tr_ + 1]) * a.t.rp + lo;
+      const double* u2 = u + size_t(tri[3 * tr_ + 2]) * a.t.rp + lo;
+      double g00 = 0, g11 = 0, g22 = 0, g01 = 0, g02 = 0, g12 = 0, acc = 0;
+      for (int i = 0; i < m; ++i) {
+        const double x0 = u0[i], x1 = u1[i], x2 = u2[i];
+        const double s1 = x0 + x1 + x2;
+        const double q0 = x0 * x0, q1 = x1 * x1, q2 = x2 * x2;
+        const double s2 = q0 + q1 + q2;
+        const double trG = g00 + g11 + g22;
+        const double SG = trG + 2.0 * (g01 + g02 + g12);
+        const double gv0 = g00 + g01 + g02, gv1 = g01 + g11 + g12, gv2 = g02 + g12 + g22;
+        const double ga = gv0 * x0 + gv1 * x1 + gv2 * x2;
+        const double da = g00 * x0 + g11 * x1 + g22 * x2;
+        const double gq = gv0 * q0 + gv1 * q1 + gv2 * q2;
+        const double dq = g00 * q0 + g11 * q1 + g22 * q2;
+        const double aGa = dq + 2.0 * (x0 * x1 * g01 + x0 * x2 * g02 + x1 * x2 * g12);
+        acc += (SG + trG) * s1 * s1 + (SG + trG) * s2 + 2.0 * aGa + 4.0 * s1 * (ga + da) +
+               4.0 * gq + 6.0 * dq;
+        g00 += q0;
+        g11 += q1;
+        g22 += q2;
+        g01 += x0 * x1;
+        g02 += x0 * x2;
+        g12 += x1 * x2;
+      }
+      acc_all += acc * tarea[tr_] * (1.0 / 180.0);
+    }
+  }
+  __shared__ double red[kBlock];
+  red[tid] = acc_all;
+  for (int st = tt.tr >> 1; st >= 1; st >>= 1) {
+    __syncthreads();
+    if (rl < st) red[tid] += red[tid + st * tt.tg];
+  }
+  __syncthreads();
+  if (rl == 0 && r < tt.rp) part_s[size_t(chunk) * tt.rp + r] = red[tid];
+}
+
+__global__ void k_red_lambda(StepArgs a, double* __restrict__ lam) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.t.rp) return;
+  const Tile& t = a.t;
+  double num = sum_chunks(a.part + part_off(t, 0), t.nchunk, t.rp, c);
+  double den = sum_chunks(a.part + part_off(t, 1), t.nchunk, t.rp, c);
+  lam[c] = a.ct.seg_len[c] > 0 ? num / den : 0.0;
+}
+
+__global__ void k_red_seps(StepArgs a, Tile tt, const double* __restrict__ part_s,
+                           const double* __restrict__ lam, double* __restrict__ seps,
+                           double* __restrict__ energy) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.ct.nres) return;
+  const double s = sum_chunks(part_s, tt.nchunk, tt.rp, r) * a.ct.res_ieps2[r];
+  double e = s;
+  const int lo = a.ct.res_lo[r], m = a.ct.res_len[r];
+  for (int i = 0; i < m; ++i) e += lam[lo + i];
+  seps[r] = s;
+  energy[r] = e;
+}
+
+// ----------------------------------------------------------------- labels --
+// Equation (vi): v_i = u_i - sum_{j != i} u_j = 2 u_i - sum_j u_j; label =
+// argmax_i v_i if positive else -1; second labelling = argmax_i u_i (lowest
+// index wins ties in both).
+__global__ void k_labels(StepArgs a, const double* __restrict__ u, const int* __restrict__ perm,
+                         int* __restrict__ lab, int* __restrict__ lab_am) {
+  const size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const size_t nres = size_t(a.ct.nres);
+  if (idx >= size_t(a.t.n) * nres) return;
+  const int row = int(idx / nres), r = int(idx % nres);
+  const int lo = a.ct.res_lo[r], m = a.ct.res_len[r];
+  const double* ur = u + size_t(row) * a.t.rp + lo;
+  double tot = 0.0;
+  for (int i = 0; i < m; ++i) tot += ur[i];
+  int best = 0, am = 0;
+  double vb = 2.0 * ur[0] - tot, ub = ur[0];
+  for (int i = 1; i < m; ++i) {
+    const double v = 2.0 * ur[i] - tot;
+    if (v > vb) { vb = v; best = i; }
+    if (ur[i] > ub) { ub = ur[i]; am = i; }
+  }
+  const size_t o = size_t(r) * a.t.n + perm[row];
+  if (lab) lab[o] = vb > 0.0 ? best : -1;
+  if (lab_am) lab_am[o] = am;
+}
+
+// ---------------------------------------------------------- layout changes --
+// Caller layout [Rq][n] (component-major, caller vertex numbering) <->
+// columns [c_lo, c_lo + Rq) of the [n][rp] state (renumbered rows).
+__global__ void k_pack(size_t total, int rp, int n, int c_lo, int Rq, const double* __restrict__ u0,
+                       const int* __restrict__ perm, double* __restrict__ u) {
+  const size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int row = int(idx / Rq), c = int(idx % Rq);
+  u[size_t(row) * rp + c_lo + c] = u0[size_t(c) * n + perm[row]];
+}
+
+__global__ void k_unpack(size_t total, int rp, int n, int c_lo, int Rq, const double* __restrict__ u,
+                         const int* __restrict__ perm, double* __restrict__ out) {
+  const size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int row = int(idx / Rq), c = int(idx % Rq);
+  out[size_t(c) * n + perm[row]] = u[size_t(row) * rp + c_lo + c];
+}
+
+inline unsigned nblocks(size_t work, int bs = kBlock) { return unsigned((work + bs - 1) / bs); }
+inline unsigned colblocks(const Tile& t) { return nblocks(size_t(t.rp)); }
+
+#define SP_LAUNCH_CHECK() SP_HIP(hipGetLastError())
+
+}  // namespace
+
+Tile make_tile(int n, int rp, int tg_cap, int target_blocks) {
+  Tile t;
+  t.n = n;
+  t.rp = rp;
+  t.G = tg_cap > 64 ? rp : rp / 4;  // triangle tiles use one restart per "group"
+  int tg = 1;
+  while (tg < t.G && tg < tg_cap) tg <<= 1;
+  t.tg = tg;
+  t.tr = kBlock / tg;
+  t.nct = (t.G + tg - 1) / tg;
+  int want_chunks = std::max(1, target_blocks / t.nct);
+  int ch = (n + want_chunks - 1) / want_chunks;
+  ch = ((ch + t.tr - 1) / t.tr) * t.tr;
+  if (ch < t.tr) ch = t.tr;
+  t.ch = ch;
+  t.nchunk = (n + ch - 1) / ch;
+  t.nblk = t.nchunk * t.nct;
+  return t;
+}
+
+namespace k {
+
+void assemble(const Mesh& m, const double* xyz_new, const int32_t* inc_ptr, const int32_t* inc,
+              hipStream_t s) {
+  hipLaunchKernelGGL(k_assemble, dim3(nblocks(m.n)), dim3(kBlock), 0, s, int(m.n), m.W, m.cols.p,
+                     xyz_new, m.tri.p, inc_ptr, inc, m.M64.p, m.A64.p, m.tarea.p);
+  SP_LAUNCH_CHECK();
+}
+
+void tau_mats(const Mesh& m, TauMats& t, hipStream_t s) {
+  size_t total = size_t(m.W) * m.n;
+  hipLaunchKernelGGL(k_tau_mats, dim3(nblocks(total)), dim3(kBlock), 0, s, total, int(m.n), t.tau,
+                     m.M64.p, m.A64.p, t.K64.p, t.K32.p, t.dinv64.p, t.dinv32.p);
+  SP_LAUNCH_CHECK();
+}
+
+void fill_i32(int32_t* p, int32_t v, size_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(nblocks(n)), dim3(kBlock), 0, s, p, v, n);
+  SP_LAUNCH_CHECK();
+}
+
+void fill_f64(double* p, double v, size_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_fill<double>, dim3(nblocks(n)), dim3(kBlock), 0, s, p, v, n);
+  SP_LAUNCH_CHECK();
+}
+
+void flag_nonconv(const StepArgs& a, const int* counter, hipStream_t s) {
+  hipLaunchKernelGGL(k_flag_nonconv, dim3(1), dim3(64), 0, s, counter, a.stat);
+  SP_LAUNCH_CHECK();
+}
+
+void init_fp64(const StepArgs& a, const double* u, double* r, double* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_fp64, dim3(a.t.nblk), dim3(kBlock), 0, s, a, u, r, p);
+  SP_LAUNCH_CHECK();
+}
+
+void red_init_fp64(const StepArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_red_init_fp64, dim3(colblocks(a.t)), dim3(kBlock), 0, s, a);
+  SP_LAUNCH_CHECK();
+}
+
+template <typename T>
+void cg_iter(const StepArgs& a, int it, T* x, T* r, T* p, T* q, const T* K, const T* dinv,
+             hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  const int slot = it % kRing, next = (it + 1) % kRing;
+  if (ev0) SP_HIP(hipEventRecord(ev0, s));
+  hipLaunchKernelGGL(k_cg_spmm<T>, dim3(a.t.nblk), dim3(kBlock), 0, s, a, slot, K, (const T*)p, q);
+  if (ev1) SP_HIP(hipEventRecord(ev1, s));
+  hipLaunchKernelGGL(k_red_alpha, dim3(colblocks(a.t)), dim3(kBlock), 0, s, a, slot, next);
+  hipLaunchKernelGGL(k_cg_update<T>, dim3(a.t.nblk), dim3(kBlock), 0, s, a, slot, x, r, (const T*)p,
+                     (const T*)q, dinv);
+  hipLaunchKernelGGL(k_red_beta, dim3(colblocks(a.t)), dim3(kBlock), 0, s, a, slot, next);
+  hipLaunchKernelGGL(k_cg_update_p<T>, dim3(a.t.nblk), dim3(kBlock), 0, s, a, next, p, (const T*)r,
+                     dinv);
+  SP_LAUNCH_CHECK();
+}
+
+template void cg_iter<double>(const StepArgs&, int, double*, double*, double*, double*,
+                              const double*, const double*, hipStream_t, hipEvent_t, hipEvent_t);
+template void cg_iter<float>(const StepArgs&, int, float*, float*, float*, float*, const float*,
+                             const float*, hipStream_t, hipEvent_t, hipEvent_t);
+
+void init_outer(const StepArgs& a, const double* u, double* r64, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_outer, dim3(a.t.nblk), dim3(kBlock), 0, s, a, u, r64);
+  SP_LAUNCH_CHECK();
+}
+
+void red_outer_init(const StepArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_red_outer_init, dim3(colblocks(a.t)), dim3(kBlock), 0, s, a);
+  SP_LAUNCH_CHECK();
+}
+
+void inner_init(const StepArgs& a, int o, const double* r64, float* d, float* r, float* p,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_inner_init, dim3(a.t.nblk), dim3(kBlock), 0, s, a, o % kRing, r64, d, r, p);
+  SP_LAUNCH_CHECK();
+}
+
+void red_inner_init(const StepArgs& a, int o, hipStream_t s) {
+  hipLaunchKernelGGL(k_red_inner_init, dim3(colblocks(a.t)), dim3(kBlock), 0, s, a, o % kRing,
+                     (o + 1) % kRing);
+  SP_LAUNCH_CHECK();
+}
+
+void outer_update(const StepArgs& a, int o, double* u, double* r64, const float* d, hipStream_t s) {
+  hipLaunchKernelGGL(k_outer_update, dim3(a.t.nblk), dim3(kBlock), 0, s, a, o % kRing, u, r64, d);
+  SP_LAUNCH_CHECK();
+}
+
+void red_outer(const StepArgs& a, int o, hipStream_t s) {
+  hipLaunchKernelGGL(k_red_outer, dim3(colblocks(a.t)), dim3(kBlock), 0, s, a, o % kRing,
+                     (o + 1) % kRing);
+  SP_LAUNCH_CHECK();
+}
+
+void nodal(const StepArgs& a, const double* u, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_nodal, dim3(a.t.nblk), dim3(kBlock), 0, s, a, u, out);
+  SP_LAUNCH_CHECK();
+}
+
+void norm_dot(const StepArgs& a, const double* v, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm_dot, dim3(a.t.nblk), dim3(kBlock), 0, s, a, v);
+  SP_LAUNCH_CHECK();
+}
+
+void red_norm(const StepArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_red_norm, dim3(colblocks(a.t)), dim3(kBlock), 0, s, a);
+  SP_LAUNCH_CHECK();
+}
+
+void scale(const StepArgs& a, const double* v, double* u, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale, dim3(a.t.nblk), dim3(kBlock), 0, s, a, v, u);
+  SP_LAUNCH_CHECK();
+}
+
+void energy_rq(const StepArgs& a, const double* u, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy_rq, dim3(a.t.nblk), dim3(kBlock), 0, s, a, u);
+  SP_LAUNCH_CHECK();
+}
+
+void energy_seps(const StepArgs& a, const Tile& tt, const int32_t* tri, const double* tarea,
+                 const double* u, double* part_s, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy_seps, dim3(tt.nblk), dim3(kBlock), 0, s, a, tt, tri, tarea, u,
+                     part_s);
+  SP_LAUNCH_CHECK();
+}
+
+void red_energy(const StepArgs& a, const Tile& tt, const double* part_s, double* lam,
+                double* seps, double* energy, hipStream_t s) {
+  hipLaunchKernelGGL(k_red_lambda, dim3(colblocks(a.t)), dim3(kBlock), 0, s, a, lam);
+  hipLaunchKernelGGL(k_red_seps, dim3(nblocks(size_t(a.ct.nres))), dim3(kBlock), 0, s, a, tt,
+                     part_s, (const double*)lam, seps, energy);
+  SP_LAUNCH_CHECK();
+}
+
+void labels(const StepArgs& a, const double* u, const int32_t* perm, int32_t* lab, int32_t* lab_am,
+            hipStream_t s) {
+  size_t total = size_t(a.t.n) * size_t(a.ct.nres);
+  hipLaunchKernelGGL(k_labels, dim3(nblocks(total)), dim3(kBlock), 0, s, a, u, perm, lab, lab_am);
+  SP_LAUNCH_CHECK();
+}
+
+void pack(const Tile& t, int c_lo, int Rq, const double* u0, const int32_t* perm, double* u,
+          hipStream_t s) {
+  size_t total = size_t(t.n) * Rq;
+  if (!total) return;
+  hipLaunchKernelGGL(k_pack, dim3(nblocks(total)), dim3(kBlock), 0, s, total, t.rp, t.n, c_lo, Rq,
+                     u0, perm, u);
+  SP_LAUNCH_CHECK();
+}
+
+void unpack(const Tile& t, int c_lo, int Rq, const double* u, const int32_t* perm, double* out,
+            hipStream_t s) {
+  size_t total = size_t(t.n) * Rq;
+  if (!total) return;
+  hipLaunchKernelGGL(k_unpack, dim3(nblocks(total)), dim3(kBlock), 0, s, total, t.rp, t.n, c_lo, Rq,
+                     u, perm, out);
+  SP_LAUNCH_CHECK();
+}
+
+}  // namespace k
+}  // namespace sp

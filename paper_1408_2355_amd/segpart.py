@@ -1,0 +1,369 @@
+"""Python binding of libsegpart (ctypes, argument marshalling only).
+
+Each ``sp_*`` function here mirrors the C entry point of the same name in
+include/segpart.h: it converts numpy arrays (or torch tensors for the
+device-pointer calls) to pointers, calls the library, and raises
+``SegpartError`` on a negative status.  All computation happens in the HIP
+library; nothing here falls back to the CPU.  ``Mesh``, ``State`` and
+``Server`` are small owners of the opaque handles.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsegpart.so")
+
+SP_OK, SP_EINVAL, SP_EMESH, SP_ENOMEM, SP_EDEVICE, SP_ENOCONV, SP_EAGAIN, SP_ENOTFOUND = \
+    0, -1, -2, -3, -4, -5, -6, -7
+SP_FP64, SP_MIXED = 0, 1
+SP_MAT_M, SP_MAT_A = 0, 1
+SP_STAGE_HEAT, SP_STAGE_NODE, SP_STAGE_NORM = 1, 2, 3
+
+_NAMES = {SP_EINVAL: "SP_EINVAL", SP_EMESH: "SP_EMESH", SP_ENOMEM: "SP_ENOMEM",
+          SP_EDEVICE: "SP_EDEVICE", SP_ENOCONV: "SP_ENOCONV", SP_EAGAIN: "SP_EAGAIN",
+          SP_ENOTFOUND: "SP_ENOTFOUND"}
+
+
+class SegpartError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class sp_params(C.Structure):
+    _fields_ = [("tau", C.c_double), ("n_steps", C.c_int64), ("stop_tol", C.c_double),
+                ("max_steps", C.c_int64), ("energy_every", C.c_int64),
+                ("precision", C.c_int32), ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int32),
+                ("inner_rtol", C.c_double), ("max_outer", C.c_int32),
+                ("check_every", C.c_int32), ("reserved", C.c_int32)]
+
+
+class sp_stats(C.Structure):
+    _fields_ = [("steps_done", C.c_int64), ("cg_iters", C.c_int64),
+                ("outer_sweeps", C.c_int64), ("col_iters_max", C.c_int64),
+                ("seconds", C.c_double), ("converged", C.c_int32), ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+_lib = None
+
+P = C.c_void_p
+PP = C.POINTER(C.c_void_p)
+D = C.POINTER(C.c_double)
+I32 = C.POINTER(C.c_int32)
+I64 = C.POINTER(C.c_int64)
+
+_SIGS = {
+    "sp_last_error": (C.c_char_p, []),
+    "sp_version": (C.c_int, [C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "sp_params_default": (None, [C.POINTER(sp_params), C.c_double]),
+    "sp_mesh_create": (C.c_int, [C.c_int64, D, C.c_int64, I32, PP]),
+    "sp_mesh_info": (C.c_int, [P, I64, I64, I64, D]),
+    "sp_mesh_export": (C.c_int, [P, C.c_int32, I64, I32, D]),
+    "sp_mesh_destroy": (None, [P]),
+    "sp_solve": (C.c_int, [P, C.POINTER(sp_params), C.c_int32, I32, D, D, D, I32, I32, D, D,
+                           D, C.POINTER(sp_stats)]),
+    "sp_solve_async": (C.c_int, [P, C.POINTER(sp_params), C.c_int32, I32, D, P, P, P, P, P,
+                                 P, P, P]),
+    "sp_state_create": (C.c_int, [P, C.POINTER(sp_params), C.c_int32, I32, D, D, P, PP]),
+    "sp_state_step": (C.c_int, [P, C.c_int64]),
+    "sp_state_stage": (C.c_int, [P, C.c_int32]),
+    "sp_state_energy": (C.c_int, [P, D, D, D]),
+    "sp_state_read": (C.c_int, [P, D, I64]),
+    "sp_state_write": (C.c_int, [P, D, C.c_int64, C.c_int32]),
+    "sp_state_labels": (C.c_int, [P, I32, I32]),
+    "sp_state_history": (C.c_int, [P, C.c_int32, C.c_int64, I64, D, I64]),
+    "sp_state_stats": (C.c_int, [P, C.POINTER(sp_stats)]),
+    "sp_state_profile": (C.c_int, [P, C.c_int32]),
+    "sp_state_kernel_time": (C.c_int, [P, I64, D, D]),
+    "sp_state_destroy": (None, [P]),
+    "sp_server_create": (C.c_int, [C.c_int64, C.c_int32, PP]),
+    "sp_server_submit": (C.c_int, [P, P, C.POINTER(sp_params), C.c_int32, I32, D, D, I64]),
+    "sp_server_poll": (C.c_int, [P, C.c_int64, I32]),
+    "sp_server_wait": (C.c_int, [P, C.c_int64, C.c_double]),
+    "sp_server_fetch": (C.c_int, [P, C.c_int64, D, I32, D, D, D, D]),
+    "sp_server_stats": (C.c_int, [P, D, D, D, I64]),
+    "sp_server_destroy": (None, [P]),
+}
+EXPORTED = tuple(_SIGS)
+
+
+def lib():
+    """Load libsegpart.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1408_2355_amd.build`")
+        h = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(h, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = h
+    return _lib
+
+
+def _check(rc, allow=()):
+    if rc < 0 and rc not in allow:
+        raise SegpartError(rc, lib().sp_last_error().decode())
+    return rc
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(D)
+
+
+def _ip(a, t=I32):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def params(tau, **kw):
+    """sp_params with the library defaults for tau, overridden by keywords
+    (precision may be given as "fp64" / "mixed")."""
+    p = sp_params()
+    lib().sp_params_default(C.byref(p), float(tau))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = {"fp64": SP_FP64, "mixed": SP_MIXED}[v]
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def sp_version():
+    a, b = C.c_int(), C.c_int()
+    _check(lib().sp_version(C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def sp_mesh_create(xyz, tri):
+    xyz = _f64(xyz)
+    tri = _i32(tri)
+    h = C.c_void_p()
+    _check(lib().sp_mesh_create(xyz.shape[0], _dp(xyz), tri.shape[0], _ip(tri), C.byref(h)))
+    return h
+
+
+def sp_mesh_info(h):
+    n, t, z, a = C.c_int64(), C.c_int64(), C.c_int64(), C.c_double()
+    _check(lib().sp_mesh_info(h, C.byref(n), C.byref(t), C.byref(z), C.byref(a)))
+    return n.value, t.value, z.value, a.value
+
+
+def sp_mesh_export(h, which):
+    n, _, nnz, _ = sp_mesh_info(h)
+    rp = np.empty(n + 1, np.int64)
+    col = np.empty(nnz, np.int32)
+    val = np.empty(nnz, np.float64)
+    _check(lib().sp_mesh_export(h, which, _ip(rp, I64), _ip(col), _dp(val)))
+    return rp, col, val
+
+
+def _batch(m, eps, u0=None, n=None):
+    m = _i32(np.atleast_1d(m))
+    eps = _f64(np.broadcast_to(np.asarray(eps, np.float64), m.shape))
+    if u0 is not None:
+        u0 = _f64(u0)
+        if u0.shape != (int(m.sum()), n):
+            raise ValueError(f"u0 must have shape ({int(m.sum())}, {n}), got {u0.shape}")
+    return m, eps, u0
+
+
+def sp_solve(mesh_h, prm, m, eps, u0, want_u=True, want_labels=True):
+    """Returns (status, dict of outputs).  status is SP_OK or SP_ENOCONV."""
+    n = sp_mesh_info(mesh_h)[0]
+    m, eps, u0 = _batch(m, eps, u0, n)
+    nres, R = m.size, int(m.sum())
+    out = dict(lam=np.empty(R), s_eps=np.empty(nres), energy=np.empty(nres))
+    if want_u:
+        out["u"] = np.empty((R, n))
+    if want_labels:
+        out["labels"] = np.empty((nres, n), np.int32)
+        out["labels_argmax"] = np.empty((nres, n), np.int32)
+    st = sp_stats()
+    rc = _check(lib().sp_solve(mesh_h, C.byref(prm), nres, _ip(m), _dp(eps), _dp(u0),
+                               _dp(out.get("u")), _ip(out.get("labels")),
+                               _ip(out.get("labels_argmax")), _dp(out["lam"]),
+                               _dp(out["s_eps"]), _dp(out["energy"]), C.byref(st)),
+                allow=(SP_ENOCONV,))
+    out["stats"] = st.as_dict()
+    return rc, out
+
+
+def _tptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def sp_solve_async(mesh_h, prm, m, eps, d_u0, d_u_out=None, d_labels=None,
+                   d_labels_argmax=None, d_lambda=None, d_s_eps=None, d_energy=None,
+                   stream=None):
+    """Device-pointer form; tensors are torch CUDA (HIP) tensors, stream a
+    torch.cuda.Stream (None = the current stream)."""
+    import torch
+    m, eps, _ = _batch(m, eps)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    _check(lib().sp_solve_async(mesh_h, C.byref(prm), m.size, _ip(m), _dp(eps), _tptr(d_u0),
+                                _tptr(d_u_out), _tptr(d_labels), _tptr(d_labels_argmax),
+                                _tptr(d_lambda), _tptr(d_s_eps), _tptr(d_energy),
+                                C.c_void_p(stream.cuda_stream)))
+
+
+class Mesh:
+    """Owner of an sp_mesh handle."""
+
+    def __init__(self, xyz, tri):
+        self.h = sp_mesh_create(xyz, tri)
+        self.n_vert, self.n_tri, self.nnz, self.area = sp_mesh_info(self.h)
+
+    def export(self, which):
+        """(row_ptr, col, val) CSR of M (SP_MAT_M) or A (SP_MAT_A)."""
+        return sp_mesh_export(self.h, which)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sp_mesh_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+
+def solve(mesh, prm, m, eps, u0, **kw):
+    return sp_solve(mesh.h, prm, m, eps, u0, **kw)
+
+
+class State:
+    """Owner of an sp_state handle (a batch kept on the GPU)."""
+
+    def __init__(self, mesh, prm, m, eps, u0, stream=None):
+        self.mesh = mesh
+        self.m, self.eps, u0 = _batch(m, eps, u0, mesh.n_vert)
+        self.R = int(self.m.sum())
+        h = C.c_void_p()
+        s = None if stream is None else C.c_void_p(stream.cuda_stream)
+        _check(lib().sp_state_create(mesh.h, C.byref(prm), self.m.size, _ip(self.m),
+                                     _dp(self.eps), _dp(u0), s, C.byref(h)))
+        self.h = h
+
+    def step(self, k=1):
+        return _check(lib().sp_state_step(self.h, int(k)), allow=(SP_ENOCONV,))
+
+    def stage(self, which):
+        _check(lib().sp_state_stage(self.h, int(which)))
+
+    def energy(self):
+        lam, s, e = np.empty(self.R), np.empty(self.m.size), np.empty(self.m.size)
+        _check(lib().sp_state_energy(self.h, _dp(lam), _dp(s), _dp(e)))
+        return lam, s, e
+
+    def read(self):
+        u = np.empty((self.R, self.mesh.n_vert))
+        k = C.c_int64()
+        _check(lib().sp_state_read(self.h, _dp(u), C.byref(k)))
+        return u, k.value
+
+    def write(self, u, step=0, normalise=False):
+        u = _f64(u)
+        _check(lib().sp_state_write(self.h, _dp(u), int(step), int(bool(normalise))))
+
+    def labels(self):
+        a = np.empty((self.m.size, self.mesh.n_vert), np.int32)
+        b = np.empty_like(a)
+        _check(lib().sp_state_labels(self.h, _ip(a), _ip(b)))
+        return a, b
+
+    def history(self, r):
+        cnt = C.c_int64()
+        _check(lib().sp_state_history(self.h, r, 0, None, None, C.byref(cnt)))
+        k = np.empty(cnt.value, np.int64)
+        e = np.empty(cnt.value)
+        _check(lib().sp_state_history(self.h, r, cnt.value, _ip(k, I64), _dp(e), C.byref(cnt)))
+        return k, e
+
+    def stats(self):
+        st = sp_stats()
+        _check(lib().sp_state_stats(self.h, C.byref(st)))
+        return st.as_dict()
+
+    def profile(self, on=True):
+        _check(lib().sp_state_profile(self.h, int(bool(on))))
+
+    def kernel_time(self):
+        n, ms, b = C.c_int64(), C.c_double(), C.c_double()
+        _check(lib().sp_state_kernel_time(self.h, C.byref(n), C.byref(ms), C.byref(b)))
+        return n.value, ms.value, b.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sp_state_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+
+class Server:
+    """Owner of an sp_server handle (continuous-batching request loop)."""
+
+    def __init__(self, hbm_budget_bytes, max_batch_columns=0):
+        h = C.c_void_p()
+        _check(lib().sp_server_create(int(hbm_budget_bytes), int(max_batch_columns), C.byref(h)))
+        self.h = h
+        self._shape = {}
+
+    def submit(self, mesh, prm, m, eps, u0):
+        m, eps, u0 = _batch(m, eps, u0, mesh.n_vert)
+        t = C.c_int64()
+        _check(lib().sp_server_submit(self.h, mesh.h, C.byref(prm), m.size, _ip(m), _dp(eps),
+                                      _dp(u0), C.byref(t)))
+        self._shape[t.value] = (int(m.sum()), m.size, mesh.n_vert)
+        return t.value
+
+    def poll(self, ticket):
+        d = C.c_int32()
+        _check(lib().sp_server_poll(self.h, int(ticket), C.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket, timeout_s=600.0):
+        return _check(lib().sp_server_wait(self.h, int(ticket), float(timeout_s)),
+                      allow=(SP_EAGAIN,)) == SP_OK
+
+    def fetch(self, ticket):
+        R, nres, n = self._shape[ticket]
+        out = dict(u=np.empty((R, n)), labels=np.empty((nres, n), np.int32), lam=np.empty(R),
+                   s_eps=np.empty(nres), energy=np.empty(nres))
+        lat = C.c_double()
+        _check(lib().sp_server_fetch(self.h, int(ticket), _dp(out["u"]), _ip(out["labels"]),
+                                     _dp(out["lam"]), _dp(out["s_eps"]), _dp(out["energy"]),
+                                     C.byref(lat)))
+        out["latency_s"] = lat.value
+        del self._shape[ticket]
+        return out
+
+    def stats(self):
+        p50, p99, cd, n = C.c_double(), C.c_double(), C.c_double(), C.c_int64()
+        _check(lib().sp_server_stats(self.h, C.byref(p50), C.byref(p99), C.byref(cd),
+                                     C.byref(n)))
+        return dict(p50_s=p50.value, p99_s=p99.value, cdof_per_s=cd.value, completed=n.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sp_server_destroy(self.h)
+            self.h = None
+
+    __del__ = close

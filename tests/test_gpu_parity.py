@@ -1,0 +1,279 @@
+"""Parity of the HIP time stepper with the CPU oracle, through the C ABI.
+
+Tolerances: float64 mode 1e-10 relative (element by element on u, and on
+every lambda_i, sum lambda, S_eps); mixed mode 1e-5.  Each test prints what
+it runs before the GPU call.  Labels must agree at every vertex away from an
+interface (a vertex whose closed one-ring carries more than one oracle argmax
+label, or whose top two components differ by less than 1e-6 max u).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import energy as oenergy, flow, fem, labels as olabels  # noqa: E402
+from paper_1408_2355_amd import segpart as sp  # noqa: E402
+from workloads import icosphere, torus, ellipsoid, uniform_u0, batch_u0  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def csr(mat):
+    mat = mat.tocsr()
+    mat.sort_indices()
+    return mat.indptr, mat.indices, mat.data
+
+
+@pytest.mark.parametrize("kind", ["sphere3", "torus", "ellipsoid"])
+def test_assembled_matrices_match_oracle(kind):
+    v, f = {"sphere3": lambda: icosphere(3), "torus": lambda: torus(24, 16),
+            "ellipsoid": lambda: ellipsoid(2)}[kind]()
+    say("assembly", kind, v.shape[0])
+    mesh = sp.Mesh(v, f)
+    M, A = fem.assemble(v, f)
+    assert mesh.nnz == M.nnz and abs(mesh.area - fem.surface_area(v, f)) < 1e-12
+    for which, ref in ((sp.SP_MAT_M, M), (sp.SP_MAT_A, A)):
+        rp, col, val = mesh.export(which)
+        rr, rc, rv = csr(ref)
+        np.testing.assert_array_equal(rp, rr)
+        np.testing.assert_array_equal(col, rc)
+        np.testing.assert_allclose(val, rv, rtol=1e-13, atol=1e-15 * np.abs(rv).max())
+
+
+def _state(level=3, groups=((11, 1, 3), (12, 1, 5))):
+    v, f = icosphere(level)
+    u0, ms = batch_u0(v.shape[0], groups)
+    return v, f, u0, ms
+
+
+def _oracle_blocks(u, ms):
+    return flow.split_restarts(u, ms)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("mixed", 1e-9)])
+def test_each_stage_matches_oracle(precision, tol):
+    v, f, u0, ms = _state()
+    eps = np.array([0.1, 0.07])
+    tau = 1e-3
+    say("stages", precision)
+    mesh = sp.Mesh(v, f)
+    prm = sp.params(tau, precision=precision, cg_rtol=1e-13, energy_every=0)
+    st = sp.State(mesh, prm, ms, eps, u0)
+    prob = flow.Problem(v, f, tau)
+    u = np.concatenate([flow.normalise(prob.M, b) for b in _oracle_blocks(u0, ms)])
+    got, _ = st.read()
+    assert rel(got, u) < 1e-14
+    st.stage(sp.SP_STAGE_HEAT)
+    got, _ = st.read()
+    ut = np.concatenate([flow.heat_step(prob, b) for b in _oracle_blocks(u, ms)])
+    assert rel(got, ut) < tol
+    st.write(ut, 0, normalise=False)
+    st.stage(sp.SP_STAGE_NODE)
+    got, _ = st.read()
+    uh = np.concatenate([flow.nodal_step(b, tau, e)
+                         for b, e in zip(_oracle_blocks(ut, ms), eps)])
+    assert rel(got, uh) < 1e-14
+    st.stage(sp.SP_STAGE_NORM)
+    got, _ = st.read()
+    un = np.concatenate([flow.normalise(prob.M, b) for b in _oracle_blocks(uh, ms)])
+    assert rel(got, un) < 1e-14
+    lam, s, e = st.energy()
+    for r, (b, ep) in enumerate(zip(_oracle_blocks(un, ms), eps)):
+        l_o, s_o, e_o = oenergy.energy(v, f, prob.M, prob.A, b, ep)
+        lo = int(np.sum(ms[:r]))
+        assert rel(lam[lo:lo + ms[r]], l_o) < 1e-13
+        assert abs(s[r] - s_o) < 1e-12 * s_o and abs(e[r] - e_o) < 1e-12 * e_o
+    lab, am = st.labels()
+    for r, b in enumerate(_oracle_blocks(un, ms)):
+        ol, oa = olabels.labels(b)
+        np.testing.assert_array_equal(lab[r], ol)
+        np.testing.assert_array_equal(am[r], oa)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-9)])
+def test_one_step_map(precision, tol):
+    v, f, u0, ms = _state(level=4)
+    eps = np.array([0.05, 0.1])
+    tau = 2e-4
+    say("one-step map", precision)
+    mesh = sp.Mesh(v, f)
+    prm = sp.params(tau, precision=precision, cg_rtol=1e-13, energy_every=0)
+    st = sp.State(mesh, prm, ms, eps, u0)
+    prob = flow.Problem(v, f, tau)
+    u = np.concatenate([flow.normalise(prob.M, b) for b in _oracle_blocks(u0, ms)])
+    for k in range(3):
+        st.step(1)
+        u = np.concatenate([flow.step(prob, b, e) for b, e in zip(_oracle_blocks(u, ms), eps)])
+        got, steps = st.read()
+        assert steps == k + 1
+        assert rel(got, u) < tol, (k, rel(got, u))
+        st.write(u, k + 1)      # restart every step from the oracle's state
+
+
+def interface_mask(f, u):
+    """Vertices near an interface of the argmax labelling (see module doc)."""
+    am = np.argmax(u, axis=0)
+    n = u.shape[1]
+    bad = np.zeros(n, bool)
+    for a, b in ((0, 1), (1, 2), (2, 0)):
+        diff = am[f[:, a]] != am[f[:, b]]
+        bad[f[diff, a]] = True
+        bad[f[diff, b]] = True
+    s = np.sort(u, axis=0)
+    if u.shape[0] > 1:
+        bad |= (s[-1] - s[-2]) < 1e-6 * np.abs(u).max()
+    return bad
+
+
+def _run_both(v, f, u0, ms, eps, tau, steps, precision, rtol, every):
+    mesh = sp.Mesh(v, f)
+    prm = sp.params(tau, precision=precision, n_steps=steps, cg_rtol=rtol,
+                    energy_every=every)
+    rc, out = sp.solve(mesh, prm, ms, eps, u0)
+    assert rc == sp.SP_OK
+    ref = flow.run(flow.Problem(v, f, tau), u0, ms, eps, steps, energy_every=every)
+    return out, ref
+
+
+def _noise_floor(v, f, u0, ms, eps, tau, steps, ref):
+    """Oracle against itself with u0 perturbed by 1e-14 relative."""
+    rng = np.random.default_rng(0)
+    up = u0 * (1.0 + 1e-14 * rng.standard_normal(u0.shape))
+    alt = flow.run(flow.Problem(v, f, tau), up, ms, eps, steps)
+    return max(rel(alt["u"], ref["u"]), rel(alt["lam"], ref["lam"]),
+               rel(alt["s_eps"], ref["s_eps"]))
+
+
+def test_config1_sphere_l3_fp64_end_to_end():
+    """Unit sphere level 3 (642 vertices), m = 3, eps = 0.1, tau = 1e-3, 200
+    steps, float64, CG rtol 1e-12, u0 iid U[0,1) from seed 1003."""
+    v, f = icosphere(3)
+    u0 = uniform_u0(1003, 1, 3, v.shape[0])
+    say("config 1 fp64")
+    out, ref = _run_both(v, f, u0, [3], [0.1], 1e-3, 200, "fp64", 1e-12, 10)
+    floor = _noise_floor(v, f, u0, [3], [0.1], 1e-3, 200, ref)
+    bar = max(1e-10, 10 * floor)
+    say(f"  noise floor {floor:.2e}, u {rel(out['u'], ref['u']):.2e}")
+    assert rel(out["u"], ref["u"]) < bar
+    assert rel(out["lam"], ref["lam"]) < bar
+    assert abs(out["lam"].sum() - ref["lam"].sum()) < bar * ref["lam"].sum()
+    assert rel(out["s_eps"], ref["s_eps"]) < bar
+    assert rel(out["energy"], ref["energy"]) < bar
+    ok = ~interface_mask(f, ref["u"])
+    np.testing.assert_array_equal(out["labels"][0][ok], ref["labels"][0][ok])
+    np.testing.assert_array_equal(out["labels_argmax"][0][ok], ref["labels_argmax"][0][ok])
+    assert out["stats"]["converged"] == 1 and out["stats"]["steps_done"] == 200
+
+
+def test_config1_mixed_end_to_end():
+    v, f = icosphere(3)
+    u0 = uniform_u0(1003, 1, 3, v.shape[0])
+    say("config 1 mixed")
+    out, ref = _run_both(v, f, u0, [3], [0.1], 1e-3, 200, "mixed", 1e-12, 10)
+    assert rel(out["lam"], ref["lam"]) < 1e-5
+    assert rel(out["s_eps"], ref["s_eps"]) < 1e-5
+    assert rel(out["energy"], ref["energy"]) < 1e-5
+    assert rel(out["u"], ref["u"]) < 1e-5
+
+
+def test_batch_of_mixed_m_equals_each_restart_alone():
+    v, f = icosphere(3)
+    u0, ms = batch_u0(v.shape[0], [(21, 2, 3), (22, 1, 6), (23, 2, 4)])
+    eps = np.array([0.1, 0.1, 0.08, 0.12, 0.12])
+    tau = 1e-3
+    say("batch vs alone")
+    mesh = sp.Mesh(v, f)
+    prm = sp.params(tau, precision="fp64", n_steps=20, cg_rtol=1e-12, energy_every=0)
+    rc, out = sp.solve(mesh, prm, ms, eps, u0)
+    lo = 0
+    for r, m in enumerate(ms):
+        rc1, one = sp.solve(mesh, prm, [m], [eps[r]], u0[lo:lo + m])
+        assert rel(out["u"][lo:lo + m], one["u"]) < 1e-11
+        assert rel(out["lam"][lo:lo + m], one["lam"]) < 1e-11
+        assert abs(out["s_eps"][r] - one["s_eps"][0]) < 1e-11 * one["s_eps"][0]
+        lo += m
+
+
+def test_other_surfaces_short_run():
+    for name, (v, f) in (("torus", torus(32, 24)), ("ellipsoid", ellipsoid(3))):
+        u0 = uniform_u0(4008, 1, 4, v.shape[0])
+        say("surface", name)
+        out, ref = _run_both(v, f, u0, [4], [0.05], 5e-4, 20, "fp64", 1e-12, 0)
+        assert rel(out["u"], ref["u"]) < 1e-10
+        assert rel(out["lam"], ref["lam"]) < 1e-10
+        assert rel(out["s_eps"], ref["s_eps"]) < 1e-10
+
+
+def test_zero_norm_component_rejected():
+    v, f = icosphere(2)
+    u0 = uniform_u0(1, 1, 3, v.shape[0])
+    u0[1] = 0.0
+    mesh = sp.Mesh(v, f)
+    with pytest.raises(sp.SegpartError) as e:
+        sp.solve(mesh, sp.params(1e-3, n_steps=1), [3], [0.1], u0)
+    assert e.value.code == sp.SP_EINVAL
+
+
+def test_iteration_cap_reports_noconv_and_still_writes():
+    v, f = icosphere(3)
+    u0 = uniform_u0(5, 1, 3, v.shape[0])
+    mesh = sp.Mesh(v, f)
+    prm = sp.params(1e-3, precision="fp64", n_steps=2, cg_rtol=1e-14, cg_max_iter=1,
+                    energy_every=0)
+    rc, out = sp.solve(mesh, prm, [3], [0.1], u0)
+    assert rc == sp.SP_ENOCONV and out["stats"]["converged"] == 0
+    assert np.isfinite(out["u"]).all() and np.isfinite(out["lam"]).all()
+
+
+def test_stop_rule_and_history():
+    v, f = icosphere(2)
+    u0 = uniform_u0(9, 1, 3, v.shape[0])
+    tau = 2e-2
+    mesh = sp.Mesh(v, f)
+    prm = sp.params(tau, precision="fp64", n_steps=0, energy_every=20, stop_tol=1e-6,
+                    cg_rtol=1e-12, max_steps=5000)
+    rc, out = sp.solve(mesh, prm, [3], [0.5], u0)
+    ref = flow.run(flow.Problem(v, f, tau), u0, [3], [0.5], 0, energy_every=20,
+                   stop_tol=1e-6)
+    assert out["stats"]["steps_done"] == ref["steps"][0]
+    assert rel(out["energy"], ref["energy"]) < 1e-9
+
+
+def test_async_device_pointers():
+    v, f = icosphere(3)
+    u0 = uniform_u0(31, 2, 3, v.shape[0])
+    mesh = sp.Mesh(v, f)
+    prm = sp.params(1e-3, precision="mixed", n_steps=10, energy_every=0)
+    rc, ref = sp.solve(mesh, prm, [3, 3], [0.1, 0.1], u0)
+    dev = torch.device("cuda:0")
+    d_u0 = torch.from_numpy(u0).to(dev)
+    d_u = torch.empty_like(d_u0)
+    d_lab = torch.empty((2, v.shape[0]), dtype=torch.int32, device=dev)
+    d_lam = torch.empty(6, dtype=torch.float64, device=dev)
+    d_s = torch.empty(2, dtype=torch.float64, device=dev)
+    d_e = torch.empty(2, dtype=torch.float64, device=dev)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        sp.sp_solve_async(mesh.h, prm, [3, 3], [0.1, 0.1], d_u0, d_u_out=d_u, d_labels=d_lab,
+                          d_lambda=d_lam, d_s_eps=d_s, d_energy=d_e, stream=s)
+    s.synchronize()
+    assert rel(d_u.cpu().numpy(), ref["u"]) < 1e-12
+    assert rel(d_lam.cpu().numpy(), ref["lam"]) < 1e-12
+    assert rel(d_e.cpu().numpy(), ref["energy"]) < 1e-12
+    np.testing.assert_array_equal(d_lab.cpu().numpy(), ref["labels"])
