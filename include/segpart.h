@@ -206,14 +206,18 @@ int sp_state_labels(sp_state* st, int32_t* labels, int32_t* labels_argmax);
 int sp_state_history(sp_state* st, int32_t r, int64_t cap, int64_t* steps, double* energies,
                      int64_t* count);
 int sp_state_stats(sp_state* st, sp_stats* stats);
-/* Kernel timing with HIP events on the state's stream, for the dominant
- * kernel class of the time step (the CG matrix product).  enable != 0 starts
- * recording (and clears the totals). */
+/* Kernel timing with HIP events recorded on the state's stream around the
+ * three large kernels of every CG iteration.  enable != 0 starts recording
+ * (and clears the totals); enable == 0 stops. */
 int sp_state_profile(sp_state* st, int32_t enable);
-/* Launch count and summed duration (ms) of the CG matrix-product kernel since
- * profiling was enabled, plus its algorithmic bytes per launch (float32
- * vectors in SP_MIXED, float64 in SP_FP64). */
-int sp_state_kernel_time(sp_state* st, int64_t* launches, double* total_ms,
+enum { SP_KERNEL_MATVEC = 0, SP_KERNEL_UPDATE = 1, SP_KERNEL_DIRECTION = 2 };
+/* For kernel class `which` -- SP_KERNEL_MATVEC (q = (M + tau A) p and the
+ * per-column p.q), SP_KERNEL_UPDATE (x += alpha p, r -= alpha q, z = D r and
+ * the per-column r.z, r.r) or SP_KERNEL_DIRECTION (p = z + beta p) -- the
+ * launch count and summed duration (ms) since profiling was enabled, and the
+ * algorithmic (minimum) HBM bytes of one launch over the live columns:
+ * float32 vectors in SP_MIXED, float64 in SP_FP64. */
+int sp_state_kernel_time(sp_state* st, int32_t which, int64_t* launches, double* total_ms,
                          double* bytes_per_launch);
 void sp_state_destroy(sp_state* st);
 

@@ -327,11 +327,11 @@ int sp_state_profile(sp_state* st, int32_t enable) {
   });
 }
 
-int sp_state_kernel_time(sp_state* st, int64_t* launches, double* total_ms,
+int sp_state_kernel_time(sp_state* st, int32_t which, int64_t* launches, double* total_ms,
                          double* bytes_per_launch) {
   return guard([&] {
     SP_REQUIRE(st && st->solver, SP_EINVAL, "NULL state");
-    st->solver->kernel_time(launches, total_ms, bytes_per_launch);
+    st->solver->kernel_time(which, launches, total_ms, bytes_per_launch);
     return SP_OK;
   });
 }

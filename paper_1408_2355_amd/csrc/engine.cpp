@@ -13,6 +13,7 @@
 #include "engine.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 
@@ -194,10 +195,8 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
 
 Solver::~Solver() {
   if (!detached_ || own_stream_) (void)hipStreamSynchronize(s_);
-  for (auto& e : ev_) {
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
-  }
+  for (auto& e : ev_)
+    for (auto x : e) (void)hipEventDestroy(x);
   if (h_poll_) (void)hipHostFree(h_poll_);
   if (own_stream_) (void)hipStreamDestroy(s_);
 }
@@ -350,22 +349,8 @@ void Solver::heat_fp64() {
   k::red_init_fp64(args_, s_);
   int last = 0;
   for (int it = 0; it < prm_.cg_max_iter; ++it) {
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (prof_) {
-      if (ev_used_ == ev_.size()) {
-        if (ev_.size() >= 8192) prof_flush();
-        if (ev_used_ == ev_.size()) {
-          hipEvent_t a, b;
-          SP_HIP(hipEventCreate(&a));
-          SP_HIP(hipEventCreate(&b));
-          ev_.push_back({a, b});
-        }
-      }
-      e0 = ev_[ev_used_].first;
-      e1 = ev_[ev_used_].second;
-      ++ev_used_;
-    }
-    k::cg_iter<double>(args_, it, u_.p, r64_.p, p64_.p, q64_.p, km_->K64.p, km_->dinv64.p, s_, e0, e1);
+    k::cg_iter<double>(args_, it, u_.p, r64_.p, p64_.p, q64_.p, km_->K64.p, km_->dinv64.p, s_,
+                       prof_events());
     last = it + 1;
     if (prm_.check_every > 0 && last % prm_.check_every == 0 && last < prm_.cg_max_iter)
       if (poll(ring_.p + last % kRing) == 0) break;
@@ -382,23 +367,8 @@ void Solver::heat_mixed() {
     k::inner_init(args_, o, r64_.p, d32_.p, r32_.p, p32_.p, s_);
     k::red_inner_init(args_, o, s_);
     for (int it = 0; it < prm_.cg_max_iter; ++it) {
-      hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (prof_) {
-        if (ev_used_ == ev_.size()) {
-          if (ev_.size() >= 8192) prof_flush();
-          if (ev_used_ == ev_.size()) {
-            hipEvent_t a, b;
-            SP_HIP(hipEventCreate(&a));
-            SP_HIP(hipEventCreate(&b));
-            ev_.push_back({a, b});
-          }
-        }
-        e0 = ev_[ev_used_].first;
-        e1 = ev_[ev_used_].second;
-        ++ev_used_;
-      }
       k::cg_iter<float>(args_, it, d32_.p, r32_.p, p32_.p, q32_.p, km_->K32.p, km_->dinv32.p, s_,
-                        e0, e1);
+                        prof_events());
       const int last = it + 1;
       if (prm_.check_every > 0 && last % prm_.check_every == 0 && last < prm_.cg_max_iter)
         if (poll(ring_.p + last % kRing) == 0) break;
@@ -534,14 +504,29 @@ sp_stats Solver::stats() {
 
 bool Solver::converged() { return stats().converged != 0; }
 
+const hipEvent_t* Solver::prof_events() {
+  if (!prof_) return nullptr;
+  if (ev_used_ == ev_.size()) {
+    if (ev_.size() >= 4096) prof_flush();
+    if (ev_used_ == ev_.size()) {
+      std::array<hipEvent_t, 6> e{};
+      for (auto& x : e) SP_HIP(hipEventCreate(&x));
+      ev_.push_back(e);
+    }
+  }
+  return ev_[ev_used_++].data();
+}
+
 void Solver::prof_flush() {
   if (ev_used_ == 0) return;
   SP_HIP(hipStreamSynchronize(s_));
   for (size_t i = 0; i < ev_used_; ++i) {
-    float ms = 0.f;
-    SP_HIP(hipEventElapsedTime(&ms, ev_[i].first, ev_[i].second));
-    prof_ms_ += ms;
-    ++prof_launches_;
+    for (int k = 0; k < 3; ++k) {
+      float ms = 0.f;
+      SP_HIP(hipEventElapsedTime(&ms, ev_[i][2 * k], ev_[i][2 * k + 1]));
+      prof_ms_[k] += ms;
+      ++prof_launches_[k];
+    }
   }
   ev_used_ = 0;
 }
@@ -549,21 +534,30 @@ void Solver::prof_flush() {
 void Solver::profile(bool on) {
   prof_flush();
   prof_ = on;
-  prof_launches_ = 0;
-  prof_ms_ = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    prof_launches_[k] = 0;
+    prof_ms_[k] = 0.0;
+  }
 }
 
-void Solver::kernel_time(int64_t* launches, double* ms, double* bytes_per_launch) {
+void Solver::kernel_time(int which, int64_t* launches, double* ms, double* bytes_per_launch) {
+  SP_REQUIRE(which >= 0 && which < 3, SP_EINVAL, "kernel class must be 0, 1 or 2");
   prof_flush();
-  if (launches) *launches = prof_launches_;
-  if (ms) *ms = prof_ms_;
+  if (launches) *launches = prof_launches_[which];
+  if (ms) *ms = prof_ms_[which];
   if (bytes_per_launch) {
-    // minimum traffic of one q = K p launch over all live columns: read p and
-    // write q once per element, plus the matrix (column indices and values)
+    // minimum HBM traffic of one launch over all live columns:
+    //   0  q = K p            read p, write q (+ the matrix: indices, values)
+    //   1  x += a p, r -= a q read x, r, p, q, write x, r (+ the diagonal)
+    //   2  p = D r + b p      read r, p, write p (+ the diagonal)
     int live = 0;
     for (int c = 0; c < rp_; ++c) live += h_live_[c];
     const double s = prm_.precision == SP_FP64 ? 8.0 : 4.0;
-    *bytes_per_launch = double(mesh_->n) * (double(live) * 2.0 * s + double(mesh_->W) * (4.0 + s));
+    const double n = double(mesh_->n), L = double(live);
+    const double per[3] = {2.0, 6.0, 3.0};
+    double b = n * L * per[which] * s;
+    b += which == 0 ? n * double(mesh_->W) * (4.0 + s) : n * s;
+    *bytes_per_launch = b;
   }
 }
 

@@ -3,6 +3,7 @@
 // energies and labels.
 #pragma once
 
+#include <array>
 #include <utility>
 #include <vector>
 
@@ -66,9 +67,10 @@ class Solver {
   sp_stats stats();
   bool converged();
 
-  // event timing of the CG matrix-product kernel
+  // event timing of the three large CG kernels (0 matrix product, 1 x/r
+  // update, 2 p update) on the solver's stream
   void profile(bool on);
-  void kernel_time(int64_t* launches, double* ms, double* bytes_per_launch);
+  void kernel_time(int which, int64_t* launches, double* ms, double* bytes_per_launch);
 
   const double* d_lam() const { return lam_.p; }
   const double* d_seps() const { return seps_.p; }
@@ -134,11 +136,12 @@ class Solver {
   std::vector<std::vector<std::pair<int64_t, double>>> hist_;
 
   bool prof_ = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_;
+  std::vector<std::array<hipEvent_t, 6>> ev_;
   size_t ev_used_ = 0;
-  int64_t prof_launches_ = 0;
-  double prof_ms_ = 0.0;
+  int64_t prof_launches_[3] = {0, 0, 0};
+  double prof_ms_[3] = {0.0, 0.0, 0.0};
   void prof_flush();
+  const hipEvent_t* prof_events();
 };
 
 // Solvers whose work was enqueued asynchronously are freed later, from an

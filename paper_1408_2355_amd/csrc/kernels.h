@@ -64,10 +64,12 @@ void flag_nonconv(const StepArgs& a, const int* counter, hipStream_t s);
 // float64 CG (plain form): x is the state u itself.
 void init_fp64(const StepArgs& a, const double* u, double* r, double* p, hipStream_t s);
 void red_init_fp64(const StepArgs& a, hipStream_t s);
-// one CG iteration on type T vectors (float64 plain or float32 inner)
+// one CG iteration on type T vectors (float64 plain or float32 inner); ev,
+// when given, holds 6 events recorded around the matrix product, the x/r
+// update and the p update (before/after each)
 template <typename T>
 void cg_iter(const StepArgs& a, int it, T* x, T* r, T* p, T* q, const T* K, const T* dinv,
-             hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+             hipStream_t s, const hipEvent_t* ev);
 // mixed precision refinement
 void init_outer(const StepArgs& a, const double* u, double* r64, hipStream_t s);
 void red_outer_init(const StepArgs& a, hipStream_t s);

@@ -927,24 +927,28 @@ void red_init_fp64(const StepArgs& a, hipStream_t s) {
 
 template <typename T>
 void cg_iter(const StepArgs& a, int it, T* x, T* r, T* p, T* q, const T* K, const T* dinv,
-             hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+             hipStream_t s, const hipEvent_t* ev) {
   const int slot = it % kRing, next = (it + 1) % kRing;
-  if (ev0) SP_HIP(hipEventRecord(ev0, s));
+  if (ev) SP_HIP(hipEventRecord(ev[0], s));
   hipLaunchKernelGGL(k_cg_spmm<T>, dim3(a.t.nblk), dim3(kBlock), 0, s, a, slot, K, (const T*)p, q);
-  if (ev1) SP_HIP(hipEventRecord(ev1, s));
+  if (ev) SP_HIP(hipEventRecord(ev[1], s));
   hipLaunchKernelGGL(k_red_alpha, dim3(colblocks(a.t)), dim3(kBlock), 0, s, a, slot, next);
+  if (ev) SP_HIP(hipEventRecord(ev[2], s));
   hipLaunchKernelGGL(k_cg_update<T>, dim3(a.t.nblk), dim3(kBlock), 0, s, a, slot, x, r, (const T*)p,
                      (const T*)q, dinv);
+  if (ev) SP_HIP(hipEventRecord(ev[3], s));
   hipLaunchKernelGGL(k_red_beta, dim3(colblocks(a.t)), dim3(kBlock), 0, s, a, slot, next);
+  if (ev) SP_HIP(hipEventRecord(ev[4], s));
   hipLaunchKernelGGL(k_cg_update_p<T>, dim3(a.t.nblk), dim3(kBlock), 0, s, a, next, p, (const T*)r,
                      dinv);
+  if (ev) SP_HIP(hipEventRecord(ev[5], s));
   SP_LAUNCH_CHECK();
 }
 
 template void cg_iter<double>(const StepArgs&, int, double*, double*, double*, double*,
-                              const double*, const double*, hipStream_t, hipEvent_t, hipEvent_t);
+                              const double*, const double*, hipStream_t, const hipEvent_t*);
 template void cg_iter<float>(const StepArgs&, int, float*, float*, float*, float*, const float*,
-                             const float*, hipStream_t, hipEvent_t, hipEvent_t);
+                             const float*, hipStream_t, const hipEvent_t*);
 
 void init_outer(const StepArgs& a, const double* u, double* r64, hipStream_t s) {
   hipLaunchKernelGGL(k_init_outer, dim3(a.t.nblk), dim3(kBlock), 0, s, a, u, r64);

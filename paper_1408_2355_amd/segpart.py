@@ -22,6 +22,7 @@ SP_OK, SP_EINVAL, SP_EMESH, SP_ENOMEM, SP_EDEVICE, SP_ENOCONV, SP_EAGAIN, SP_ENO
 SP_FP64, SP_MIXED = 0, 1
 SP_MAT_M, SP_MAT_A = 0, 1
 SP_STAGE_HEAT, SP_STAGE_NODE, SP_STAGE_NORM = 1, 2, 3
+SP_KERNEL_MATVEC, SP_KERNEL_UPDATE, SP_KERNEL_DIRECTION = 0, 1, 2
 
 _NAMES = {SP_EINVAL: "SP_EINVAL", SP_EMESH: "SP_EMESH", SP_ENOMEM: "SP_ENOMEM",
           SP_EDEVICE: "SP_EDEVICE", SP_ENOCONV: "SP_ENOCONV", SP_EAGAIN: "SP_EAGAIN",
@@ -81,7 +82,7 @@ _SIGS = {
     "sp_state_history": (C.c_int, [P, C.c_int32, C.c_int64, I64, D, I64]),
     "sp_state_stats": (C.c_int, [P, C.POINTER(sp_stats)]),
     "sp_state_profile": (C.c_int, [P, C.c_int32]),
-    "sp_state_kernel_time": (C.c_int, [P, I64, D, D]),
+    "sp_state_kernel_time": (C.c_int, [P, C.c_int32, I64, D, D]),
     "sp_state_destroy": (None, [P]),
     "sp_server_create": (C.c_int, [C.c_int64, C.c_int32, PP]),
     "sp_server_submit": (C.c_int, [P, P, C.POINTER(sp_params), C.c_int32, I32, D, D, I64]),
@@ -304,9 +305,11 @@ class State:
     def profile(self, on=True):
         _check(lib().sp_state_profile(self.h, int(bool(on))))
 
-    def kernel_time(self):
+    def kernel_time(self, which=SP_KERNEL_MATVEC):
+        """(launches, total ms, algorithmic bytes per launch) of a kernel class."""
         n, ms, b = C.c_int64(), C.c_double(), C.c_double()
-        _check(lib().sp_state_kernel_time(self.h, C.byref(n), C.byref(ms), C.byref(b)))
+        _check(lib().sp_state_kernel_time(self.h, int(which), C.byref(n), C.byref(ms),
+                                          C.byref(b)))
         return n.value, ms.value, b.value
 
     def close(self):
