@@ -531,6 +531,11 @@ void Solver::prof_flush() {
   ev_used_ = 0;
 }
 
+void Solver::read_stat(long long* st) {
+  SP_HIP(hipMemcpyAsync(st, stat_.p, 4 * sizeof(long long), hipMemcpyDeviceToHost, s_));
+  SP_HIP(hipStreamSynchronize(s_));
+}
+
 void Solver::profile(bool on) {
   prof_flush();
   prof_ = on;
@@ -538,6 +543,7 @@ void Solver::profile(bool on) {
     prof_launches_[k] = 0;
     prof_ms_[k] = 0.0;
   }
+  read_stat(prof_stat0_);
 }
 
 void Solver::kernel_time(int which, int64_t* launches, double* ms, double* bytes_per_launch) {
@@ -546,18 +552,22 @@ void Solver::kernel_time(int which, int64_t* launches, double* ms, double* bytes
   if (launches) *launches = prof_launches_[which];
   if (ms) *ms = prof_ms_[which];
   if (bytes_per_launch) {
-    // minimum HBM traffic of one launch over all live columns:
-    //   0  q = K p            read p, write q (+ the matrix: indices, values)
-    //   1  x += a p, r -= a q read x, r, p, q, write x, r (+ the diagonal)
-    //   2  p = D r + b p      read r, p, write p (+ the diagonal)
-    int live = 0;
-    for (int c = 0; c < rp_; ++c) live += h_live_[c];
+    // Minimum HBM traffic, summed over the profiled launches and divided by
+    // their count.  Per column that is still iterating:
+    //   0  q = K p            read p, write q; + the matrix (indices, values)
+    //   1  x += a p, r -= a q read x, r, p, q, write x, r; + the diagonal
+    //   2  p = D r + b p      read r, p, write p; + the diagonal
+    // Launches after convergence exit at once and move no data.
+    long long st[4];
+    read_stat(st);
+    const double work_iters = double(st[0] - prof_stat0_[0]);
+    const double col_iters = double(st[3] - prof_stat0_[3]);
     const double s = prm_.precision == SP_FP64 ? 8.0 : 4.0;
-    const double n = double(mesh_->n), L = double(live);
+    const double n = double(mesh_->n);
     const double per[3] = {2.0, 6.0, 3.0};
-    double b = n * L * per[which] * s;
-    b += which == 0 ? n * double(mesh_->W) * (4.0 + s) : n * s;
-    *bytes_per_launch = b;
+    double b = n * col_iters * per[which] * s;
+    b += work_iters * (which == 0 ? n * double(mesh_->W) * (4.0 + s) : n * s);
+    *bytes_per_launch = prof_launches_[which] ? b / double(prof_launches_[which]) : 0.0;
   }
 }
 

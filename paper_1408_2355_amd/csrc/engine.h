@@ -140,8 +140,10 @@ class Solver {
   size_t ev_used_ = 0;
   int64_t prof_launches_[3] = {0, 0, 0};
   double prof_ms_[3] = {0.0, 0.0, 0.0};
+  long long prof_stat0_[4] = {0, 0, 0, 0};
   void prof_flush();
   const hipEvent_t* prof_events();
+  void read_stat(long long* st);
 };
 
 // Solvers whose work was enqueued asynchronously are freed later, from an

@@ -56,7 +56,8 @@ struct StepArgs {
   double* part;        // [3][nchunk][rp] partial sums
   int* ring;           // [kRing] inner active counts
   int* oring;          // [kRing] outer active counts
-  long long* stat;     // [0] CG iterations with work, [1] outer sweeps, [2] cap hit
+  long long* stat;     // [0] CG iterations with work, [1] outer sweeps, [2] cap hit,
+                       // [3] active columns summed over CG iterations
 };
 
 namespace k {

@@ -275,6 +275,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmm(StepArgs a, int slot, const 
 __global__ void k_red_alpha(StepArgs a, int slot, int next) {
   if (blockIdx.x == 0 && threadIdx.x == 0) a.ring[next] = 0;
   if (a.ring[slot] == 0) return;
+  // columns this iteration works on, summed over iterations (traffic model)
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.stat[3] += a.ring[slot];
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= a.t.rp) return;
   double al = 0.0;
