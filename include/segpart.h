@@ -122,12 +122,15 @@ typedef struct {
   int32_t check_every;  /* CG iterations between host-side convergence polls; 0 = no
                            polling (cg_max_iter device iterations are enqueued and the
                            kernels exit at once after convergence)                  */
-  int32_t reserved;
+  int32_t extrapolate;  /* SP_MIXED only: 1 = start each heat solve from u plus the
+                           previous step's increment (u~ - u) instead of from u; the
+                           solution is the same to cg_rtol, only the start differs.
+                           Ignored in SP_FP64 (which always starts from u)          */
 } sp_params;
 
 /* Fill *p with defaults for time step tau: n_steps 100, stop_tol 1e-6,
  * max_steps 10^6, energy_every = round(0.1 / tau), SP_MIXED, cg_rtol 1e-10,
- * cg_max_iter 500, inner_rtol 1e-5, max_outer 8, check_every 8. */
+ * cg_max_iter 500, inner_rtol 1e-5, max_outer 8, check_every 8, extrapolate 1. */
 void sp_params_default(sp_params* p, double tau);
 
 typedef struct {

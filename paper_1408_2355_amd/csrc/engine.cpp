@@ -40,6 +40,8 @@ void validate_params(const sp_params& p) {
              "params: cg_rtol must be in (0, 1)");
   SP_REQUIRE(p.cg_max_iter >= 1, SP_EINVAL, "params: cg_max_iter must be >= 1");
   SP_REQUIRE(p.check_every >= 0, SP_EINVAL, "params: check_every must be >= 0");
+  SP_REQUIRE(p.extrapolate == 0 || p.extrapolate == 1, SP_EINVAL,
+             "params: extrapolate must be 0 or 1");
   if (p.precision == SP_MIXED) {
     SP_REQUIRE(std::isfinite(p.inner_rtol) && p.inner_rtol > 0 && p.inner_rtol < 1, SP_EINVAL,
                "params: inner_rtol must be in (0, 1)");
@@ -81,7 +83,11 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     const int n = int(mesh_->n);
     const size_t nv = size_t(n) * rp_;
     Tile t = make_tile(n, rp_, 64, kTargetBlocks);
-    tt_ = make_tile(int(mesh_->nt), nres_p_, 256, kTargetBlocks);
+    sp_.nt = int(mesh_->nt);
+    sp_.tchunk = std::max(256, int((mesh_->nt + 1023) / 1024 + 3) / 4 * 4);
+    sp_.nchunk = int((mesh_->nt + sp_.tchunk - 1) / sp_.tchunk);
+    sp_.nres_p = nres_p_;
+    seps_tiles_.alloc(nres_p_);
     u_.alloc(nv);
     r64_.alloc(nv);
     if (prm_.precision == SP_FP64) {
@@ -92,9 +98,10 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
       r32_.alloc(nv);
       p32_.alloc(nv);
       q32_.alloc(nv);
+      if (prm_.extrapolate) dprev_.alloc(nv);
     }
     part_.alloc(3 * size_t(t.nchunk) * rp_);
-    part_s_.alloc(size_t(tt_.nchunk) * nres_p_);
+    part_s_.alloc(size_t(sp_.nchunk) * nres_p_);
     colf_.alloc(size_t(CF_N) * rp_ + nres_p_);
     coli_.alloc(size_t(CI_N) * rp_ + 3 * size_t(nres_p_));
     ring_.alloc(2 * kRing);
@@ -220,6 +227,12 @@ void Solver::push_tables() {
                         nres_p_ * sizeof(int), hipMemcpyHostToDevice, s_));
   SP_HIP(hipMemcpyAsync(const_cast<double*>(args_.ct.res_ieps2), h_res_ieps2_.data(),
                         nres_p_ * sizeof(double), hipMemcpyHostToDevice, s_));
+  std::vector<int4> tiles = k::seps_tiles(h_res_lo_, h_res_len_, nres);
+  sp_.ntile = int(tiles.size());
+  sp_.tiles = seps_tiles_.p;
+  if (!tiles.empty())
+    SP_HIP(hipMemcpyAsync(seps_tiles_.p, tiles.data(), tiles.size() * sizeof(int4),
+                          hipMemcpyHostToDevice, s_));
   // the host vectors may change right after: wait for the copies
   SP_HIP(hipStreamSynchronize(s_));
 }
@@ -266,6 +279,7 @@ void Solver::sync() { SP_HIP(hipStreamSynchronize(s_)); }
 
 void Solver::upload_host(const double* u0, bool normalise) {
   SP_REQUIRE(u0 != nullptr, SP_EINVAL, "NULL u0");
+  have_dprev_ = false;
   const size_t cnt = size_t(R_) * mesh_->n;
   for (size_t i = 0; i < cnt; ++i)
     SP_REQUIRE(std::isfinite(u0[i]), SP_EINVAL, "u0 holds a non-finite value");
@@ -280,6 +294,7 @@ void Solver::upload_host(const double* u0, bool normalise) {
 
 void Solver::upload_device(const double* d_u0, bool normalise, bool check_norms) {
   SP_REQUIRE(d_u0 != nullptr, SP_EINVAL, "NULL u0");
+  have_dprev_ = false;
   k::pack(args_.t, 0, R_, d_u0, mesh_->perm_d.p, u_.p, s_);
   if (normalise) {
     if (check_norms) {
@@ -308,6 +323,7 @@ void Solver::normalise_columns() {
 
 void Solver::pack_range(int c_lo, int Rq, const double* d_src) {
   SP_REQUIRE(c_lo >= 0 && Rq >= 0 && c_lo + Rq <= rp_, SP_EINVAL, "column range");
+  have_dprev_ = false;  // the new columns have no previous increment
   k::pack(args_.t, c_lo, Rq, d_src, mesh_->perm_d.p, u_.p, s_);
 }
 
@@ -359,8 +375,18 @@ void Solver::heat_fp64() {
 }
 
 void Solver::heat_mixed() {
+  const bool extrap = prm_.extrapolate != 0;
   k::fill_i32(ring_.p, 0, ring_.n, s_);
   k::init_outer(args_, u_.p, r64_.p, s_);
+  if (extrap) {
+    // start from u + (previous step's increment); the refinement sweeps then
+    // accumulate this step's increment in the same buffer
+    if (have_dprev_)
+      k::apply_guess(args_, u_.p, r64_.p, dprev_.p, s_);
+    else
+      k::fill_f32(dprev_.p, 0.0f, dprev_.n, s_);
+    have_dprev_ = true;
+  }
   k::red_outer_init(args_, s_);
   int olast = 0;
   for (int o = 0; o < prm_.max_outer; ++o) {
@@ -373,7 +399,7 @@ void Solver::heat_mixed() {
       if (prm_.check_every > 0 && last % prm_.check_every == 0 && last < prm_.cg_max_iter)
         if (poll(ring_.p + last % kRing) == 0) break;
     }
-    k::outer_update(args_, o, u_.p, r64_.p, d32_.p, s_);
+    k::outer_update(args_, o, u_.p, r64_.p, d32_.p, extrap ? dprev_.p : nullptr, s_);
     k::red_outer(args_, o, s_);
     olast = o + 1;
     if (prm_.check_every > 0 && olast < prm_.max_outer)
@@ -408,8 +434,8 @@ void Solver::stage_norm() { norm_dot_scale(u_.p); }
 void Solver::energy() {
   if (args_.ct.nres == 0) return;
   k::energy_rq(args_, u_.p, s_);
-  k::energy_seps(args_, tt_, mesh_->tri.p, mesh_->tarea.p, u_.p, part_s_.p, s_);
-  k::red_energy(args_, tt_, part_s_.p, lam_.p, seps_.p, energy_.p, s_);
+  k::energy_seps(args_, sp_, mesh_->tri.p, mesh_->tarea.p, u_.p, part_s_.p, s_);
+  k::red_energy(args_, sp_, part_s_.p, lam_.p, seps_.p, energy_.p, s_);
 }
 
 void Solver::energy_to_host(double* lam, double* seps, double* E) {

@@ -96,6 +96,8 @@ class Solver {
   void normalise_range(int c_lo, int Rq);
   // Skip the stream synchronisation in the destructor (work already done).
   void detach() { detached_ = true; }
+  // Forget the previous heat increment (the next step starts from x0 = u).
+  void reset_guess() { have_dprev_ = false; }
 
   bool record_history = true;          // copy energies to the host at the cadence
   std::vector<int64_t> restart_steps;  // per restart: steps taken (stop mode)
@@ -119,6 +121,8 @@ class Solver {
 
   DevBuf<double> u_, r64_, p64_, q64_;
   DevBuf<float> d32_, r32_, p32_, q32_;
+  DevBuf<float> dprev_;      // previous step's heat increment (extrapolated start)
+  bool have_dprev_ = false;
   DevBuf<double> part_, part_s_;
   DevBuf<double> colf_;  // 8 x rp column doubles + nres_p restart doubles
   DevBuf<int> coli_;     // 7 x rp column ints + 3 x nres_p restart ints
@@ -131,7 +135,8 @@ class Solver {
   std::vector<double> h_coef_, h_res_ieps2_;
 
   StepArgs args_{};
-  Tile tt_{};
+  SepsPlan sp_{};
+  DevBuf<int4> seps_tiles_;
   int64_t steps_done_ = 0;
   std::vector<std::vector<std::pair<int64_t, double>>> hist_;
 

@@ -118,6 +118,7 @@ void assemble(const Mesh& m, const double* xyz_new, const int32_t* inc_ptr, cons
 void tau_mats(const Mesh& m, TauMats& t, hipStream_t s);
 void fill_i32(int32_t* p, int32_t v, size_t n, hipStream_t s);
 void fill_f64(double* p, double v, size_t n, hipStream_t s);
+void fill_f32(float* p, float v, size_t n, hipStream_t s);
 }  // namespace k
 
 }  // namespace sp

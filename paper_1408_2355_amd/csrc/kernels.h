@@ -60,7 +60,18 @@ struct StepArgs {
                        // [3] active columns summed over CG iterations
 };
 
+// Triangle-chunk x restart-tile plan of the S_eps element kernel.
+struct SepsPlan {
+  const int4* tiles = nullptr;  // (r0, r1, c0, c1): restarts [r0, r1) use columns [c0, c1)
+  int ntile = 0;
+  int nchunk = 0;  // triangle chunks
+  int tchunk = 0;  // triangles per chunk
+  int nt = 0;      // triangles
+  int nres_p = 0;  // row stride of the partial sums
+};
 namespace k {
+std::vector<int4> seps_tiles(const std::vector<int>& res_lo, const std::vector<int>& res_len,
+                             int nres);
 void flag_nonconv(const StepArgs& a, const int* counter, hipStream_t s);
 // float64 CG (plain form): x is the state u itself.
 void init_fp64(const StepArgs& a, const double* u, double* r, double* p, hipStream_t s);
@@ -77,7 +88,12 @@ void red_outer_init(const StepArgs& a, hipStream_t s);
 void inner_init(const StepArgs& a, int o, const double* r64, float* d, float* r, float* p,
                 hipStream_t s);
 void red_inner_init(const StepArgs& a, int o, hipStream_t s);
-void outer_update(const StepArgs& a, int o, double* u, double* r64, const float* d, hipStream_t s);
+// u += d, r64 -= K d on the columns still refining; dacc (nullable) += d
+void outer_update(const StepArgs& a, int o, double* u, double* r64, const float* d, float* dacc,
+                  hipStream_t s);
+// start from x0 = u + delta on every live column: u += delta, r64 -= K delta,
+// ||r64||^2 into partial slot 1 (call between init_outer and red_outer_init)
+void apply_guess(const StepArgs& a, double* u, double* r64, const float* delta, hipStream_t s);
 void red_outer(const StepArgs& a, int o, hipStream_t s);
 // node step and normalisation
 void nodal(const StepArgs& a, const double* u, double* out, hipStream_t s);
@@ -86,9 +102,9 @@ void red_norm(const StepArgs& a, hipStream_t s);
 void scale(const StepArgs& a, const double* v, double* u, hipStream_t s);
 // energies
 void energy_rq(const StepArgs& a, const double* u, hipStream_t s);
-void energy_seps(const StepArgs& a, const Tile& tt, const int32_t* tri, const double* tarea,
+void energy_seps(const StepArgs& a, const SepsPlan& sp, const int32_t* tri, const double* tarea,
                  const double* u, double* part_s, hipStream_t s);
-void red_energy(const StepArgs& a, const Tile& tt, const double* part_s, double* lam,
+void red_energy(const StepArgs& a, const SepsPlan& sp, const double* part_s, double* lam,
                 double* seps, double* energy, hipStream_t s);
 // labels and layout changes
 void labels(const StepArgs& a, const double* u, const int32_t* perm, int32_t* lab,

@@ -91,10 +91,65 @@ __device__ __forceinline__ double sum_chunks(const double* p, int nchunk, int rp
   return s;
 }
 
+// Column reductions over the chunk partials: a workgroup serves kRC columns
+// with kRL lanes each; lane l adds chunks l, l + kRL, ... and lane 0 adds
+// the lane sums in order (fixed order, so results are reproducible).  Every
+// thread of the block must call red_sum; the total is valid in lane 0.
+constexpr int kRL = 8;
+constexpr int kRC = kBlock / kRL;
+
+__device__ __forceinline__ int red_col() { return blockIdx.x * kRC + threadIdx.x % kRC; }
+__device__ __forceinline__ bool red_lead() { return threadIdx.x < kRC; }
+
+__device__ __forceinline__ double red_sum(const double* p, int nchunk, int rp, int c) {
+  __shared__ double sh[kBlock];
+  const int lane = threadIdx.x / kRC, cl = threadIdx.x % kRC;
+  double s = 0.0;
+  if (c < rp)
+    for (int ch = lane; ch < nchunk; ch += kRL) s += p[size_t(ch) * rp + c];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  double tot = 0.0;
+  if (lane == 0)
+    for (int l = 0; l < kRL; ++l) tot += sh[l * kRC + cl];
+  __syncthreads();
+  return tot;
+}
+
 // Count the columns for which flag is set, into *counter (one atomic per wave).
 __device__ __forceinline__ void count_active(int flag, int* counter) {
   unsigned long long bal = __ballot(flag);
   if ((threadIdx.x & 63) == 0 && bal) atomicAdd(counter, __popcll(bal));
+}
+
+// ELL row product helper.  For rows of width W <= kWFast all neighbour
+// indices are loaded first and then all neighbour vectors are requested
+// before any is used, so each thread keeps up to kWFast gathers in flight
+// (the loop is unrolled; slots >= W are predicated off).  f(k, x_k, o) gets
+// the slot, the neighbour's 4 column values and the matrix offset o = k*n+row.
+constexpr int kWFast = 8;
+
+template <typename T, typename F>
+__device__ __forceinline__ void for_neighbors(const StepArgs& a, int row, int c0,
+                                              const T* __restrict__ x, F&& f) {
+  const int W = a.W, n = a.t.n, rp = a.t.rp;
+  if (W <= kWFast) {
+    int idx[kWFast];
+#pragma unroll
+    for (int k = 0; k < kWFast; ++k) idx[k] = k < W ? a.cols[size_t(k) * n + row] : row;
+    V4<T> xv[kWFast];
+#pragma unroll
+    for (int k = 0; k < kWFast; ++k)
+      if (k < W) xv[k] = ld4(x + size_t(idx[k]) * rp + c0);
+#pragma unroll
+    for (int k = 0; k < kWFast; ++k)
+      if (k < W) f(k, xv[k], size_t(k) * n + row);
+  } else {
+    for (int k = 0; k < W; ++k) {
+      const size_t o = size_t(k) * n + row;
+      f(k, ld4(x + size_t(a.cols[o]) * rp + c0), o);
+    }
+  }
 }
 
 // --------------------------------------------------------------- assembly --
@@ -194,16 +249,13 @@ __global__ __launch_bounds__(kBlock) void k_init_fp64(StepArgs a, const double* 
     const int r1 = min(chunk * t.ch + t.ch, t.n);
     for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
       double au[4] = {}, mu[4] = {};
-      for (int k = 0; k < a.W; ++k) {
-        const size_t o = size_t(k) * t.n + row;
-        const int c = a.cols[o];
+      for_neighbors(a, row, c0, u, [&](int, const V4<double>& x, size_t o) {
         const double va = a.A64[o], vm = a.M64[o];
-        V4<double> x = ld4(u + size_t(c) * t.rp + c0);
         for (int j = 0; j < 4; ++j) {
           au[j] = fma(va, x.v[j], au[j]);
           mu[j] = fma(vm, x.v[j], mu[j]);
         }
-      }
+      });
       const double di = a.dinv64[row];
       V4<double> rv, pv;
       for (int j = 0; j < 4; ++j) {
@@ -221,13 +273,13 @@ __global__ __launch_bounds__(kBlock) void k_init_fp64(StepArgs a, const double* 
 }
 
 __global__ void k_red_init_fp64(StepArgs a) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = red_col();
+  const Tile& t = a.t;
+  const double bb = red_sum(a.part + part_off(t, 0), t.nchunk, t.rp, c);
+  const double rz = red_sum(a.part + part_off(t, 1), t.nchunk, t.rp, c);
+  const double rr = red_sum(a.part + part_off(t, 2), t.nchunk, t.rp, c);
   int act = 0;
-  if (c < a.t.rp) {
-    const Tile& t = a.t;
-    double bb = sum_chunks(a.part + part_off(t, 0), t.nchunk, t.rp, c);
-    double rz = sum_chunks(a.part + part_off(t, 1), t.nchunk, t.rp, c);
-    double rr = sum_chunks(a.part + part_off(t, 2), t.nchunk, t.rp, c);
+  if (red_lead() && c < a.t.rp) {
     a.cg.bb[c] = bb;
     a.cg.rz[c] = rz;
     a.cg.tol2[c] = a.rtol2 * bb;
@@ -256,14 +308,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmm(StepArgs a, int slot, const 
       const int r1 = min(chunk * t.ch + t.ch, t.n);
       for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
         V4<T> acc = {}, pd = {};
-        for (int k = 0; k < a.W; ++k) {
-          const size_t o = size_t(k) * t.n + row;
-          const int c = a.cols[o];
+        for_neighbors(a, row, c0, p, [&](int k, const V4<T>& x, size_t o) {
           const T v = K[o];
-          V4<T> x = ld4(p + size_t(c) * t.rp + c0);
           if (k == 0) pd = x;
           for (int j = 0; j < 4; ++j) acc.v[j] = fma(v, x.v[j], acc.v[j]);
-        }
+        });
         st4(q + size_t(row) * t.rp + c0, acc);
         for (int j = 0; j < 4; ++j) s[0][j] += double(pd.v[j]) * double(acc.v[j]);
       }
@@ -277,13 +326,12 @@ __global__ void k_red_alpha(StepArgs a, int slot, int next) {
   if (a.ring[slot] == 0) return;
   // columns this iteration works on, summed over iterations (traffic model)
   if (blockIdx.x == 0 && threadIdx.x == 0) a.stat[3] += a.ring[slot];
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= a.t.rp) return;
+  const int c = red_col();
+  const bool act = c < a.t.rp && a.cg.act[c];
+  const double pq = red_sum(a.part, act ? a.t.nchunk : 0, a.t.rp, c);
+  if (!red_lead() || c >= a.t.rp) return;
   double al = 0.0;
-  if (a.cg.act[c]) {
-    double pq = sum_chunks(a.part, a.t.nchunk, a.t.rp, c);
-    if (pq > 0.0) al = a.cg.rz[c] / pq;
-  }
+  if (act && pq > 0.0) al = a.cg.rz[c] / pq;
   a.cg.alpha[c] = al;
 }
 
@@ -336,12 +384,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(StepArgs a, int slot, T* _
 __global__ void k_red_beta(StepArgs a, int slot, int next) {
   if (a.ring[slot] == 0) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) a.stat[0] += 1;  // an iteration that did work
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = red_col();
+  const Tile& t = a.t;
+  const bool act = c < t.rp && a.cg.act[c];
+  const double rzn = red_sum(a.part + part_off(t, 0), act ? t.nchunk : 0, t.rp, c);
+  const double rr = red_sum(a.part + part_off(t, 1), act ? t.nchunk : 0, t.rp, c);
   int still = 0;
-  if (c < a.t.rp && a.cg.act[c]) {
-    const Tile& t = a.t;
-    double rzn = sum_chunks(a.part + part_off(t, 0), t.nchunk, t.rp, c);
-    double rr = sum_chunks(a.part + part_off(t, 1), t.nchunk, t.rp, c);
+  if (red_lead() && act) {
     a.cg.iters[c] += 1;
     if (rr <= a.cg.tol2[c] || !(rr == rr)) {
       a.cg.act[c] = 0;
@@ -404,16 +453,13 @@ __global__ __launch_bounds__(kBlock) void k_init_outer(StepArgs a, const double*
     const int r1 = min(chunk * t.ch + t.ch, t.n);
     for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
       double au[4] = {}, mu[4] = {};
-      for (int k = 0; k < a.W; ++k) {
-        const size_t o = size_t(k) * t.n + row;
-        const int c = a.cols[o];
+      for_neighbors(a, row, c0, u, [&](int, const V4<double>& x, size_t o) {
         const double va = a.A64[o], vm = a.M64[o];
-        V4<double> x = ld4(u + size_t(c) * t.rp + c0);
         for (int j = 0; j < 4; ++j) {
           au[j] = fma(va, x.v[j], au[j]);
           mu[j] = fma(vm, x.v[j], mu[j]);
         }
-      }
+      });
       V4<double> rv;
       for (int j = 0; j < 4; ++j) {
         rv.v[j] = -a.tau * au[j] * lv[j];
@@ -427,12 +473,12 @@ __global__ __launch_bounds__(kBlock) void k_init_outer(StepArgs a, const double*
 }
 
 __global__ void k_red_outer_init(StepArgs a) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = red_col();
+  const Tile& t = a.t;
+  const double bb = red_sum(a.part + part_off(t, 0), t.nchunk, t.rp, c);
+  const double rr = red_sum(a.part + part_off(t, 1), t.nchunk, t.rp, c);
   int act = 0;
-  if (c < a.t.rp) {
-    const Tile& t = a.t;
-    double bb = sum_chunks(a.part + part_off(t, 0), t.nchunk, t.rp, c);
-    double rr = sum_chunks(a.part + part_off(t, 1), t.nchunk, t.rp, c);
+  if (red_lead() && c < t.rp) {
     a.cg.bb[c] = bb;
     a.cg.rr_o[c] = rr;
     act = (a.ct.live[c] && rr > a.rtol2 * bb) ? 1 : 0;
@@ -482,12 +528,12 @@ __global__ __launch_bounds__(kBlock) void k_inner_init(StepArgs a, int oslot,
 __global__ void k_red_inner_init(StepArgs a, int oslot, int onext) {
   if (blockIdx.x == 0 && threadIdx.x == 0) a.oring[onext] = 0;
   if (a.oring[oslot] == 0) return;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = red_col();
+  const Tile& t = a.t;
+  const double rz = red_sum(a.part + part_off(t, 0), t.nchunk, t.rp, c);
+  const double rr = red_sum(a.part + part_off(t, 1), t.nchunk, t.rp, c);
   int act = 0;
-  if (c < a.t.rp) {
-    const Tile& t = a.t;
-    double rz = sum_chunks(a.part + part_off(t, 0), t.nchunk, t.rp, c);
-    double rr = sum_chunks(a.part + part_off(t, 1), t.nchunk, t.rp, c);
+  if (red_lead() && c < t.rp) {
     a.cg.rz[c] = rz;
     // stop the inner solve once its residual drops by inner_rtol, or below a
     // quarter of the outer target (no point solving further than needed)
@@ -502,21 +548,29 @@ __global__ void k_red_inner_init(StepArgs a, int oslot, int onext) {
 
 // x64 += d; r64 -= K64 d (float64 product of the float32 correction);
 // partial ||r64||^2.
-__global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot,
+//
+// The same kernel applies the extrapolated start x0 = u + delta (guess
+// mode: every live column, no sweep gating, partial written to slot 1 next to
+// the ||M u||^2 of slot 0).  In refinement mode, dacc (if given) accumulates
+// this step's corrections, so after the last sweep it holds the step's heat
+// increment x - u used as the next step's start.
+__global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot, bool guess,
                                                          double* __restrict__ u,
                                                          double* __restrict__ r64,
-                                                         const float* __restrict__ d) {
-  if (a.oring[oslot] == 0) return;
+                                                         const float* __restrict__ d,
+                                                         float* __restrict__ dacc) {
+  if (!guess && a.oring[oslot] == 0) return;
   const Tile& t = a.t;
   int chunk, ct;
   tile_block(t, chunk, ct);
   const int rl = threadIdx.x / t.tg, g = ct * t.tg + threadIdx.x % t.tg;
+  const int* mask = guess ? a.ct.live : a.cg.act_o;
   double s[1][4] = {};
   if (g < t.G) {
     const int c0 = 4 * g;
     int act[4], any = 0;
     for (int j = 0; j < 4; ++j) {
-      act[j] = a.cg.act_o[c0 + j];
+      act[j] = mask[c0 + j];
       any |= act[j];
     }
     if (any) {
@@ -524,15 +578,12 @@ __global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot,
       for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
         double kd[4] = {};
         float dd[4] = {};
-        for (int k = 0; k < a.W; ++k) {
-          const size_t o = size_t(k) * t.n + row;
-          const int c = a.cols[o];
+        for_neighbors(a, row, c0, d, [&](int k, const V4<float>& x, size_t o) {
           const double v = a.K64[o];
-          V4<float> x = ld4(d + size_t(c) * t.rp + c0);
           if (k == 0)
             for (int j = 0; j < 4; ++j) dd[j] = x.v[j];
           for (int j = 0; j < 4; ++j) kd[j] = fma(v, double(x.v[j]), kd[j]);
-        }
+        });
         const size_t o = size_t(row) * t.rp + c0;
         V4<double> uv = ld4(u + o), rv = ld4(r64 + o);
         for (int j = 0; j < 4; ++j) {
@@ -544,19 +595,26 @@ __global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot,
         }
         st4(u + o, uv);
         st4(r64 + o, rv);
+        if (dacc) {
+          V4<float> av = ld4(dacc + o);
+          for (int j = 0; j < 4; ++j)
+            if (act[j]) av.v[j] += dd[j];
+          st4(dacc + o, av);
+        }
       }
     }
   }
-  block_store<1>(t, s, a.part, chunk, ct);
+  block_store<1>(t, s, a.part + (guess ? part_off(t, 1) : 0), chunk, ct);
 }
 
 __global__ void k_red_outer(StepArgs a, int oslot, int onext) {
   if (a.oring[oslot] == 0) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) a.stat[1] += 1;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = red_col();
+  const bool act = c < a.t.rp && a.cg.act_o[c];
+  const double rr = red_sum(a.part, act ? a.t.nchunk : 0, a.t.rp, c);
   int still = 0;
-  if (c < a.t.rp && a.cg.act_o[c]) {
-    double rr = sum_chunks(a.part, a.t.nchunk, a.t.rp, c);
+  if (red_lead() && act) {
     a.cg.rr_o[c] = rr;
     a.cg.sweeps[c] += 1;
     if (rr <= a.rtol2 * a.cg.bb[c] || !(rr == rr))
@@ -629,14 +687,11 @@ __global__ __launch_bounds__(kBlock) void k_norm_dot(StepArgs a, const double* _
       for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
         double mv[4] = {};
         V4<double> vd = {};
-        for (int k = 0; k < a.W; ++k) {
-          const size_t o = size_t(k) * t.n + row;
-          const int c = a.cols[o];
+        for_neighbors(a, row, c0, v, [&](int k, const V4<double>& x, size_t o) {
           const double w = a.M64[o];
-          V4<double> x = ld4(v + size_t(c) * t.rp + c0);
           if (k == 0) vd = x;
           for (int j = 0; j < 4; ++j) mv[j] = fma(w, x.v[j], mv[j]);
-        }
+        });
         for (int j = 0; j < 4; ++j)
           if (lv[j]) s[0][j] += vd.v[j] * mv[j];
       }
@@ -646,11 +701,11 @@ __global__ __launch_bounds__(kBlock) void k_norm_dot(StepArgs a, const double* _
 }
 
 __global__ void k_red_norm(StepArgs a) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= a.t.rp) return;
-  double nv = 1.0;
-  if (a.ct.live[c]) nv = sqrt(sum_chunks(a.part, a.t.nchunk, a.t.rp, c));
-  a.cg.nrm[c] = nv;
+  const int c = red_col();
+  const bool lv = c < a.t.rp && a.ct.live[c];
+  const double s = red_sum(a.part, lv ? a.t.nchunk : 0, a.t.rp, c);
+  if (!red_lead() || c >= a.t.rp) return;
+  a.cg.nrm[c] = lv ? sqrt(s) : 1.0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_scale(StepArgs a, const double* __restrict__ v,
@@ -700,17 +755,14 @@ __global__ __launch_bounds__(kBlock) void k_energy_rq(StepArgs a, const double* 
       for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
         double au[4] = {}, mu[4] = {};
         V4<double> ud = {};
-        for (int k = 0; k < a.W; ++k) {
-          const size_t o = size_t(k) * t.n + row;
-          const int c = a.cols[o];
+        for_neighbors(a, row, c0, u, [&](int k, const V4<double>& x, size_t o) {
           const double va = a.A64[o], vm = a.M64[o];
-          V4<double> x = ld4(u + size_t(c) * t.rp + c0);
           if (k == 0) ud = x;
           for (int j = 0; j < 4; ++j) {
             au[j] = fma(va, x.v[j], au[j]);
             mu[j] = fma(vm, x.v[j], mu[j]);
           }
-        }
+        });
         for (int j = 0; j < 4; ++j)
           if (lv[j]) {
             s[0][j] += ud.v[j] * au[j];
@@ -733,78 +785,121 @@ __global__ __launch_bounds__(kBlock) void k_energy_rq(StepArgs a, const double* 
 // with S = 1^T X 1, tr = trace, g = G 1, h = H 1, dX = diag X.  Then
 //   int_T sum_{i != j} u_i^2 u_j^2 = (2|T|/360) sum_i B(G_{<i}, a_i a_i^T),
 //   G_{<i} = sum_{j<i} a_j a_j^T,
-// a sum of nonnegative terms for nonnegative u (no cancellation).  Each
-// thread takes one (triangle, restart); the restart's m vertex triples are
-// read straight from the [n][rp] state (consecutive restarts are adjacent in
-// memory).  Partials per (triangle chunk, restart).
-__global__ __launch_bounds__(kBlock) void k_energy_seps(StepArgs a, Tile tt,
+// a sum of nonnegative terms for nonnegative u (no cancellation).
+// quartic_pairs returns sum_i B(G_{<i}, a_i a_i^T) for one restart of m
+// components whose values at the three corners start at u0, u1, u2.
+__device__ __forceinline__ double quartic_pairs(const double* u0, const double* u1,
+                                                const double* u2, int m) {
+  double g00 = 0, g11 = 0, g22 = 0, g01 = 0, g02 = 0, g12 = 0, acc = 0;
+  for (int i = 0; i < m; ++i) {
+    const double x0 = u0[i], x1 = u1[i], x2 = u2[i];
+    const double s1 = x0 + x1 + x2;
+    const double q0 = x0 * x0, q1 = x1 * x1, q2 = x2 * x2;
+    const double s2 = q0 + q1 + q2;
+    const double trG = g00 + g11 + g22;
+    const double SG = trG + 2.0 * (g01 + g02 + g12);
+    const double gv0 = g00 + g01 + g02, gv1 = g01 + g11 + g12, gv2 = g02 + g12 + g22;
+    const double ga = gv0 * x0 + gv1 * x1 + gv2 * x2;
+    const double da = g00 * x0 + g11 * x1 + g22 * x2;
+    const double gq = gv0 * q0 + gv1 * q1 + gv2 * q2;
+    const double dq = g00 * q0 + g11 * q1 + g22 * q2;
+    const double aGa = dq + 2.0 * (x0 * x1 * g01 + x0 * x2 * g02 + x1 * x2 * g12);
+    acc += (SG + trG) * s1 * s1 + (SG + trG) * s2 + 2.0 * aGa + 4.0 * s1 * (ga + da) +
+           4.0 * gq + 6.0 * dq;
+    g00 += q0;
+    g11 += q1;
+    g22 += q2;
+    g01 += x0 * x1;
+    g02 += x0 * x2;
+    g12 += x1 * x2;
+  }
+  return acc;
+}
+
+// Element kernel with LDS staging.  A workgroup takes one restart tile (a
+// run of restarts whose columns fit in kSepsCols) and one chunk of triangles.
+// Per pass it stages the three corner rows of up to 4 triangles, columns
+// [c0, c1), into LDS with coalesced loads (the triangles are sorted by
+// vertex, so neighbouring passes share rows in L2), then one thread per
+// (triangle, restart) runs the quartic over the staged values.  A tile wider
+// than kSepsCols reads its corners straight from global memory instead.
+// Partials per (triangle chunk, restart), reduced over the pass in fixed order.
+constexpr int kSepsCols = 256;
+constexpr int kSepsTri = 4;
+
+__global__ __launch_bounds__(kBlock) void k_energy_seps(StepArgs a, SepsPlan sp,
                                                         const int* __restrict__ tri,
                                                         const double* __restrict__ tarea,
                                                         const double* __restrict__ u,
                                                         double* __restrict__ part_s) {
-  int chunk, ct;
-  tile_block(tt, chunk, ct);
-  const int tid = threadIdx.x, rl = tid / tt.tg, gl = tid % tt.tg;
-  const int r = ct * tt.tg + gl;
-  double acc_all = 0.0;
-  if (r < a.ct.nres) {
-    const int lo = a.ct.res_lo[r], m = a.ct.res_len[r];
-    const int r1 = min(chunk * tt.ch + tt.ch, tt.n);
-    for (int tr_ = chunk * tt.ch + rl; tr_ < r1; tr_ += tt.tr) {
-      const double* u0 = u + size_t(tri[3 * tr_ + 0]) * a.t.rp + lo;
-      const double* u1 = u + size_t(tri[3 * tr_ + 1]) * a.t.rp + lo;
-      const double* u2 = u + size_t(tri[3 * tr_ + 2]) * a.t.rp + lo;
-      double g00 = 0, g11 = 0, g22 = 0, g01 = 0, g02 = 0, g12 = 0, acc = 0;
-      for (int i = 0; i < m; ++i) {
-        const double x0 = u0[i], x1 = u1[i], x2 = u2[i];
-        const double s1 = x0 + x1 + x2;
-        const double q0 = x0 * x0, q1 = x1 * x1, q2 = x2 * x2;
-        const double s2 = q0 + q1 + q2;
-        const double trG = g00 + g11 + g22;
-        const double SG = trG + 2.0 * (g01 + g02 + g12);
-        const double gv0 = g00 + g01 + g02, gv1 = g01 + g11 + g12, gv2 = g02 + g12 + g22;
-        const double ga = gv0 * x0 + gv1 * x1 + gv2 * x2;
-        const double da = g00 * x0 + g11 * x1 + g22 * x2;
-        const double gq = gv0 * q0 + gv1 * q1 + gv2 * q2;
-        const double dq = g00 * q0 + g11 * q1 + g22 * q2;
-        const double aGa = dq + 2.0 * (x0 * x1 * g01 + x0 * x2 * g02 + x1 * x2 * g12);
-        acc += (SG + trG) * s1 * s1 + (SG + trG) * s2 + 2.0 * aGa + 4.0 * s1 * (ga + da) +
-               4.0 * gq + 6.0 * dq;
-        g00 += q0;
-        g11 += q1;
-        g22 += q2;
-        g01 += x0 * x1;
-        g02 += x0 * x2;
-        g12 += x1 * x2;
-      }
-      acc_all += acc * tarea[tr_] * (1.0 / 180.0);
-    }
-  }
+  __shared__ double sh[kSepsTri * 3 * kSepsCols];
   __shared__ double red[kBlock];
-  red[tid] = acc_all;
-  for (int st = tt.tr >> 1; st >= 1; st >>= 1) {
-    __syncthreads();
-    if (rl < st) red[tid] += red[tid + st * tt.tg];
+  const int tile = blockIdx.x / sp.nchunk, chunk = blockIdx.x % sp.nchunk;
+  const int4 tl = sp.tiles[tile];
+  const int r0 = tl.x, nr = tl.y - tl.x, c0 = tl.z, ncol = tl.w - tl.z;
+  const bool staged = ncol <= kSepsCols;
+  const int TB = max(1, min(kSepsTri, kBlock / max(nr, 1)));
+  const int tid = threadIdx.x, tb = tid / max(nr, 1), rr = tid % max(nr, 1);
+  const bool worker = tid < TB * nr;
+  const int rp = a.t.rp;
+  const int t_beg = chunk * sp.tchunk, t_end = min(t_beg + sp.tchunk, sp.nt);
+  int lo = 0, m = 0;
+  if (worker) {
+    lo = a.ct.res_lo[r0 + rr];
+    m = a.ct.res_len[r0 + rr];
   }
+  double acc = 0.0;
+  for (int t0 = t_beg; t0 < t_end; t0 += TB) {
+    if (staged) {
+      const int per_tri = 3 * ncol;
+      for (int idx = tid; idx < TB * per_tri; idx += kBlock) {
+        const int b = idx / per_tri, rem = idx - b * per_tri;
+        const int k = rem / ncol, c = rem - k * ncol;
+        const int t = t0 + b;
+        sh[(b * 3 + k) * kSepsCols + c] =
+            t < t_end ? u[size_t(tri[3 * t + k]) * rp + c0 + c] : 0.0;
+      }
+      __syncthreads();
+    }
+    const int t = t0 + tb;
+    if (worker && t < t_end && m > 0) {
+      double q;
+      if (staged) {
+        const double* base = sh + size_t(tb) * 3 * kSepsCols + (lo - c0);
+        q = quartic_pairs(base, base + kSepsCols, base + 2 * kSepsCols, m);
+      } else {
+        q = quartic_pairs(u + size_t(tri[3 * t + 0]) * rp + lo, u + size_t(tri[3 * t + 1]) * rp + lo,
+                          u + size_t(tri[3 * t + 2]) * rp + lo, m);
+      }
+      acc += q * tarea[t] * (1.0 / 180.0);
+    }
+    if (staged) __syncthreads();
+  }
+  red[tid] = acc;
   __syncthreads();
-  if (rl == 0 && r < tt.rp) part_s[size_t(chunk) * tt.rp + r] = red[tid];
+  if (tid < nr) {
+    double s = 0.0;
+    for (int b = 0; b < TB; ++b) s += red[b * nr + tid];
+    part_s[size_t(chunk) * sp.nres_p + r0 + tid] = s;
+  }
 }
 
 __global__ void k_red_lambda(StepArgs a, double* __restrict__ lam) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= a.t.rp) return;
+  const int c = red_col();
   const Tile& t = a.t;
-  double num = sum_chunks(a.part + part_off(t, 0), t.nchunk, t.rp, c);
-  double den = sum_chunks(a.part + part_off(t, 1), t.nchunk, t.rp, c);
-  lam[c] = a.ct.seg_len[c] > 0 ? num / den : 0.0;
+  const bool real = c < t.rp && a.ct.seg_len[c] > 0;
+  const double num = red_sum(a.part + part_off(t, 0), real ? t.nchunk : 0, t.rp, c);
+  const double den = red_sum(a.part + part_off(t, 1), real ? t.nchunk : 0, t.rp, c);
+  if (!red_lead() || c >= t.rp) return;
+  lam[c] = real ? num / den : 0.0;
 }
 
-__global__ void k_red_seps(StepArgs a, Tile tt, const double* __restrict__ part_s,
+__global__ void k_red_seps(StepArgs a, SepsPlan sp, const double* __restrict__ part_s,
                            const double* __restrict__ lam, double* __restrict__ seps,
                            double* __restrict__ energy) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= a.ct.nres) return;
-  const double s = sum_chunks(part_s, tt.nchunk, tt.rp, r) * a.ct.res_ieps2[r];
+  const double s = sum_chunks(part_s, sp.nchunk, sp.nres_p, r) * a.ct.res_ieps2[r];
   double e = s;
   const int lo = a.ct.res_lo[r], m = a.ct.res_len[r];
   for (int i = 0; i < m; ++i) e += lam[lo + i];
@@ -858,7 +953,8 @@ __global__ void k_unpack(size_t total, int rp, int n, int c_lo, int Rq, const do
 }
 
 inline unsigned nblocks(size_t work, int bs = kBlock) { return unsigned((work + bs - 1) / bs); }
-inline unsigned colblocks(const Tile& t) { return nblocks(size_t(t.rp)); }
+// blocks of the column reductions (kRC columns per block)
+inline unsigned colblocks(const Tile& t) { return nblocks(size_t(t.rp), kRC); }
 
 #define SP_LAUNCH_CHECK() SP_HIP(hipGetLastError())
 
@@ -909,6 +1005,12 @@ void fill_i32(int32_t* p, int32_t v, size_t n, hipStream_t s) {
 void fill_f64(double* p, double v, size_t n, hipStream_t s) {
   if (!n) return;
   hipLaunchKernelGGL(k_fill<double>, dim3(nblocks(n)), dim3(kBlock), 0, s, p, v, n);
+  SP_LAUNCH_CHECK();
+}
+
+void fill_f32(float* p, float v, size_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_fill<float>, dim3(nblocks(n)), dim3(kBlock), 0, s, p, v, n);
   SP_LAUNCH_CHECK();
 }
 
@@ -974,8 +1076,16 @@ void red_inner_init(const StepArgs& a, int o, hipStream_t s) {
   SP_LAUNCH_CHECK();
 }
 
-void outer_update(const StepArgs& a, int o, double* u, double* r64, const float* d, hipStream_t s) {
-  hipLaunchKernelGGL(k_outer_update, dim3(a.t.nblk), dim3(kBlock), 0, s, a, o % kRing, u, r64, d);
+void outer_update(const StepArgs& a, int o, double* u, double* r64, const float* d, float* dacc,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_outer_update, dim3(a.t.nblk), dim3(kBlock), 0, s, a, o % kRing, false, u,
+                     r64, d, dacc);
+  SP_LAUNCH_CHECK();
+}
+
+void apply_guess(const StepArgs& a, double* u, double* r64, const float* delta, hipStream_t s) {
+  hipLaunchKernelGGL(k_outer_update, dim3(a.t.nblk), dim3(kBlock), 0, s, a, 0, true, u, r64, delta,
+                     (float*)nullptr);
   SP_LAUNCH_CHECK();
 }
 
@@ -1010,19 +1120,47 @@ void energy_rq(const StepArgs& a, const double* u, hipStream_t s) {
   SP_LAUNCH_CHECK();
 }
 
-void energy_seps(const StepArgs& a, const Tile& tt, const int32_t* tri, const double* tarea,
+void energy_seps(const StepArgs& a, const SepsPlan& sp, const int32_t* tri, const double* tarea,
                  const double* u, double* part_s, hipStream_t s) {
-  hipLaunchKernelGGL(k_energy_seps, dim3(tt.nblk), dim3(kBlock), 0, s, a, tt, tri, tarea, u,
-                     part_s);
+  if (sp.ntile == 0) return;
+  hipLaunchKernelGGL(k_energy_seps, dim3(unsigned(sp.ntile) * sp.nchunk), dim3(kBlock), 0, s, a,
+                     sp, tri, tarea, u, part_s);
   SP_LAUNCH_CHECK();
 }
 
-void red_energy(const StepArgs& a, const Tile& tt, const double* part_s, double* lam,
+void red_energy(const StepArgs& a, const SepsPlan& sp, const double* part_s, double* lam,
                 double* seps, double* energy, hipStream_t s) {
   hipLaunchKernelGGL(k_red_lambda, dim3(colblocks(a.t)), dim3(kBlock), 0, s, a, lam);
-  hipLaunchKernelGGL(k_red_seps, dim3(nblocks(size_t(a.ct.nres))), dim3(kBlock), 0, s, a, tt,
+  hipLaunchKernelGGL(k_red_seps, dim3(nblocks(size_t(a.ct.nres))), dim3(kBlock), 0, s, a, sp,
                      part_s, (const double*)lam, seps, energy);
   SP_LAUNCH_CHECK();
+}
+
+std::vector<int4> seps_tiles(const std::vector<int>& res_lo, const std::vector<int>& res_len,
+                             int nres) {
+  // contiguous runs of restarts whose columns fit in kSepsCols (at most 64
+  // restarts, so every restart of a run gets a worker thread per triangle)
+  std::vector<int4> tiles;
+  int r = 0;
+  while (r < nres) {
+    int r1 = r, c0 = 0, c1 = 0;
+    bool any = false;
+    while (r1 < nres && r1 - r < 64) {
+      const int lo = res_lo[r1], len = res_len[r1];
+      if (len > 0) {
+        const int n0 = any ? std::min(c0, lo) : lo, n1 = any ? std::max(c1, lo + len) : lo + len;
+        if (any && n1 - n0 > kSepsCols) break;
+        c0 = n0;
+        c1 = n1;
+        any = true;
+      }
+      ++r1;
+    }
+    if (r1 == r) r1 = r + 1;  // a single restart wider than the stage
+    tiles.push_back(make_int4(r, r1, c0, c1));
+    r = r1;
+  }
+  return tiles;
 }
 
 void labels(const StepArgs& a, const double* u, const int32_t* perm, int32_t* lab, int32_t* lab_am,

@@ -35,6 +35,7 @@ Server::~Server() {
 bool Server::compatible(const sp_params& a, const sp_params& b) {
   return a.tau == b.tau && a.precision == b.precision && a.cg_rtol == b.cg_rtol &&
          a.cg_max_iter == b.cg_max_iter && a.check_every == b.check_every &&
+         a.extrapolate == b.extrapolate &&
          (a.precision == SP_FP64 || (a.inner_rtol == b.inner_rtol && a.max_outer == b.max_outer));
 }
 

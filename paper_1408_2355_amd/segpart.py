@@ -40,7 +40,7 @@ class sp_params(C.Structure):
                 ("max_steps", C.c_int64), ("energy_every", C.c_int64),
                 ("precision", C.c_int32), ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int32),
                 ("inner_rtol", C.c_double), ("max_outer", C.c_int32),
-                ("check_every", C.c_int32), ("reserved", C.c_int32)]
+                ("check_every", C.c_int32), ("extrapolate", C.c_int32)]
 
 
 class sp_stats(C.Structure):
