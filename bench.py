@@ -76,6 +76,12 @@ def main():
     ap.add_argument("--workload", default="sphere7-batched", choices=sorted(WORKLOADS))
     ap.add_argument("--no-plain", action="store_true", help="skip the plain float64 leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--inner-rtol", type=float, default=1e-6,
+                    help="relative reduction of each float32 inner solve")
+    ap.add_argument("--check-every", type=int, default=8,
+                    help="CG iterations between host convergence polls")
+    ap.add_argument("--no-extrapolate", action="store_true",
+                    help="start every heat solve from u (not u + previous increment)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -109,7 +115,8 @@ def main():
 
     mesh = sp.Mesh(v, f)
     prm = sp.params(tau, precision="mixed", n_steps=1, energy_every=1, cg_rtol=1e-10,
-                    inner_rtol=1e-5, max_outer=8, cg_max_iter=500, check_every=8)
+                    inner_rtol=args.inner_rtol, max_outer=8, cg_max_iter=500,
+                    check_every=args.check_every, extrapolate=int(not args.no_extrapolate))
     st = sp.State(mesh, prm, ms, np.full(nres, eps), u0)
     del u0
     log("[bench] warmup")

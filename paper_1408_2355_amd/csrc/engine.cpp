@@ -20,7 +20,6 @@
 namespace sp {
 
 namespace {
-constexpr int kTargetBlocks = 2048;
 enum { CF_BB, CF_RZ, CF_TOL2, CF_ALPHA, CF_BETA, CF_RRO, CF_NRM, CF_COEF, CF_N };
 enum { CI_ACT, CI_ACTO, CI_ITERS, CI_SWEEPS, CI_SEGLO, CI_SEGLEN, CI_LIVE, CI_N };
 }  // namespace
@@ -82,7 +81,7 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     km_ = mesh_->tau_mats(prm_.tau);
     const int n = int(mesh_->n);
     const size_t nv = size_t(n) * rp_;
-    Tile t = make_tile(n, rp_, 64, kTargetBlocks);
+    Tile t = make_tile(n, rp_);
     sp_.nt = int(mesh_->nt);
     sp_.tchunk = std::max(256, int((mesh_->nt + 1023) / 1024 + 3) / 4 * 4);
     sp_.nchunk = int((mesh_->nt + sp_.tchunk - 1) / sp_.tchunk);

@@ -67,20 +67,26 @@ struct DevBuf {
 
 // Row x column tiling of an [n][rp] column-interleaved array for the
 // row-parallel kernels.  A thread owns 4 consecutive columns of one row; a
-// 256-thread workgroup covers tr rows x tg column groups per pass and walks a
-// chunk of ch rows; per-column partial sums are written per chunk.
+// 256-thread workgroup covers tr rows x tg column groups per pass.  The rows
+// are split into 8 contiguous ranges (one per XCD) of xrows rows; within a
+// range, chunks of ch rows go to the range's nper workgroups cyclically.
+// Every workgroup walks all nct column tiles and writes one partial sum per
+// column, so partial arrays have nchunk = nblk rows.
 struct Tile {
   int n = 0;       // rows
   int rp = 0;      // padded columns (multiple of 4)
   int G = 0;       // column groups (rp / 4)
   int tg = 1;      // column groups per tile (power of two, <= 64)
   int tr = 256;    // rows per pass (256 / tg)
-  int ch = 256;    // rows per chunk (multiple of tr)
-  int nchunk = 1;  // chunks
   int nct = 1;     // column tiles
-  int nblk = 1;    // workgroups
+  int xrows = 0;   // rows per XCD range (ceil(n / 8))
+  int ch = 256;    // rows per chunk (multiple of tr)
+  int nchx = 1;    // chunks per XCD range
+  int nper = 1;    // workgroups per XCD range
+  int nblk = 8;    // workgroups (8 * nper)
+  int nchunk = 8;  // rows of the partial-sum arrays (= nblk)
 };
-Tile make_tile(int n, int rp, int tg_cap, int target_blocks);
+Tile make_tile(int n, int rp);
 
 // Per-time-step matrices for one tau: K = M + tau A in float64 and float32,
 // and the inverse diagonals used by the Jacobi preconditioner.

@@ -46,17 +46,22 @@ __device__ __forceinline__ void st4(float* p, const V4<float>& x) {
   *reinterpret_cast<float4*>(p) = make_float4(x.v[0], x.v[1], x.v[2], x.v[3]);
 }
 
-// Logical (chunk, column tile) of this workgroup.  Workgroups are handed to
-// the 8 XCDs round-robin by id; remap so every XCD gets one contiguous range
-// of logical blocks (neighbouring row chunks of one column tile), which keeps
-// the gathered neighbour rows in that XCD's L2.
-__device__ __forceinline__ void tile_block(const Tile& t, int& chunk, int& ct) {
-  int b = blockIdx.x, nb = t.nblk;
-  int q = nb >> 3, rem = nb & 7;
-  int x = b & 7, k = b >> 3;
-  int L = x * q + min(x, rem) + k;
-  chunk = L % t.nchunk;
-  ct = L / t.nchunk;
+// Row traversal of the row-parallel kernels.  Workgroups are handed to the
+// 8 XCDs round-robin by id, so workgroup b runs on XCD b % 8.  The rows are
+// split into 8 contiguous ranges, one per XCD; inside its range an XCD's
+// workgroups take chunks of ch rows cyclically (chunk j -> workgroup j mod
+// nper), so at any moment they work on one compact window of rows and the
+// neighbour rows they gather stay in that XCD's L2.  Each workgroup walks
+// every column tile in turn (the caller's loop over ct).
+template <typename F>
+__device__ __forceinline__ void for_rows(const Tile& t, F&& f) {
+  const int xcd = blockIdx.x & 7, kb = blockIdx.x >> 3;
+  const int rbeg = xcd * t.xrows, rend = min(rbeg + t.xrows, t.n);
+  const int rl = threadIdx.x / t.tg;
+  for (int j = kb; j < t.nchx; j += t.nper) {
+    const int r1 = min(rbeg + (j + 1) * t.ch, rend);
+    for (int row = rbeg + j * t.ch + rl; row < r1; row += t.tr) f(row);
+  }
 }
 
 __device__ __forceinline__ size_t part_off(const Tile& t, int d) {
@@ -238,16 +243,14 @@ __global__ __launch_bounds__(kBlock) void k_init_fp64(StepArgs a, const double* 
                                                       double* __restrict__ r,
                                                       double* __restrict__ p) {
   const Tile& t = a.t;
-  int chunk, ct;
-  tile_block(t, chunk, ct);
-  const int rl = threadIdx.x / t.tg, g = ct * t.tg + threadIdx.x % t.tg;
+  for (int ct = 0; ct < t.nct; ++ct) {
+  const int g = ct * t.tg + threadIdx.x % t.tg;
   double s[3][4] = {};
   if (g < t.G) {
     const int c0 = 4 * g;
     double lv[4];
     for (int j = 0; j < 4; ++j) lv[j] = a.ct.live[c0 + j] ? 1.0 : 0.0;
-    const int r1 = min(chunk * t.ch + t.ch, t.n);
-    for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
+    for_rows(t, [&](int row) {
       double au[4] = {}, mu[4] = {};
       for_neighbors(a, row, c0, u, [&](int, const V4<double>& x, size_t o) {
         const double va = a.A64[o], vm = a.M64[o];
@@ -267,9 +270,10 @@ __global__ __launch_bounds__(kBlock) void k_init_fp64(StepArgs a, const double* 
       }
       st4(r + size_t(row) * t.rp + c0, rv);
       st4(p + size_t(row) * t.rp + c0, pv);
-    }
+    });
   }
-  block_store<3>(t, s, a.part, chunk, ct);
+  block_store<3>(t, s, a.part, blockIdx.x, ct);
+  }
 }
 
 __global__ void k_red_init_fp64(StepArgs a) {
@@ -297,16 +301,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmm(StepArgs a, int slot, const 
                                                     const T* __restrict__ p, T* __restrict__ q) {
   if (a.ring[slot] == 0) return;
   const Tile& t = a.t;
-  int chunk, ct;
-  tile_block(t, chunk, ct);
-  const int rl = threadIdx.x / t.tg, g = ct * t.tg + threadIdx.x % t.tg;
+  for (int ct = 0; ct < t.nct; ++ct) {
+  const int g = ct * t.tg + threadIdx.x % t.tg;
   double s[1][4] = {};
   if (g < t.G) {
     const int c0 = 4 * g;
     const int any = a.cg.act[c0] | a.cg.act[c0 + 1] | a.cg.act[c0 + 2] | a.cg.act[c0 + 3];
     if (any) {
-      const int r1 = min(chunk * t.ch + t.ch, t.n);
-      for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
+      for_rows(t, [&](int row) {
         V4<T> acc = {}, pd = {};
         for_neighbors(a, row, c0, p, [&](int k, const V4<T>& x, size_t o) {
           const T v = K[o];
@@ -315,10 +317,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmm(StepArgs a, int slot, const 
         });
         st4(q + size_t(row) * t.rp + c0, acc);
         for (int j = 0; j < 4; ++j) s[0][j] += double(pd.v[j]) * double(acc.v[j]);
-      }
+      });
     }
   }
-  block_store<1>(t, s, a.part, chunk, ct);
+  block_store<1>(t, s, a.part, blockIdx.x, ct);
+  }
 }
 
 __global__ void k_red_alpha(StepArgs a, int slot, int next) {
@@ -343,9 +346,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(StepArgs a, int slot, T* _
                                                       const T* __restrict__ dinv) {
   if (a.ring[slot] == 0) return;
   const Tile& t = a.t;
-  int chunk, ct;
-  tile_block(t, chunk, ct);
-  const int rl = threadIdx.x / t.tg, g = ct * t.tg + threadIdx.x % t.tg;
+  for (int ct = 0; ct < t.nct; ++ct) {
+  const int g = ct * t.tg + threadIdx.x % t.tg;
   double s[2][4] = {};
   if (g < t.G) {
     const int c0 = 4 * g;
@@ -358,8 +360,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(StepArgs a, int slot, T* _
       any |= act[j];
     }
     if (any) {
-      const int r1 = min(chunk * t.ch + t.ch, t.n);
-      for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
+      for_rows(t, [&](int row) {
         const size_t o = size_t(row) * t.rp + c0;
         V4<T> xv = ld4(x + o), rv = ld4(r + o);
         const V4<T> pv = ld4(p + o), qv = ld4(q + o);
@@ -375,10 +376,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(StepArgs a, int slot, T* _
         }
         st4(x + o, xv);
         st4(r + o, rv);
-      }
+      });
     }
   }
-  block_store<2>(t, s, a.part, chunk, ct);
+  block_store<2>(t, s, a.part, blockIdx.x, ct);
+  }
 }
 
 __global__ void k_red_beta(StepArgs a, int slot, int next) {
@@ -411,10 +413,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_p(StepArgs a, int next, T*
                                                         const T* __restrict__ dinv) {
   if (a.ring[next] == 0) return;
   const Tile& t = a.t;
-  int chunk, ct;
-  tile_block(t, chunk, ct);
-  const int rl = threadIdx.x / t.tg, g = ct * t.tg + threadIdx.x % t.tg;
-  if (g >= t.G) return;
+  for (int ct = 0; ct < t.nct; ++ct) {
+  const int g = ct * t.tg + threadIdx.x % t.tg;
+  if (g >= t.G) continue;
   const int c0 = 4 * g;
   int act[4];
   T be[4];
@@ -424,9 +425,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_p(StepArgs a, int next, T*
     be[j] = T(a.cg.beta[c0 + j]);
     any |= act[j];
   }
-  if (!any) return;
-  const int r1 = min(chunk * t.ch + t.ch, t.n);
-  for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
+  if (!any) continue;
+  for_rows(t, [&](int row) {
     const size_t o = size_t(row) * t.rp + c0;
     V4<T> pv = ld4(p + o);
     const V4<T> rv = ld4(r + o);
@@ -434,6 +434,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_p(StepArgs a, int next, T*
     for (int j = 0; j < 4; ++j)
       if (act[j]) pv.v[j] = fma(be[j], pv.v[j], di * rv.v[j]);
     st4(p + o, pv);
+  });
   }
 }
 
@@ -442,16 +443,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_p(StepArgs a, int next, T*
 __global__ __launch_bounds__(kBlock) void k_init_outer(StepArgs a, const double* __restrict__ u,
                                                        double* __restrict__ r64) {
   const Tile& t = a.t;
-  int chunk, ct;
-  tile_block(t, chunk, ct);
-  const int rl = threadIdx.x / t.tg, g = ct * t.tg + threadIdx.x % t.tg;
+  for (int ct = 0; ct < t.nct; ++ct) {
+  const int g = ct * t.tg + threadIdx.x % t.tg;
   double s[2][4] = {};
   if (g < t.G) {
     const int c0 = 4 * g;
     double lv[4];
     for (int j = 0; j < 4; ++j) lv[j] = a.ct.live[c0 + j] ? 1.0 : 0.0;
-    const int r1 = min(chunk * t.ch + t.ch, t.n);
-    for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
+    for_rows(t, [&](int row) {
       double au[4] = {}, mu[4] = {};
       for_neighbors(a, row, c0, u, [&](int, const V4<double>& x, size_t o) {
         const double va = a.A64[o], vm = a.M64[o];
@@ -467,9 +466,10 @@ __global__ __launch_bounds__(kBlock) void k_init_outer(StepArgs a, const double*
         s[1][j] += rv.v[j] * rv.v[j];
       }
       st4(r64 + size_t(row) * t.rp + c0, rv);
-    }
+    });
   }
-  block_store<2>(t, s, a.part, chunk, ct);
+  block_store<2>(t, s, a.part, blockIdx.x, ct);
+  }
 }
 
 __global__ void k_red_outer_init(StepArgs a) {
@@ -497,16 +497,14 @@ __global__ __launch_bounds__(kBlock) void k_inner_init(StepArgs a, int oslot,
   if (blockIdx.x == 0 && threadIdx.x == 0) a.ring[0] = 0;
   if (a.oring[oslot] == 0) return;
   const Tile& t = a.t;
-  int chunk, ct;
-  tile_block(t, chunk, ct);
-  const int rl = threadIdx.x / t.tg, g = ct * t.tg + threadIdx.x % t.tg;
+  for (int ct = 0; ct < t.nct; ++ct) {
+  const int g = ct * t.tg + threadIdx.x % t.tg;
   double s[2][4] = {};
   if (g < t.G) {
     const int c0 = 4 * g;
     int act[4];
     for (int j = 0; j < 4; ++j) act[j] = a.cg.act_o[c0 + j];
-    const int r1 = min(chunk * t.ch + t.ch, t.n);
-    for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
+    for_rows(t, [&](int row) {
       const size_t o = size_t(row) * t.rp + c0;
       const V4<double> rd = ld4(r64 + o);
       const float di = a.dinv32[row];
@@ -520,9 +518,10 @@ __global__ __launch_bounds__(kBlock) void k_inner_init(StepArgs a, int oslot,
       st4(d + o, dv);
       st4(r + o, rv);
       st4(p + o, pv);
-    }
+    });
   }
-  block_store<2>(t, s, a.part, chunk, ct);
+  block_store<2>(t, s, a.part, blockIdx.x, ct);
+  }
 }
 
 __global__ void k_red_inner_init(StepArgs a, int oslot, int onext) {
@@ -561,9 +560,8 @@ __global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot, 
                                                          float* __restrict__ dacc) {
   if (!guess && a.oring[oslot] == 0) return;
   const Tile& t = a.t;
-  int chunk, ct;
-  tile_block(t, chunk, ct);
-  const int rl = threadIdx.x / t.tg, g = ct * t.tg + threadIdx.x % t.tg;
+  for (int ct = 0; ct < t.nct; ++ct) {
+  const int g = ct * t.tg + threadIdx.x % t.tg;
   const int* mask = guess ? a.ct.live : a.cg.act_o;
   double s[1][4] = {};
   if (g < t.G) {
@@ -574,8 +572,7 @@ __global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot, 
       any |= act[j];
     }
     if (any) {
-      const int r1 = min(chunk * t.ch + t.ch, t.n);
-      for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
+      for_rows(t, [&](int row) {
         double kd[4] = {};
         float dd[4] = {};
         for_neighbors(a, row, c0, d, [&](int k, const V4<float>& x, size_t o) {
@@ -601,10 +598,11 @@ __global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot, 
             if (act[j]) av.v[j] += dd[j];
           st4(dacc + o, av);
         }
-      }
+      });
     }
   }
-  block_store<1>(t, s, a.part + (guess ? part_off(t, 1) : 0), chunk, ct);
+  block_store<1>(t, s, a.part + (guess ? part_off(t, 1) : 0), blockIdx.x, ct);
+  }
 }
 
 __global__ void k_red_outer(StepArgs a, int oslot, int onext) {
@@ -631,10 +629,9 @@ __global__ void k_red_outer(StepArgs a, int oslot, int onext) {
 __global__ __launch_bounds__(kBlock) void k_nodal(StepArgs a, const double* __restrict__ u,
                                                   double* __restrict__ out) {
   const Tile& t = a.t;
-  int chunk, ct;
-  tile_block(t, chunk, ct);
-  const int rl = threadIdx.x / t.tg, g = ct * t.tg + threadIdx.x % t.tg;
-  if (g >= t.G) return;
+  for (int ct = 0; ct < t.nct; ++ct) {
+  const int g = ct * t.tg + threadIdx.x % t.tg;
+  if (g >= t.G) continue;
   const int c0 = 4 * g;
   int lo[4], len[4], lv[4];
   double cf[4];
@@ -644,9 +641,8 @@ __global__ __launch_bounds__(kBlock) void k_nodal(StepArgs a, const double* __re
     lv[j] = a.ct.live[c0 + j];
     cf[j] = a.ct.coef[c0 + j];
   }
-  if (!(lv[0] | lv[1] | lv[2] | lv[3])) return;
-  const int r1 = min(chunk * t.ch + t.ch, t.n);
-  for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
+  if (!(lv[0] | lv[1] | lv[2] | lv[3])) continue;
+  for_rows(t, [&](int row) {
     const double* ur = u + size_t(row) * t.rp;
     V4<double> uv = ld4(ur + c0), ov = uv;
     double S = 0.0;
@@ -665,15 +661,15 @@ __global__ __launch_bounds__(kBlock) void k_nodal(StepArgs a, const double* __re
       ov.v[j] = x * exp(-cf[j] * (S - x * x));
     }
     st4(out + size_t(row) * t.rp + c0, ov);
+  });
   }
 }
 
 // ---------------------------------------------------------- normalisation --
 __global__ __launch_bounds__(kBlock) void k_norm_dot(StepArgs a, const double* __restrict__ v) {
   const Tile& t = a.t;
-  int chunk, ct;
-  tile_block(t, chunk, ct);
-  const int rl = threadIdx.x / t.tg, g = ct * t.tg + threadIdx.x % t.tg;
+  for (int ct = 0; ct < t.nct; ++ct) {
+  const int g = ct * t.tg + threadIdx.x % t.tg;
   double s[1][4] = {};
   if (g < t.G) {
     const int c0 = 4 * g;
@@ -683,8 +679,7 @@ __global__ __launch_bounds__(kBlock) void k_norm_dot(StepArgs a, const double* _
       any |= lv[j];
     }
     if (any) {
-      const int r1 = min(chunk * t.ch + t.ch, t.n);
-      for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
+      for_rows(t, [&](int row) {
         double mv[4] = {};
         V4<double> vd = {};
         for_neighbors(a, row, c0, v, [&](int k, const V4<double>& x, size_t o) {
@@ -694,10 +689,11 @@ __global__ __launch_bounds__(kBlock) void k_norm_dot(StepArgs a, const double* _
         });
         for (int j = 0; j < 4; ++j)
           if (lv[j]) s[0][j] += vd.v[j] * mv[j];
-      }
+      });
     }
   }
-  block_store<1>(t, s, a.part, chunk, ct);
+  block_store<1>(t, s, a.part, blockIdx.x, ct);
+  }
 }
 
 __global__ void k_red_norm(StepArgs a) {
@@ -711,10 +707,9 @@ __global__ void k_red_norm(StepArgs a) {
 __global__ __launch_bounds__(kBlock) void k_scale(StepArgs a, const double* __restrict__ v,
                                                   double* __restrict__ u) {
   const Tile& t = a.t;
-  int chunk, ct;
-  tile_block(t, chunk, ct);
-  const int rl = threadIdx.x / t.tg, g = ct * t.tg + threadIdx.x % t.tg;
-  if (g >= t.G) return;
+  for (int ct = 0; ct < t.nct; ++ct) {
+  const int g = ct * t.tg + threadIdx.x % t.tg;
+  if (g >= t.G) continue;
   const int c0 = 4 * g;
   int lv[4], any = 0;
   double inv[4];
@@ -723,15 +718,15 @@ __global__ __launch_bounds__(kBlock) void k_scale(StepArgs a, const double* __re
     any |= lv[j];
     inv[j] = 1.0 / a.cg.nrm[c0 + j];
   }
-  if (!any) return;
-  const int r1 = min(chunk * t.ch + t.ch, t.n);
-  for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
+  if (!any) continue;
+  for_rows(t, [&](int row) {
     const size_t o = size_t(row) * t.rp + c0;
     const V4<double> vv = ld4(v + o);
     V4<double> uv = ld4(u + o);
     for (int j = 0; j < 4; ++j)
       if (lv[j]) uv.v[j] = vv.v[j] * inv[j];
     st4(u + o, uv);
+  });
   }
 }
 
@@ -739,9 +734,8 @@ __global__ __launch_bounds__(kBlock) void k_scale(StepArgs a, const double* __re
 // Rayleigh quotient parts u.Au and u.Mu per column.
 __global__ __launch_bounds__(kBlock) void k_energy_rq(StepArgs a, const double* __restrict__ u) {
   const Tile& t = a.t;
-  int chunk, ct;
-  tile_block(t, chunk, ct);
-  const int rl = threadIdx.x / t.tg, g = ct * t.tg + threadIdx.x % t.tg;
+  for (int ct = 0; ct < t.nct; ++ct) {
+  const int g = ct * t.tg + threadIdx.x % t.tg;
   double s[2][4] = {};
   if (g < t.G) {
     const int c0 = 4 * g;
@@ -751,8 +745,7 @@ __global__ __launch_bounds__(kBlock) void k_energy_rq(StepArgs a, const double* 
       any |= lv[j];
     }
     if (any) {
-      const int r1 = min(chunk * t.ch + t.ch, t.n);
-      for (int row = chunk * t.ch + rl; row < r1; row += t.tr) {
+      for_rows(t, [&](int row) {
         double au[4] = {}, mu[4] = {};
         V4<double> ud = {};
         for_neighbors(a, row, c0, u, [&](int k, const V4<double>& x, size_t o) {
@@ -768,10 +761,11 @@ __global__ __launch_bounds__(kBlock) void k_energy_rq(StepArgs a, const double* 
             s[0][j] += ud.v[j] * au[j];
             s[1][j] += ud.v[j] * mu[j];
           }
-      }
+      });
     }
   }
-  block_store<2>(t, s, a.part, chunk, ct);
+  block_store<2>(t, s, a.part, blockIdx.x, ct);
+  }
 }
 
 // S_eps element kernel.  On a triangle T the P1 functions are u_i = sum_p
@@ -960,23 +954,24 @@ inline unsigned colblocks(const Tile& t) { return nblocks(size_t(t.rp), kRC); }
 
 }  // namespace
 
-Tile make_tile(int n, int rp, int tg_cap, int target_blocks) {
+Tile make_tile(int n, int rp) {
   Tile t;
   t.n = n;
   t.rp = rp;
-  t.G = tg_cap > 64 ? rp : rp / 4;  // triangle tiles use one restart per "group"
+  t.G = rp / 4;
   int tg = 1;
-  while (tg < t.G && tg < tg_cap) tg <<= 1;
+  while (tg < t.G && tg < 64) tg <<= 1;
   t.tg = tg;
   t.tr = kBlock / tg;
   t.nct = (t.G + tg - 1) / tg;
-  int want_chunks = std::max(1, target_blocks / t.nct);
-  int ch = (n + want_chunks - 1) / want_chunks;
-  ch = ((ch + t.tr - 1) / t.tr) * t.tr;
-  if (ch < t.tr) ch = t.tr;
-  t.ch = ch;
-  t.nchunk = (n + ch - 1) / ch;
-  t.nblk = t.nchunk * t.nct;
+  t.xrows = (n + 7) / 8;
+  // up to 4 passes per chunk, as long as a range still has >= 256 chunks
+  int passes = std::max(1, std::min(4, t.xrows / (t.tr * 256)));
+  t.ch = t.tr * passes;
+  t.nchx = std::max(1, (t.xrows + t.ch - 1) / t.ch);
+  t.nper = std::min(t.nchx, 256);
+  t.nblk = 8 * t.nper;
+  t.nchunk = t.nblk;
   return t;
 }
 
