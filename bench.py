@@ -162,6 +162,7 @@ def main():
                "outer_sweeps_per_step": (s1["outer_sweeps"] - s0["outer_sweeps"]) / args.steps,
                "converged": s1["converged"]},
         "roofline": roofline,
+        "tiling": st.tiling(),
     }
 
     if not args.no_plain:

@@ -22,7 +22,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsegpart.so")
 
 ARCH = "gfx950"
-SOURCES = ["kernels.hip", "mesh.cpp", "engine.cpp", "server.cpp", "capi.cpp"]
+SOURCES = ["kernels.hip", "mesh.cpp", "engine.cpp", "autotune.cpp", "server.cpp", "capi.cpp"]
 
 
 def hipcc():

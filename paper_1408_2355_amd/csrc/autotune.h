@@ -1,0 +1,25 @@
+// Tiling autotuner cache.  A tiling of the row-parallel kernels is chosen by
+// timing the CG matrix product for a set of candidate (lanes per row, passes
+// per chunk, workgroups per XCD range) on the first solver of a given
+// (mesh size, ELL width, column count, precision, device); the winner is kept
+// in a process-wide table and, when SEGPART_TUNE_CACHE names a file, in that
+// JSON file as well (read at first use, rewritten after each new entry).
+#pragma once
+
+#include <string>
+
+namespace sp {
+
+struct TuneChoice {
+  int tg_cap = 64;
+  int passes = 1;
+  int nper_cap = 256;
+  double us = 0.0;  // measured time of one matrix product
+};
+
+bool tune_lookup(const std::string& key, TuneChoice* out);
+void tune_store(const std::string& key, const TuneChoice& c);
+// 1 = tune, 0 = default tiling; from SEGPART_AUTOTUNE if set, else `dflt`.
+bool tune_enabled(bool dflt);
+
+}  // namespace sp

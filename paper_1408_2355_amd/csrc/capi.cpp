@@ -337,6 +337,19 @@ int sp_state_kernel_time(sp_state* st, int32_t which, int64_t* launches, double*
   });
 }
 
+int sp_state_tiling(sp_state* st, int32_t* lanes_per_row, int32_t* rows_per_chunk,
+                    int32_t* groups_per_xcd, double* matvec_us) {
+  return guard([&] {
+    SP_REQUIRE(st && st->solver, SP_EINVAL, "NULL state");
+    const sp::Tile& t = st->solver->tile();
+    if (lanes_per_row) *lanes_per_row = t.tg;
+    if (rows_per_chunk) *rows_per_chunk = t.ch;
+    if (groups_per_xcd) *groups_per_xcd = t.nper;
+    if (matvec_us) *matvec_us = st->solver->tuned_us();
+    return SP_OK;
+  });
+}
+
 void sp_state_destroy(sp_state* st) { delete st; }
 
 int sp_server_create(int64_t hbm_budget_bytes, int32_t max_batch_columns, sp_server** out) {

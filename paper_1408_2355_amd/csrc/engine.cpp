@@ -15,6 +15,8 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 namespace sp {
@@ -99,7 +101,11 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
       q32_.alloc(nv);
       if (prm_.extrapolate) dprev_.alloc(nv);
     }
-    part_.alloc(3 * size_t(t.nchunk) * rp_);
+    // partial sums: one row per workgroup, sized for the widest tiling the
+    // autotuner may pick
+    int max_blk = t.nblk;
+    for (const Tile& c : tile_candidates()) max_blk = std::max(max_blk, c.nblk);
+    part_.alloc(3 * size_t(max_blk) * rp_);
     part_s_.alloc(size_t(sp_.nchunk) * nres_p_);
     colf_.alloc(size_t(CF_N) * rp_ + nres_p_);
     coli_.alloc(size_t(CI_N) * rp_ + 3 * size_t(nres_p_));
@@ -188,6 +194,7 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     }
     push_tables();
     hist_.assign(nres, {});
+    autotune();
   } catch (...) {
     if (h_poll_) (void)hipHostFree(h_poll_);
     h_poll_ = nullptr;
@@ -205,6 +212,86 @@ Solver::~Solver() {
     for (auto x : e) (void)hipEventDestroy(x);
   if (h_poll_) (void)hipHostFree(h_poll_);
   if (own_stream_) (void)hipStreamDestroy(s_);
+}
+
+std::vector<Tile> Solver::tile_candidates() const {
+  std::vector<Tile> out;
+  const int n = int(mesh_->n);
+  for (int tg : {16, 32, 64})
+    for (int passes : {1, 2, 4})
+      for (int nper : {64, 128, 256}) {
+        Tile c = make_tile(n, rp_, tg, passes, nper);
+        bool dup = false;
+        for (const Tile& o : out)
+          dup |= o.tg == c.tg && o.ch == c.ch && o.nper == c.nper;
+        if (!dup) out.push_back(c);
+      }
+  return out;
+}
+
+// Pick the tiling of the row-parallel kernels by timing the CG matrix
+// product (the kernel with the gathers) for every candidate, once per
+// (mesh size, ELL width, columns, precision, device); see autotune.h.
+void Solver::autotune() {
+  const size_t work = size_t(mesh_->n) * size_t(rp_);
+  if (!tune_enabled(work >= (size_t(1) << 22))) return;
+  int dev = 0;
+  SP_HIP(hipGetDevice(&dev));
+  const bool f64 = prm_.precision == SP_FP64;
+  const std::string key = "n" + std::to_string(mesh_->n) + "_W" + std::to_string(mesh_->W) +
+                          "_rp" + std::to_string(rp_) + (f64 ? "_f64" : "_f32") + "_dev" +
+                          std::to_string(dev);
+  TuneChoice best;
+  if (!tune_lookup(key, &best)) {
+    // every column active, a nonzero iteration counter, p = 1
+    k::fill_i32(args_.cg.act, 1, rp_, s_);
+    k::fill_i32(ring_.p, 1, 1, s_);
+    const size_t nv = size_t(mesh_->n) * rp_;
+    if (f64)
+      k::fill_f64(p64_.p, 1.0, nv, s_);
+    else
+      k::fill_f32(p32_.p, 1.0f, nv, s_);
+    hipEvent_t e0, e1;
+    SP_HIP(hipEventCreate(&e0));
+    SP_HIP(hipEventCreate(&e1));
+    best.us = 1e30;
+    const Tile keep = args_.t;
+    for (const Tile& c : tile_candidates()) {
+      args_.t = c;
+      auto launch = [&] {
+        if (f64)
+          k::matvec<double>(args_, km_->K64.p, p64_.p, q64_.p, s_);
+        else
+          k::matvec<float>(args_, km_->K32.p, p32_.p, q32_.p, s_);
+      };
+      launch();
+      SP_HIP(hipEventRecord(e0, s_));
+      for (int i = 0; i < 3; ++i) launch();
+      SP_HIP(hipEventRecord(e1, s_));
+      SP_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      SP_HIP(hipEventElapsedTime(&ms, e0, e1));
+      const double us = 1e3 * ms / 3.0;
+      if (std::getenv("SEGPART_TUNE_VERBOSE"))
+        std::fprintf(stderr, "[segpart tune] %s lanes=%d chunk=%d groups/xcd=%d: %.1f us\n",
+                     key.c_str(), c.tg, c.ch, c.nper, us);
+      if (us < best.us) {
+        best.us = us;
+        best.tg_cap = c.tg;
+        best.passes = c.ch / c.tr;
+        best.nper_cap = c.nper;
+      }
+    }
+    args_.t = keep;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    k::fill_i32(args_.cg.act, 0, rp_, s_);
+    k::fill_i32(ring_.p, 0, ring_.n, s_);
+    SP_HIP(hipStreamSynchronize(s_));
+    tune_store(key, best);
+  }
+  args_.t = make_tile(int(mesh_->n), rp_, best.tg_cap, best.passes, best.nper_cap);
+  tuned_ = best;
 }
 
 void Solver::push_tables() {

@@ -7,6 +7,7 @@
 #include <utility>
 #include <vector>
 
+#include "autotune.h"
 #include "kernels.h"
 
 namespace sp {
@@ -77,6 +78,7 @@ class Solver {
   const double* d_energy() const { return energy_.p; }
   double* d_u() { return u_.p; }
   const Tile& tile() const { return args_.t; }
+  double tuned_us() const { return tuned_.us; }
   const sp_params& params() const { return prm_; }
   Mesh* mesh() const { return mesh_; }
 
@@ -109,6 +111,9 @@ class Solver {
   void norm_dot_scale(const double* v);
   int poll(const int* dev_counter);
   void push_tables();
+  std::vector<Tile> tile_candidates() const;
+  void autotune();
+  TuneChoice tuned_{};
 
   Mesh* mesh_;
   TauMats* km_;

@@ -86,7 +86,10 @@ struct Tile {
   int nblk = 8;    // workgroups (8 * nper)
   int nchunk = 8;  // rows of the partial-sum arrays (= nblk)
 };
-Tile make_tile(int n, int rp);
+constexpr int kMaxPer = 256;  // workgroups per XCD range at most (partials sized for 8 x this)
+// tg_cap: lanes-per-row cap (1..64, rounded to a power of two); passes: row
+// passes per chunk; nper_cap: workgroups per XCD range.
+Tile make_tile(int n, int rp, int tg_cap = 64, int passes = 1, int nper_cap = kMaxPer);
 
 // Per-time-step matrices for one tau: K = M + tau A in float64 and float32,
 // and the inverse diagonals used by the Jacobi preconditioner.

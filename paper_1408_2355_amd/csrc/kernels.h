@@ -82,6 +82,10 @@ void red_init_fp64(const StepArgs& a, hipStream_t s);
 template <typename T>
 void cg_iter(const StepArgs& a, int it, T* x, T* r, T* p, T* q, const T* K, const T* dinv,
              hipStream_t s, const hipEvent_t* ev);
+// the CG matrix product alone (q = K p over the active columns; needs
+// ring[0] != 0), used to time tilings
+template <typename T>
+void matvec(const StepArgs& a, const T* K, const T* p, T* q, hipStream_t s);
 // mixed precision refinement
 void init_outer(const StepArgs& a, const double* u, double* r64, hipStream_t s);
 void red_outer_init(const StepArgs& a, hipStream_t s);

@@ -954,22 +954,22 @@ inline unsigned colblocks(const Tile& t) { return nblocks(size_t(t.rp), kRC); }
 
 }  // namespace
 
-Tile make_tile(int n, int rp) {
+Tile make_tile(int n, int rp, int tg_cap, int passes, int nper_cap) {
   Tile t;
   t.n = n;
   t.rp = rp;
   t.G = rp / 4;
+  tg_cap = std::max(1, std::min(tg_cap, 64));
   int tg = 1;
-  while (tg < t.G && tg < 64) tg <<= 1;
+  while (tg < t.G && tg < tg_cap) tg <<= 1;
   t.tg = tg;
   t.tr = kBlock / tg;
   t.nct = (t.G + tg - 1) / tg;
   t.xrows = (n + 7) / 8;
-  // up to 4 passes per chunk, as long as a range still has >= 256 chunks
-  int passes = std::max(1, std::min(4, t.xrows / (t.tr * 256)));
+  passes = std::max(1, passes);
   t.ch = t.tr * passes;
   t.nchx = std::max(1, (t.xrows + t.ch - 1) / t.ch);
-  t.nper = std::min(t.nchx, 256);
+  t.nper = std::max(1, std::min(t.nchx, std::min(nper_cap, kMaxPer)));
   t.nblk = 8 * t.nper;
   t.nchunk = t.nblk;
   return t;
@@ -1043,6 +1043,14 @@ void cg_iter(const StepArgs& a, int it, T* x, T* r, T* p, T* q, const T* K, cons
   if (ev) SP_HIP(hipEventRecord(ev[5], s));
   SP_LAUNCH_CHECK();
 }
+
+template <typename T>
+void matvec(const StepArgs& a, const T* K, const T* p, T* q, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_spmm<T>, dim3(a.t.nblk), dim3(kBlock), 0, s, a, 0, K, p, q);
+  SP_LAUNCH_CHECK();
+}
+template void matvec<double>(const StepArgs&, const double*, const double*, double*, hipStream_t);
+template void matvec<float>(const StepArgs&, const float*, const float*, float*, hipStream_t);
 
 template void cg_iter<double>(const StepArgs&, int, double*, double*, double*, double*,
                               const double*, const double*, hipStream_t, const hipEvent_t*);

@@ -83,6 +83,7 @@ _SIGS = {
     "sp_state_stats": (C.c_int, [P, C.POINTER(sp_stats)]),
     "sp_state_profile": (C.c_int, [P, C.c_int32]),
     "sp_state_kernel_time": (C.c_int, [P, C.c_int32, I64, D, D]),
+    "sp_state_tiling": (C.c_int, [P, I32, I32, I32, D]),
     "sp_state_destroy": (None, [P]),
     "sp_server_create": (C.c_int, [C.c_int64, C.c_int32, PP]),
     "sp_server_submit": (C.c_int, [P, P, C.POINTER(sp_params), C.c_int32, I32, D, D, I64]),
@@ -311,6 +312,13 @@ class State:
         _check(lib().sp_state_kernel_time(self.h, int(which), C.byref(n), C.byref(ms),
                                           C.byref(b)))
         return n.value, ms.value, b.value
+
+    def tiling(self):
+        """Tiling of the row-parallel kernels (see sp_state_tiling)."""
+        a, b, c, us = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
+        _check(lib().sp_state_tiling(self.h, C.byref(a), C.byref(b), C.byref(c), C.byref(us)))
+        return dict(lanes_per_row=a.value, rows_per_chunk=b.value, groups_per_xcd=c.value,
+                    matvec_us=us.value)
 
     def close(self):
         if getattr(self, "h", None):
