@@ -127,33 +127,27 @@ __device__ __forceinline__ void count_active(int flag, int* counter) {
   if ((threadIdx.x & 63) == 0 && bal) atomicAdd(counter, __popcll(bal));
 }
 
-// ELL row product helper.  For rows of width W <= kWFast all neighbour
-// indices are loaded first and then all neighbour vectors are requested
-// before any is used, so each thread keeps up to kWFast gathers in flight
-// (the loop is unrolled; slots >= W are predicated off).  f(k, x_k, o) gets
-// the slot, the neighbour's 4 column values and the matrix offset o = k*n+row.
-constexpr int kWFast = 8;
+// ELL row product helper.  The ELL width W is a multiple of kSlots (the mesh
+// pads it; padding slots point at the row itself with value 0), so slots are
+// walked in groups of kSlots with straight-line code: all indices of a group
+// are loaded, then all neighbour vectors are requested, then used, so a
+// thread keeps kSlots gathers in flight.  f(k, x_k, o) gets the slot, the
+// neighbour's 4 column values and the matrix offset o = k*n + row.
+constexpr int kSlots = 8;
 
 template <typename T, typename F>
 __device__ __forceinline__ void for_neighbors(const StepArgs& a, int row, int c0,
                                               const T* __restrict__ x, F&& f) {
-  const int W = a.W, n = a.t.n, rp = a.t.rp;
-  if (W <= kWFast) {
-    int idx[kWFast];
+  const int n = a.t.n, rp = a.t.rp;
+  for (int kb = 0; kb < a.W; kb += kSlots) {
+    int idx[kSlots];
 #pragma unroll
-    for (int k = 0; k < kWFast; ++k) idx[k] = k < W ? a.cols[size_t(k) * n + row] : row;
-    V4<T> xv[kWFast];
+    for (int k = 0; k < kSlots; ++k) idx[k] = a.cols[size_t(kb + k) * n + row];
+    V4<T> xv[kSlots];
 #pragma unroll
-    for (int k = 0; k < kWFast; ++k)
-      if (k < W) xv[k] = ld4(x + size_t(idx[k]) * rp + c0);
+    for (int k = 0; k < kSlots; ++k) xv[k] = ld4(x + size_t(idx[k]) * rp + c0);
 #pragma unroll
-    for (int k = 0; k < kWFast; ++k)
-      if (k < W) f(k, xv[k], size_t(k) * n + row);
-  } else {
-    for (int k = 0; k < W; ++k) {
-      const size_t o = size_t(k) * n + row;
-      f(k, ld4(x + size_t(a.cols[o]) * rp + c0), o);
-    }
+    for (int k = 0; k < kSlots; ++k) f(kb + k, xv[k], size_t(kb + k) * n + row);
   }
 }
 

@@ -153,6 +153,9 @@ Mesh* mesh_create(int64_t n, const double* xyz, int64_t nt, const int32_t* tri) 
   int W = 0;
   for (int64_t i = 0; i < n; ++i) W = std::max<int>(W, int(ptr[i + 1] - ptr[i]) + 1);
   SP_REQUIRE(W <= 64, SP_EMESH, "mesh: a vertex has more than 63 neighbours");
+  // The row kernels walk slots in unrolled groups of 8; pad the width to a
+  // multiple of 8 (padding slots point at the row itself with value 0).
+  W = (W + 7) / 8 * 8;
   M->W = W;
   M->nnz = n + int64_t(uedge.size()) * 2;
 
