@@ -222,10 +222,12 @@ enum { SP_KERNEL_MATVEC = 0, SP_KERNEL_UPDATE = 1, SP_KERNEL_DIRECTION = 2 };
  * float32 vectors in SP_MIXED, float64 in SP_FP64. */
 int sp_state_kernel_time(sp_state* st, int32_t which, int64_t* launches, double* total_ms,
                          double* bytes_per_launch);
-/* Tiling the state's row-parallel kernels use: lanes per vertex row (each
- * lane owns 4 columns), rows per chunk, workgroups per XCD row range, and the
- * autotuner's measured time (us) of one matrix product with it (0 when the
- * default tiling was used: small problems or SEGPART_AUTOTUNE=0).  Nullable. */
+/* Tiling the state's matrix-product kernels use (the autotuned one): lanes
+ * per vertex row (each lane owns 4 columns), rows per chunk, workgroups per
+ * XCD row range, and the autotuner's measured time (us) of one matrix product
+ * with it (0 when the default tiling was used: small problems or
+ * SEGPART_AUTOTUNE=0).  The streaming vector kernels always use the widest
+ * tiling.  Nullable outputs. */
 int sp_state_tiling(sp_state* st, int32_t* lanes_per_row, int32_t* rows_per_chunk,
                     int32_t* groups_per_xcd, double* matvec_us);
 void sp_state_destroy(sp_state* st);

@@ -341,7 +341,7 @@ int sp_state_tiling(sp_state* st, int32_t* lanes_per_row, int32_t* rows_per_chun
                     int32_t* groups_per_xcd, double* matvec_us) {
   return guard([&] {
     SP_REQUIRE(st && st->solver, SP_EINVAL, "NULL state");
-    const sp::Tile& t = st->solver->tile();
+    const sp::Tile& t = st->solver->gather_tile();
     if (lanes_per_row) *lanes_per_row = t.tg;
     if (rows_per_chunk) *rows_per_chunk = t.ch;
     if (groups_per_xcd) *groups_per_xcd = t.nper;

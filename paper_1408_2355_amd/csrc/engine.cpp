@@ -127,7 +127,8 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     k::fill_f64(energy_.p, 0.0, energy_.n, s_);
 
     StepArgs& a = args_;
-    a.t = t;
+    a.t = t;   // streaming kernels: widest tiling (most workgroups in flight)
+    a.tm = t;  // gathering kernels: replaced by the autotuner's pick
     a.W = mesh_->W;
     a.cols = mesh_->cols.p;
     a.M64 = mesh_->M64.p;
@@ -255,9 +256,9 @@ void Solver::autotune() {
     SP_HIP(hipEventCreate(&e0));
     SP_HIP(hipEventCreate(&e1));
     best.us = 1e30;
-    const Tile keep = args_.t;
+    const Tile keep = args_.tm;
     for (const Tile& c : tile_candidates()) {
-      args_.t = c;
+      args_.tm = c;
       auto launch = [&] {
         if (f64)
           k::matvec<double>(args_, km_->K64.p, p64_.p, q64_.p, s_);
@@ -282,7 +283,7 @@ void Solver::autotune() {
         best.nper_cap = c.nper;
       }
     }
-    args_.t = keep;
+    args_.tm = keep;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     k::fill_i32(args_.cg.act, 0, rp_, s_);
@@ -290,7 +291,7 @@ void Solver::autotune() {
     SP_HIP(hipStreamSynchronize(s_));
     tune_store(key, best);
   }
-  args_.t = make_tile(int(mesh_->n), rp_, best.tg_cap, best.passes, best.nper_cap);
+  args_.tm = make_tile(int(mesh_->n), rp_, best.tg_cap, best.passes, best.nper_cap);
   tuned_ = best;
 }
 

@@ -78,6 +78,7 @@ class Solver {
   const double* d_energy() const { return energy_.p; }
   double* d_u() { return u_.p; }
   const Tile& tile() const { return args_.t; }
+  const Tile& gather_tile() const { return args_.tm; }
   double tuned_us() const { return tuned_.us; }
   const sp_params& params() const { return prm_; }
   Mesh* mesh() const { return mesh_; }

@@ -39,7 +39,8 @@ struct CgCols {
 };
 
 struct StepArgs {
-  Tile t;
+  Tile t;   // tiling of the streaming row kernels (no neighbour gathers)
+  Tile tm;  // tiling of the gathering row kernels (matrix products); same n, rp
   int W;
   const int* cols;
   const double* M64;

@@ -236,7 +236,7 @@ __global__ void k_fill(T* p, T v, size_t n) {
 __global__ __launch_bounds__(kBlock) void k_init_fp64(StepArgs a, const double* __restrict__ u,
                                                       double* __restrict__ r,
                                                       double* __restrict__ p) {
-  const Tile& t = a.t;
+  const Tile& t = a.tm;
   for (int ct = 0; ct < t.nct; ++ct) {
   const int g = ct * t.tg + threadIdx.x % t.tg;
   double s[3][4] = {};
@@ -272,12 +272,12 @@ __global__ __launch_bounds__(kBlock) void k_init_fp64(StepArgs a, const double* 
 
 __global__ void k_red_init_fp64(StepArgs a) {
   const int c = red_col();
-  const Tile& t = a.t;
+  const Tile& t = a.tm;
   const double bb = red_sum(a.part + part_off(t, 0), t.nchunk, t.rp, c);
   const double rz = red_sum(a.part + part_off(t, 1), t.nchunk, t.rp, c);
   const double rr = red_sum(a.part + part_off(t, 2), t.nchunk, t.rp, c);
   int act = 0;
-  if (red_lead() && c < a.t.rp) {
+  if (red_lead() && c < a.tm.rp) {
     a.cg.bb[c] = bb;
     a.cg.rz[c] = rz;
     a.cg.tol2[c] = a.rtol2 * bb;
@@ -294,7 +294,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cg_spmm(StepArgs a, int slot, const T* __restrict__ K,
                                                     const T* __restrict__ p, T* __restrict__ q) {
   if (a.ring[slot] == 0) return;
-  const Tile& t = a.t;
+  const Tile& t = a.tm;
   for (int ct = 0; ct < t.nct; ++ct) {
   const int g = ct * t.tg + threadIdx.x % t.tg;
   double s[1][4] = {};
@@ -324,9 +324,9 @@ __global__ void k_red_alpha(StepArgs a, int slot, int next) {
   // columns this iteration works on, summed over iterations (traffic model)
   if (blockIdx.x == 0 && threadIdx.x == 0) a.stat[3] += a.ring[slot];
   const int c = red_col();
-  const bool act = c < a.t.rp && a.cg.act[c];
-  const double pq = red_sum(a.part, act ? a.t.nchunk : 0, a.t.rp, c);
-  if (!red_lead() || c >= a.t.rp) return;
+  const bool act = c < a.tm.rp && a.cg.act[c];
+  const double pq = red_sum(a.part, act ? a.tm.nchunk : 0, a.tm.rp, c);
+  if (!red_lead() || c >= a.tm.rp) return;
   double al = 0.0;
   if (act && pq > 0.0) al = a.cg.rz[c] / pq;
   a.cg.alpha[c] = al;
@@ -436,7 +436,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_p(StepArgs a, int next, T*
 // Outer residual r64 = -tau A u (float64), partials ||M u||^2 and ||r64||^2.
 __global__ __launch_bounds__(kBlock) void k_init_outer(StepArgs a, const double* __restrict__ u,
                                                        double* __restrict__ r64) {
-  const Tile& t = a.t;
+  const Tile& t = a.tm;
   for (int ct = 0; ct < t.nct; ++ct) {
   const int g = ct * t.tg + threadIdx.x % t.tg;
   double s[2][4] = {};
@@ -468,7 +468,7 @@ __global__ __launch_bounds__(kBlock) void k_init_outer(StepArgs a, const double*
 
 __global__ void k_red_outer_init(StepArgs a) {
   const int c = red_col();
-  const Tile& t = a.t;
+  const Tile& t = a.tm;
   const double bb = red_sum(a.part + part_off(t, 0), t.nchunk, t.rp, c);
   const double rr = red_sum(a.part + part_off(t, 1), t.nchunk, t.rp, c);
   int act = 0;
@@ -553,7 +553,7 @@ __global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot, 
                                                          const float* __restrict__ d,
                                                          float* __restrict__ dacc) {
   if (!guess && a.oring[oslot] == 0) return;
-  const Tile& t = a.t;
+  const Tile& t = a.tm;
   for (int ct = 0; ct < t.nct; ++ct) {
   const int g = ct * t.tg + threadIdx.x % t.tg;
   const int* mask = guess ? a.ct.live : a.cg.act_o;
@@ -603,8 +603,8 @@ __global__ void k_red_outer(StepArgs a, int oslot, int onext) {
   if (a.oring[oslot] == 0) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) a.stat[1] += 1;
   const int c = red_col();
-  const bool act = c < a.t.rp && a.cg.act_o[c];
-  const double rr = red_sum(a.part, act ? a.t.nchunk : 0, a.t.rp, c);
+  const bool act = c < a.tm.rp && a.cg.act_o[c];
+  const double rr = red_sum(a.part, act ? a.tm.nchunk : 0, a.tm.rp, c);
   int still = 0;
   if (red_lead() && act) {
     a.cg.rr_o[c] = rr;
@@ -661,7 +661,7 @@ __global__ __launch_bounds__(kBlock) void k_nodal(StepArgs a, const double* __re
 
 // ---------------------------------------------------------- normalisation --
 __global__ __launch_bounds__(kBlock) void k_norm_dot(StepArgs a, const double* __restrict__ v) {
-  const Tile& t = a.t;
+  const Tile& t = a.tm;
   for (int ct = 0; ct < t.nct; ++ct) {
   const int g = ct * t.tg + threadIdx.x % t.tg;
   double s[1][4] = {};
@@ -692,9 +692,9 @@ __global__ __launch_bounds__(kBlock) void k_norm_dot(StepArgs a, const double* _
 
 __global__ void k_red_norm(StepArgs a) {
   const int c = red_col();
-  const bool lv = c < a.t.rp && a.ct.live[c];
-  const double s = red_sum(a.part, lv ? a.t.nchunk : 0, a.t.rp, c);
-  if (!red_lead() || c >= a.t.rp) return;
+  const bool lv = c < a.tm.rp && a.ct.live[c];
+  const double s = red_sum(a.part, lv ? a.tm.nchunk : 0, a.tm.rp, c);
+  if (!red_lead() || c >= a.tm.rp) return;
   a.cg.nrm[c] = lv ? sqrt(s) : 1.0;
 }
 
@@ -727,7 +727,7 @@ __global__ __launch_bounds__(kBlock) void k_scale(StepArgs a, const double* __re
 // ---------------------------------------------------------------- energies --
 // Rayleigh quotient parts u.Au and u.Mu per column.
 __global__ __launch_bounds__(kBlock) void k_energy_rq(StepArgs a, const double* __restrict__ u) {
-  const Tile& t = a.t;
+  const Tile& t = a.tm;
   for (int ct = 0; ct < t.nct; ++ct) {
   const int g = ct * t.tg + threadIdx.x % t.tg;
   double s[2][4] = {};
@@ -874,7 +874,7 @@ __global__ __launch_bounds__(kBlock) void k_energy_seps(StepArgs a, SepsPlan sp,
 
 __global__ void k_red_lambda(StepArgs a, double* __restrict__ lam) {
   const int c = red_col();
-  const Tile& t = a.t;
+  const Tile& t = a.tm;
   const bool real = c < t.rp && a.ct.seg_len[c] > 0;
   const double num = red_sum(a.part + part_off(t, 0), real ? t.nchunk : 0, t.rp, c);
   const double den = red_sum(a.part + part_off(t, 1), real ? t.nchunk : 0, t.rp, c);
@@ -1009,7 +1009,7 @@ void flag_nonconv(const StepArgs& a, const int* counter, hipStream_t s) {
 }
 
 void init_fp64(const StepArgs& a, const double* u, double* r, double* p, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_fp64, dim3(a.t.nblk), dim3(kBlock), 0, s, a, u, r, p);
+  hipLaunchKernelGGL(k_init_fp64, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, u, r, p);
   SP_LAUNCH_CHECK();
 }
 
@@ -1023,7 +1023,7 @@ void cg_iter(const StepArgs& a, int it, T* x, T* r, T* p, T* q, const T* K, cons
              hipStream_t s, const hipEvent_t* ev) {
   const int slot = it % kRing, next = (it + 1) % kRing;
   if (ev) SP_HIP(hipEventRecord(ev[0], s));
-  hipLaunchKernelGGL(k_cg_spmm<T>, dim3(a.t.nblk), dim3(kBlock), 0, s, a, slot, K, (const T*)p, q);
+  hipLaunchKernelGGL(k_cg_spmm<T>, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, slot, K, (const T*)p, q);
   if (ev) SP_HIP(hipEventRecord(ev[1], s));
   hipLaunchKernelGGL(k_red_alpha, dim3(colblocks(a.t)), dim3(kBlock), 0, s, a, slot, next);
   if (ev) SP_HIP(hipEventRecord(ev[2], s));
@@ -1040,7 +1040,7 @@ void cg_iter(const StepArgs& a, int it, T* x, T* r, T* p, T* q, const T* K, cons
 
 template <typename T>
 void matvec(const StepArgs& a, const T* K, const T* p, T* q, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_spmm<T>, dim3(a.t.nblk), dim3(kBlock), 0, s, a, 0, K, p, q);
+  hipLaunchKernelGGL(k_cg_spmm<T>, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, 0, K, p, q);
   SP_LAUNCH_CHECK();
 }
 template void matvec<double>(const StepArgs&, const double*, const double*, double*, hipStream_t);
@@ -1052,7 +1052,7 @@ template void cg_iter<float>(const StepArgs&, int, float*, float*, float*, float
                              const float*, hipStream_t, const hipEvent_t*);
 
 void init_outer(const StepArgs& a, const double* u, double* r64, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_outer, dim3(a.t.nblk), dim3(kBlock), 0, s, a, u, r64);
+  hipLaunchKernelGGL(k_init_outer, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, u, r64);
   SP_LAUNCH_CHECK();
 }
 
@@ -1075,13 +1075,13 @@ void red_inner_init(const StepArgs& a, int o, hipStream_t s) {
 
 void outer_update(const StepArgs& a, int o, double* u, double* r64, const float* d, float* dacc,
                   hipStream_t s) {
-  hipLaunchKernelGGL(k_outer_update, dim3(a.t.nblk), dim3(kBlock), 0, s, a, o % kRing, false, u,
+  hipLaunchKernelGGL(k_outer_update, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, o % kRing, false, u,
                      r64, d, dacc);
   SP_LAUNCH_CHECK();
 }
 
 void apply_guess(const StepArgs& a, double* u, double* r64, const float* delta, hipStream_t s) {
-  hipLaunchKernelGGL(k_outer_update, dim3(a.t.nblk), dim3(kBlock), 0, s, a, 0, true, u, r64, delta,
+  hipLaunchKernelGGL(k_outer_update, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, 0, true, u, r64, delta,
                      (float*)nullptr);
   SP_LAUNCH_CHECK();
 }
@@ -1098,7 +1098,7 @@ void nodal(const StepArgs& a, const double* u, double* out, hipStream_t s) {
 }
 
 void norm_dot(const StepArgs& a, const double* v, hipStream_t s) {
-  hipLaunchKernelGGL(k_norm_dot, dim3(a.t.nblk), dim3(kBlock), 0, s, a, v);
+  hipLaunchKernelGGL(k_norm_dot, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, v);
   SP_LAUNCH_CHECK();
 }
 
@@ -1113,7 +1113,7 @@ void scale(const StepArgs& a, const double* v, double* u, hipStream_t s) {
 }
 
 void energy_rq(const StepArgs& a, const double* u, hipStream_t s) {
-  hipLaunchKernelGGL(k_energy_rq, dim3(a.t.nblk), dim3(kBlock), 0, s, a, u);
+  hipLaunchKernelGGL(k_energy_rq, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, u);
   SP_LAUNCH_CHECK();
 }
 
