@@ -83,7 +83,7 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     km_ = mesh_->tau_mats(prm_.tau);
     const int n = int(mesh_->n);
     const size_t nv = size_t(n) * rp_;
-    Tile t = make_tile(n, rp_);
+    Tile t = make_tile(n, rp_, 64, 1, 128);
     sp_.nt = int(mesh_->nt);
     sp_.tchunk = std::max(256, int((mesh_->nt + 1023) / 1024 + 3) / 4 * 4);
     sp_.nchunk = int((mesh_->nt + sp_.tchunk - 1) / sp_.tchunk);
@@ -293,9 +293,40 @@ void Solver::autotune() {
   }
   args_.tm = make_tile(int(mesh_->n), rp_, best.tg_cap, best.passes, best.nper_cap);
   tuned_ = best;
+
+  // S_eps element kernel: LDS-staged or direct corner reads, whichever is
+  // faster for this batch's restart tiles
+  if (sp_.ntile > 0) {
+    hipEvent_t e0, e1;
+    SP_HIP(hipEventCreate(&e0));
+    SP_HIP(hipEventCreate(&e1));
+    double t_mode[2] = {0, 0};
+    for (int mode = 0; mode < 2; ++mode) {
+      sp_.direct = mode;
+      k::energy_seps(args_, sp_, mesh_->tri.p, mesh_->tarea.p, u_.p, part_s_.p, s_);
+      SP_HIP(hipEventRecord(e0, s_));
+      for (int i = 0; i < 2; ++i)
+        k::energy_seps(args_, sp_, mesh_->tri.p, mesh_->tarea.p, u_.p, part_s_.p, s_);
+      SP_HIP(hipEventRecord(e1, s_));
+      SP_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      SP_HIP(hipEventElapsedTime(&ms, e0, e1));
+      t_mode[mode] = ms;
+      if (std::getenv("SEGPART_TUNE_VERBOSE"))
+        std::fprintf(stderr, "[segpart tune] S_eps %s: %.1f us\n", mode ? "direct" : "staged",
+                     500.0 * ms);
+    }
+    sp_.direct = t_mode[1] < t_mode[0] ? 1 : 0;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
 }
 
 void Solver::push_tables() {
+  lam_fresh_ = false;
+  all_live_ = true;
+  for (int c = 0; c < rp_; ++c)
+    if (h_seg_len_[c] > 0 && !h_live_[c]) all_live_ = false;
   const int nres = args_.ct.nres;
   args_.ct.nres = nres;
   SP_HIP(hipMemcpyAsync(const_cast<int*>(args_.ct.seg_lo), h_seg_lo_.data(), rp_ * sizeof(int),
@@ -367,6 +398,7 @@ void Solver::sync() { SP_HIP(hipStreamSynchronize(s_)); }
 void Solver::upload_host(const double* u0, bool normalise) {
   SP_REQUIRE(u0 != nullptr, SP_EINVAL, "NULL u0");
   have_dprev_ = false;
+  lam_fresh_ = false;
   const size_t cnt = size_t(R_) * mesh_->n;
   for (size_t i = 0; i < cnt; ++i)
     SP_REQUIRE(std::isfinite(u0[i]), SP_EINVAL, "u0 holds a non-finite value");
@@ -382,21 +414,23 @@ void Solver::upload_host(const double* u0, bool normalise) {
 void Solver::upload_device(const double* d_u0, bool normalise, bool check_norms) {
   SP_REQUIRE(d_u0 != nullptr, SP_EINVAL, "NULL u0");
   have_dprev_ = false;
+  lam_fresh_ = false;
   k::pack(args_.t, 0, R_, d_u0, mesh_->perm_d.p, u_.p, s_);
   if (normalise) {
     if (check_norms) {
       normalise_columns();
     } else {
       k::norm_dot(args_, u_.p, s_);
-      k::red_norm(args_, s_);
+      k::red_norm(args_, lam_.p, s_);
       k::scale(args_, u_.p, u_.p, s_);
+      lam_fresh_ = all_live_;
     }
   }
 }
 
 void Solver::normalise_columns() {
   k::norm_dot(args_, u_.p, s_);
-  k::red_norm(args_, s_);
+  k::red_norm(args_, lam_.p, s_);
   std::vector<double> nrm(rp_);
   SP_HIP(hipMemcpyAsync(nrm.data(), args_.cg.nrm, rp_ * sizeof(double), hipMemcpyDeviceToHost, s_));
   SP_HIP(hipStreamSynchronize(s_));
@@ -406,11 +440,13 @@ void Solver::normalise_columns() {
                  "a component of u0 has zero (or non-finite) L2 norm (column " +
                      std::to_string(c) + ")");
   k::scale(args_, u_.p, u_.p, s_);
+  lam_fresh_ = all_live_;
 }
 
 void Solver::pack_range(int c_lo, int Rq, const double* d_src) {
   SP_REQUIRE(c_lo >= 0 && Rq >= 0 && c_lo + Rq <= rp_, SP_EINVAL, "column range");
   have_dprev_ = false;  // the new columns have no previous increment
+  lam_fresh_ = false;
   k::pack(args_.t, c_lo, Rq, d_src, mesh_->perm_d.p, u_.p, s_);
 }
 
@@ -496,6 +532,7 @@ void Solver::heat_mixed() {
 }
 
 void Solver::stage_heat() {
+  lam_fresh_ = false;
   if (prm_.precision == SP_FP64)
     heat_fp64();
   else
@@ -506,11 +543,13 @@ void Solver::node_to_r() { k::nodal(args_, u_.p, r64_.p, s_); }
 
 void Solver::norm_dot_scale(const double* v) {
   k::norm_dot(args_, v, s_);
-  k::red_norm(args_, s_);
+  k::red_norm(args_, lam_.p, s_);
   k::scale(args_, v, u_.p, s_);
+  lam_fresh_ = all_live_;
 }
 
 void Solver::stage_node() {
+  lam_fresh_ = false;
   node_to_r();
   k::fill_f64(args_.cg.nrm, 1.0, rp_, s_);
   k::scale(args_, r64_.p, u_.p, s_);
@@ -520,9 +559,12 @@ void Solver::stage_norm() { norm_dot_scale(u_.p); }
 
 void Solver::energy() {
   if (args_.ct.nres == 0) return;
-  k::energy_rq(args_, u_.p, s_);
+  // right after a normalisation of every column the Rayleigh quotients are
+  // already in lam (see red_norm); otherwise evaluate them now
+  const bool need_rq = !lam_fresh_;
+  if (need_rq) k::energy_rq(args_, u_.p, s_);
   k::energy_seps(args_, sp_, mesh_->tri.p, mesh_->tarea.p, u_.p, part_s_.p, s_);
-  k::red_energy(args_, sp_, part_s_.p, lam_.p, seps_.p, energy_.p, s_);
+  k::red_energy(args_, sp_, part_s_.p, need_rq, lam_.p, seps_.p, energy_.p, s_);
 }
 
 void Solver::energy_to_host(double* lam, double* seps, double* E) {

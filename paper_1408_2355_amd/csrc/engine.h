@@ -129,6 +129,8 @@ class Solver {
   DevBuf<float> d32_, r32_, p32_, q32_;
   DevBuf<float> dprev_;      // previous step's heat increment (extrapolated start)
   bool have_dprev_ = false;
+  bool lam_fresh_ = false;  // lam holds the Rayleigh quotients of the current state
+  bool all_live_ = true;    // every real column is live
   DevBuf<double> part_, part_s_;
   DevBuf<double> colf_;  // 8 x rp column doubles + nres_p restart doubles
   DevBuf<int> coli_;     // 7 x rp column ints + 3 x nres_p restart ints

@@ -69,6 +69,7 @@ struct SepsPlan {
   int tchunk = 0;  // triangles per chunk
   int nt = 0;      // triangles
   int nres_p = 0;  // row stride of the partial sums
+  int direct = 0;  // 1 = corners read from global memory, 0 = staged in LDS
 };
 namespace k {
 std::vector<int4> seps_tiles(const std::vector<int>& res_lo, const std::vector<int>& res_len,
@@ -103,13 +104,16 @@ void red_outer(const StepArgs& a, int o, hipStream_t s);
 // node step and normalisation
 void nodal(const StepArgs& a, const double* u, double* out, hipStream_t s);
 void norm_dot(const StepArgs& a, const double* v, hipStream_t s);
-void red_norm(const StepArgs& a, hipStream_t s);
+// M-norms of the live columns of the vector norm_dot saw; lam (nullable)
+// receives their Rayleigh quotients
+void red_norm(const StepArgs& a, double* lam, hipStream_t s);
 void scale(const StepArgs& a, const double* v, double* u, hipStream_t s);
 // energies
 void energy_rq(const StepArgs& a, const double* u, hipStream_t s);
 void energy_seps(const StepArgs& a, const SepsPlan& sp, const int32_t* tri, const double* tarea,
                  const double* u, double* part_s, hipStream_t s);
-void red_energy(const StepArgs& a, const SepsPlan& sp, const double* part_s, double* lam,
+void red_energy(const StepArgs& a, const SepsPlan& sp, const double* part_s, bool with_lambda,
+                double* lam,
                 double* seps, double* energy, hipStream_t s);
 // labels and layout changes
 void labels(const StepArgs& a, const double* u, const int32_t* perm, int32_t* lab,

@@ -109,9 +109,20 @@ __device__ __forceinline__ bool red_lead() { return threadIdx.x < kRC; }
 __device__ __forceinline__ double red_sum(const double* p, int nchunk, int rp, int c) {
   __shared__ double sh[kBlock];
   const int lane = threadIdx.x / kRC, cl = threadIdx.x % kRC;
-  double s = 0.0;
-  if (c < rp)
-    for (int ch = lane; ch < nchunk; ch += kRL) s += p[size_t(ch) * rp + c];
+  // 8 independent accumulators (chunk lane + 8 kRL j + i kRL goes to s[i]),
+  // combined in fixed order: the loads of 8 chunks are in flight together
+  double s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (c < rp) {
+    int ch = lane;
+    for (; ch + 7 * kRL < nchunk; ch += 8 * kRL) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) s8[i] += p[size_t(ch + i * kRL) * rp + c];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (ch + i * kRL < nchunk) s8[i] += p[size_t(ch + i * kRL) * rp + c];
+  }
+  const double s = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
   sh[threadIdx.x] = s;
   __syncthreads();
   double tot = 0.0;
@@ -664,7 +675,7 @@ __global__ __launch_bounds__(kBlock) void k_norm_dot(StepArgs a, const double* _
   const Tile& t = a.tm;
   for (int ct = 0; ct < t.nct; ++ct) {
   const int g = ct * t.tg + threadIdx.x % t.tg;
-  double s[1][4] = {};
+  double s[2][4] = {};
   if (g < t.G) {
     const int c0 = 4 * g;
     int lv[4], any = 0;
@@ -674,28 +685,40 @@ __global__ __launch_bounds__(kBlock) void k_norm_dot(StepArgs a, const double* _
     }
     if (any) {
       for_rows(t, [&](int row) {
-        double mv[4] = {};
+        double mv[4] = {}, av[4] = {};
         V4<double> vd = {};
         for_neighbors(a, row, c0, v, [&](int k, const V4<double>& x, size_t o) {
-          const double w = a.M64[o];
+          const double w = a.M64[o], z = a.A64[o];
           if (k == 0) vd = x;
-          for (int j = 0; j < 4; ++j) mv[j] = fma(w, x.v[j], mv[j]);
+          for (int j = 0; j < 4; ++j) {
+            mv[j] = fma(w, x.v[j], mv[j]);
+            av[j] = fma(z, x.v[j], av[j]);
+          }
         });
         for (int j = 0; j < 4; ++j)
-          if (lv[j]) s[0][j] += vd.v[j] * mv[j];
+          if (lv[j]) {
+            s[0][j] += vd.v[j] * mv[j];
+            s[1][j] += vd.v[j] * av[j];
+          }
       });
     }
   }
-  block_store<1>(t, s, a.part, blockIdx.x, ct);
+  block_store<2>(t, s, a.part, blockIdx.x, ct);
   }
 }
 
-__global__ void k_red_norm(StepArgs a) {
+// M-norms of the live columns, and their Rayleigh quotients v.Av / v.Mv
+// (unchanged by the scaling that follows, so they are the eigenvalue
+// estimates of the normalised state).
+__global__ void k_red_norm(StepArgs a, double* __restrict__ lam) {
   const int c = red_col();
-  const bool lv = c < a.tm.rp && a.ct.live[c];
-  const double s = red_sum(a.part, lv ? a.tm.nchunk : 0, a.tm.rp, c);
-  if (!red_lead() || c >= a.tm.rp) return;
+  const Tile& t = a.tm;
+  const bool lv = c < t.rp && a.ct.live[c];
+  const double s = red_sum(a.part, lv ? t.nchunk : 0, t.rp, c);
+  const double sa = red_sum(a.part + part_off(t, 1), lv ? t.nchunk : 0, t.rp, c);
+  if (!red_lead() || c >= t.rp) return;
   a.cg.nrm[c] = lv ? sqrt(s) : 1.0;
+  if (lv && lam) lam[c] = sa / s;
 }
 
 __global__ __launch_bounds__(kBlock) void k_scale(StepArgs a, const double* __restrict__ v,
@@ -870,6 +893,46 @@ __global__ __launch_bounds__(kBlock) void k_energy_seps(StepArgs a, SepsPlan sp,
     for (int b = 0; b < TB; ++b) s += red[b * nr + tid];
     part_s[size_t(chunk) * sp.nres_p + r0 + tid] = s;
   }
+}
+
+// Direct variant: no staging.  A workgroup holds 256/nrp triangles x nrp
+// restart lanes (nrp = restarts of the tile rounded up to a power of two);
+// each lane reads its restart's m corner values straight from global memory
+// (lanes of one triangle read adjacent segments of the same rows).
+__global__ __launch_bounds__(kBlock) void k_energy_seps_direct(StepArgs a, SepsPlan sp,
+                                                               const int* __restrict__ tri,
+                                                               const double* __restrict__ tarea,
+                                                               const double* __restrict__ u,
+                                                               double* __restrict__ part_s) {
+  __shared__ double red[kBlock];
+  const int tile = blockIdx.x / sp.nchunk, chunk = blockIdx.x % sp.nchunk;
+  const int4 tl = sp.tiles[tile];
+  const int r0 = tl.x, nr = tl.y - tl.x;
+  int nrp = 1;
+  while (nrp < nr) nrp <<= 1;
+  const int TB = kBlock / nrp;
+  const int tid = threadIdx.x, tb = tid / nrp, rr = tid % nrp;
+  const int rp = a.t.rp;
+  int lo = 0, m = 0;
+  if (rr < nr) {
+    lo = a.ct.res_lo[r0 + rr];
+    m = a.ct.res_len[r0 + rr];
+  }
+  const int t_beg = chunk * sp.tchunk, t_end = min(t_beg + sp.tchunk, sp.nt);
+  double acc = 0.0;
+  if (m > 0)
+    for (int t = t_beg + tb; t < t_end; t += TB)
+      acc += quartic_pairs(u + size_t(tri[3 * t + 0]) * rp + lo,
+                           u + size_t(tri[3 * t + 1]) * rp + lo,
+                           u + size_t(tri[3 * t + 2]) * rp + lo, m) *
+             tarea[t] * (1.0 / 180.0);
+  red[tid] = acc;
+  for (int st = TB >> 1; st >= 1; st >>= 1) {
+    __syncthreads();
+    if (tb < st) red[tid] += red[tid + st * nrp];
+  }
+  __syncthreads();
+  if (tb == 0 && rr < nr) part_s[size_t(chunk) * sp.nres_p + r0 + rr] = red[tid];
 }
 
 __global__ void k_red_lambda(StepArgs a, double* __restrict__ lam) {
@@ -1102,8 +1165,8 @@ void norm_dot(const StepArgs& a, const double* v, hipStream_t s) {
   SP_LAUNCH_CHECK();
 }
 
-void red_norm(const StepArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_red_norm, dim3(colblocks(a.t)), dim3(kBlock), 0, s, a);
+void red_norm(const StepArgs& a, double* lam, hipStream_t s) {
+  hipLaunchKernelGGL(k_red_norm, dim3(colblocks(a.t)), dim3(kBlock), 0, s, a, lam);
   SP_LAUNCH_CHECK();
 }
 
@@ -1120,14 +1183,19 @@ void energy_rq(const StepArgs& a, const double* u, hipStream_t s) {
 void energy_seps(const StepArgs& a, const SepsPlan& sp, const int32_t* tri, const double* tarea,
                  const double* u, double* part_s, hipStream_t s) {
   if (sp.ntile == 0) return;
-  hipLaunchKernelGGL(k_energy_seps, dim3(unsigned(sp.ntile) * sp.nchunk), dim3(kBlock), 0, s, a,
-                     sp, tri, tarea, u, part_s);
+  if (sp.direct)
+    hipLaunchKernelGGL(k_energy_seps_direct, dim3(unsigned(sp.ntile) * sp.nchunk), dim3(kBlock), 0,
+                       s, a, sp, tri, tarea, u, part_s);
+  else
+    hipLaunchKernelGGL(k_energy_seps, dim3(unsigned(sp.ntile) * sp.nchunk), dim3(kBlock), 0, s, a,
+                       sp, tri, tarea, u, part_s);
   SP_LAUNCH_CHECK();
 }
 
-void red_energy(const StepArgs& a, const SepsPlan& sp, const double* part_s, double* lam,
-                double* seps, double* energy, hipStream_t s) {
-  hipLaunchKernelGGL(k_red_lambda, dim3(colblocks(a.t)), dim3(kBlock), 0, s, a, lam);
+void red_energy(const StepArgs& a, const SepsPlan& sp, const double* part_s, bool with_lambda,
+                double* lam, double* seps, double* energy, hipStream_t s) {
+  if (with_lambda)
+    hipLaunchKernelGGL(k_red_lambda, dim3(colblocks(a.t)), dim3(kBlock), 0, s, a, lam);
   hipLaunchKernelGGL(k_red_seps, dim3(nblocks(size_t(a.ct.nres))), dim3(kBlock), 0, s, a, sp,
                      part_s, (const double*)lam, seps, energy);
   SP_LAUNCH_CHECK();
