@@ -34,11 +34,52 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
 KERNEL_NAMES = ("matvec q=(M+tau A)p", "update x,r", "direction p")
 
 WORKLOADS = {
-    # name: (mesh level, [(seed, restarts, m)], eps, tau)
-    "sphere7-batched": (7, [(3004, 64, 4), (3008, 64, 8), (3012, 64, 12), (3016, 64, 16)],
-                        0.01, 5e-5),
-    "sphere3": (3, [(1003, 1, 3)], 0.1, 1e-3),
+    # name: (mesh kind, [(seed, restarts, m)], eps, tau)
+    "sphere7-batched": ("sphere7", [(3004, 64, 4), (3008, 64, 8), (3012, 64, 12),
+                                    (3016, 64, 16)], 0.01, 5e-5),
+    "torus512-batched": ("torus512", [(4008, 16, 8), (4016, 16, 16), (4032, 16, 32)],
+                         0.01, 5e-5),
+    "ellipsoid7-batched": ("ellipsoid7", [(4108, 16, 8), (4116, 16, 16), (4132, 16, 32)],
+                           0.01, 5e-5),
+    "sphere3": ("sphere3", [(1003, 1, 3)], 0.1, 1e-3),
 }
+MESH_TEXT = {"sphere": "unit sphere, icosahedral level {}", "torus": "ring torus {0}x{0} (R 1, r 0.4)",
+             "ellipsoid": "ellipsoid (1, 0.8, 0.6), icosahedral level {}"}
+
+# request stream of the serving benchmark: every mesh kind, m in 3..32,
+# eps in {0.02, 0.01, 0.005}, tau = eps / 200, 1..32 restarts, 200 steps
+SERVE = dict(seed=5000, m_range=(3, 32), eps=(0.02, 0.01, 0.005), restarts=(1, 32), steps=200)
+
+
+def traffic_record(kernel):
+    """Measured HBM bytes per launch of `kernel` from the counter summaries in
+    profiles/ (FETCH_SIZE and WRITE_SIZE runs scaled by a copy calibration),
+    used only while the kernel source is the one that was measured."""
+    import glob
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_1408_2355_amd", "csrc", "kernels.hip")
+    with open(src, "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as fh:
+            for line in fh:
+                if not line.startswith("traffic-record "):
+                    continue
+                kv = dict(re.findall(r'(\w+)=("[^"]*"|\S+)', line))
+                if kv.get("kernel", "").strip('"') == kernel and kv.get("source_sha256") == sha:
+                    fetch = float(kv["fetch_bytes_per_launch"])
+                    write = float(kv["write_bytes_per_launch"])
+                    return fetch + write, (fetch + write) / float(kv["algorithmic_bytes_per_launch"]), \
+                        os.path.relpath(path, ROOT)
+    return None, None, None
+
+
+def mesh_text(kind):
+    for k, fmt in MESH_TEXT.items():
+        if kind.startswith(k):
+            return fmt.format(kind[len(k):])
+    return kind
 
 
 def log(*a):
@@ -68,6 +109,70 @@ def cpu_baseline(v, f, groups, eps, tau, steps=1):
                        f"{steps} step(s) with energy, {dt:.1f} s")
 
 
+def serve(args, sp):
+    """Serving benchmark: the first ``--serve-requests`` requests of the seeded
+    Poisson stream (every mesh kind, m 3..32, eps in {0.02, 0.01, 0.005},
+    tau = eps/200, 1..32 restarts, 200 steps, mixed precision), submitted at
+    their arrival times to one server.  Inputs are generated before the clock
+    starts.  Latency = finish - submit per request (server clock)."""
+    from workloads import MESH_KINDS, poisson_trace, surface_mesh, uniform_u0
+    trace = poisson_trace(SERVE["seed"], args.serve_requests, args.serve_rate, MESH_KINDS,
+                          SERVE["m_range"], SERVE["eps"], SERVE["restarts"])
+    meshes = {}
+    for kind in sorted({r["kind"] for r in trace}):
+        meshes[kind] = sp.Mesh(*surface_mesh(kind))
+        log(f"[serve] mesh {kind}: {meshes[kind].n_vert} vertices")
+    reqs, work = [], 0.0
+    for r in trace:
+        n = meshes[r["kind"]].n_vert
+        u0 = uniform_u0(r["seed"], r["restarts"], r["m"], n)
+        prm = sp.params(r["eps"] / 200.0, precision="mixed", n_steps=SERVE["steps"],
+                        cg_rtol=1e-10, inner_rtol=args.inner_rtol)
+        reqs.append((r, prm, u0))
+        work += r["restarts"] * r["m"] * n * SERVE["steps"]
+    span = trace[-1]["t_arrive"]
+    log(f"[serve] {len(trace)} requests over {span:.2f} s, {work:.3e} cdof offered")
+    srv = sp.Server(int(args.serve_budget_gb * 2**30))
+    tickets = []
+    t0 = time.perf_counter()
+    for r, prm, u0 in reqs:
+        dt = t0 + r["t_arrive"] - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(srv.submit(meshes[r["kind"]], prm, [r["m"]] * r["restarts"],
+                                  [r["eps"]] * r["restarts"], u0))
+    del reqs
+    lat, ok = [], 0
+    for i, t in enumerate(tickets):
+        done = srv.wait(t, timeout_s=600.0)
+        assert done, f"request {i} did not finish"
+        out = srv.fetch(t)
+        lat.append(out["latency_s"])
+        ok += int(np.isfinite(out["energy"]).all())
+        log(f"[serve] request {i} ({trace[i]['kind']}, m {trace[i]['m']}, "
+            f"{trace[i]['restarts']} restarts) done, latency {out['latency_s']:.2f} s")
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    for m in meshes.values():
+        m.close()
+    result = {
+        "metric": "serving latency and throughput (Poisson request stream, continuous batching)",
+        "value": work / wall, "unit": "cdof/s", "n_gpus": 1, "steps": SERVE["steps"],
+        "warmup": 0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"serve: first {len(trace)} requests of the seeded stream "
+                               f"(seed {SERVE['seed']}, {args.serve_rate} req/s), all mesh "
+                               "kinds, m 3..32, eps {0.02,0.01,0.005}, tau eps/200, "
+                               "1..32 restarts, 200 steps, mixed precision"},
+        "latency_p50_s": st["p50_s"], "latency_p99_s": st["p99_s"],
+        "latency_max_s": max(lat), "completed": st["completed"], "finite_results": ok,
+        "offered_cdof_per_s": work / max(span, 1e-9), "wall_s": wall,
+        "server_cdof_per_s": st["cdof_per_s"],
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +187,13 @@ def main():
                     help="CG iterations between host convergence polls")
     ap.add_argument("--no-extrapolate", action="store_true",
                     help="start every heat solve from u (not u + previous increment)")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving benchmark instead: a seeded Poisson request stream over every "
+                         "mesh kind through the continuous-batching server; prints latency "
+                         "p50/p99 and throughput")
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-rate", type=float, default=50.0, help="arrivals per second")
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -102,12 +214,14 @@ def main():
 
     import torch
     from paper_1408_2355_amd import segpart as sp
-    from workloads import icosphere, batch_u0, uniform_u0
+    from workloads import surface_mesh, batch_u0, uniform_u0
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    level, groups, eps, tau = WORKLOADS[args.workload]
-    v, f = icosphere(level)
+    if args.serve:
+        return serve(args, sp)
+    kind, groups, eps, tau = WORKLOADS[args.workload]
+    v, f = surface_mesh(kind)
     n = v.shape[0]
     u0, ms = batch_u0(n, groups)
     R, nres = int(ms.sum()), ms.size
@@ -141,8 +255,10 @@ def main():
     launches, ms_tot, bytes_launch = kt[k]
     avg_s = ms_tot / max(launches, 1) * 1e-3
     achieved = bytes_launch / avg_s / 1e9 if launches else 0.0
+    traffic, traffic_ratio, traffic_src = traffic_record(KERNEL_NAMES[k])
     roofline = dict(bound="hbm", kernel=KERNEL_NAMES[k], achieved=achieved, peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=None,
+                    unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=traffic,
+                    traffic_vs_algorithmic=traffic_ratio, traffic_source=traffic_src,
                     launches=launches, avg_us=avg_s * 1e6, bytes_per_launch=bytes_launch,
                     kernel_ms_total={KERNEL_NAMES[i]: kt[i][1] for i in range(3)})
 
@@ -152,7 +268,7 @@ def main():
         "value": value, "unit": "cdof/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": f"{args.workload}: icosphere level {level} ({n} vertices), "
+        "config": {"workload": f"{args.workload}: {mesh_text(kind)} ({n} vertices), "
                                f"m in {sorted(set(int(x) for x in ms))} x "
                                f"{groups[0][1]} restarts ({R} columns), eps {eps}, tau {tau}, "
                                "float32 CG in float64 refinement, outer rtol 1e-10, "

@@ -57,6 +57,17 @@ template <typename F>
 __device__ __forceinline__ void for_rows(const Tile& t, F&& f) {
   const int xcd = blockIdx.x & 7, kb = blockIdx.x >> 3;
   const int rbeg = xcd * t.xrows, rend = min(rbeg + t.xrows, t.n);
+  if (t.tg == 64) {
+    // one row per wavefront: the row index is wave-uniform, so the row's
+    // matrix indices and values come through scalar loads and the vector
+    // memory pipe carries only the 16-byte column gathers
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int j = kb; j < t.nchx; j += t.nper) {
+      const int r1 = min(rbeg + (j + 1) * t.ch, rend);
+      for (int row = rbeg + j * t.ch + wv; row < r1; row += kBlock / 64) f(row);
+    }
+    return;
+  }
   const int rl = threadIdx.x / t.tg;
   for (int j = kb; j < t.nchx; j += t.nper) {
     const int r1 = min(rbeg + (j + 1) * t.ch, rend);
@@ -146,6 +157,14 @@ __device__ __forceinline__ void count_active(int flag, int* counter) {
 // neighbour's 4 column values and the matrix offset o = k*n + row.
 constexpr int kSlots = 8;
 
+// Load of matrix data (pattern and values), which no kernel of the time step
+// writes: read through the constant address space, so a wave-uniform address
+// becomes a scalar load.
+template <typename T>
+__device__ __forceinline__ T ldm(const T* p) {
+  return *(const __attribute__((address_space(4))) T*)(p);
+}
+
 template <typename T, typename F>
 __device__ __forceinline__ void for_neighbors(const StepArgs& a, int row, int c0,
                                               const T* __restrict__ x, F&& f) {
@@ -153,7 +172,7 @@ __device__ __forceinline__ void for_neighbors(const StepArgs& a, int row, int c0
   for (int kb = 0; kb < a.W; kb += kSlots) {
     int idx[kSlots];
 #pragma unroll
-    for (int k = 0; k < kSlots; ++k) idx[k] = a.cols[size_t(kb + k) * n + row];
+    for (int k = 0; k < kSlots; ++k) idx[k] = ldm(a.cols + size_t(kb + k) * n + row);
     V4<T> xv[kSlots];
 #pragma unroll
     for (int k = 0; k < kSlots; ++k) xv[k] = ld4(x + size_t(idx[k]) * rp + c0);
@@ -258,7 +277,7 @@ __global__ __launch_bounds__(kBlock) void k_init_fp64(StepArgs a, const double* 
     for_rows(t, [&](int row) {
       double au[4] = {}, mu[4] = {};
       for_neighbors(a, row, c0, u, [&](int, const V4<double>& x, size_t o) {
-        const double va = a.A64[o], vm = a.M64[o];
+        const double va = ldm(a.A64 + o), vm = ldm(a.M64 + o);
         for (int j = 0; j < 4; ++j) {
           au[j] = fma(va, x.v[j], au[j]);
           mu[j] = fma(vm, x.v[j], mu[j]);
@@ -316,7 +335,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmm(StepArgs a, int slot, const 
       for_rows(t, [&](int row) {
         V4<T> acc = {}, pd = {};
         for_neighbors(a, row, c0, p, [&](int k, const V4<T>& x, size_t o) {
-          const T v = K[o];
+          const T v = ldm(K + o);
           if (k == 0) pd = x;
           for (int j = 0; j < 4; ++j) acc.v[j] = fma(v, x.v[j], acc.v[j]);
         });
@@ -458,7 +477,7 @@ __global__ __launch_bounds__(kBlock) void k_init_outer(StepArgs a, const double*
     for_rows(t, [&](int row) {
       double au[4] = {}, mu[4] = {};
       for_neighbors(a, row, c0, u, [&](int, const V4<double>& x, size_t o) {
-        const double va = a.A64[o], vm = a.M64[o];
+        const double va = ldm(a.A64 + o), vm = ldm(a.M64 + o);
         for (int j = 0; j < 4; ++j) {
           au[j] = fma(va, x.v[j], au[j]);
           mu[j] = fma(vm, x.v[j], mu[j]);
@@ -581,7 +600,7 @@ __global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot, 
         double kd[4] = {};
         float dd[4] = {};
         for_neighbors(a, row, c0, d, [&](int k, const V4<float>& x, size_t o) {
-          const double v = a.K64[o];
+          const double v = ldm(a.K64 + o);
           if (k == 0)
             for (int j = 0; j < 4; ++j) dd[j] = x.v[j];
           for (int j = 0; j < 4; ++j) kd[j] = fma(v, double(x.v[j]), kd[j]);
@@ -688,7 +707,7 @@ __global__ __launch_bounds__(kBlock) void k_norm_dot(StepArgs a, const double* _
         double mv[4] = {}, av[4] = {};
         V4<double> vd = {};
         for_neighbors(a, row, c0, v, [&](int k, const V4<double>& x, size_t o) {
-          const double w = a.M64[o], z = a.A64[o];
+          const double w = ldm(a.M64 + o), z = ldm(a.A64 + o);
           if (k == 0) vd = x;
           for (int j = 0; j < 4; ++j) {
             mv[j] = fma(w, x.v[j], mv[j]);
@@ -766,7 +785,7 @@ __global__ __launch_bounds__(kBlock) void k_energy_rq(StepArgs a, const double* 
         double au[4] = {}, mu[4] = {};
         V4<double> ud = {};
         for_neighbors(a, row, c0, u, [&](int k, const V4<double>& x, size_t o) {
-          const double va = a.A64[o], vm = a.M64[o];
+          const double va = ldm(a.A64 + o), vm = ldm(a.M64 + o);
           if (k == 0) ud = x;
           for (int j = 0; j < 4; ++j) {
             au[j] = fma(va, x.v[j], au[j]);
