@@ -122,10 +122,12 @@ typedef struct {
   int32_t check_every;  /* CG iterations between host-side convergence polls; 0 = no
                            polling (cg_max_iter device iterations are enqueued and the
                            kernels exit at once after convergence)                  */
-  int32_t extrapolate;  /* SP_MIXED only: 1 = start each heat solve from u plus the
-                           previous step's increment (u~ - u) instead of from u; the
-                           solution is the same to cg_rtol, only the start differs.
-                           Ignored in SP_FP64 (which always starts from u)          */
+  int32_t extrapolate;  /* SP_MIXED only: 1 = start each heat solve from u + g, g the
+                           increment (u~ - u) extrapolated linearly from the last two
+                           steps (2 d_k - d_{k-1}; d_k alone after the first step),
+                           instead of from u; the solution is the same to cg_rtol,
+                           only the start differs.  Costs two float32 vectors per
+                           batch.  Ignored in SP_FP64 (which always starts from u) */
 } sp_params;
 
 /* Fill *p with defaults for time step tau: n_steps 100, stop_tol 1e-6,

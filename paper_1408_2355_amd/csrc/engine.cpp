@@ -90,6 +90,7 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     sp_.nres_p = nres_p_;
     seps_tiles_.alloc(nres_p_);
     u_.alloc(nv);
+    heat_x_ = u_.p;
     r64_.alloc(nv);
     if (prm_.precision == SP_FP64) {
       p64_.alloc(nv);
@@ -99,7 +100,13 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
       r32_.alloc(nv);
       p32_.alloc(nv);
       q32_.alloc(nv);
-      if (prm_.extrapolate) dprev_.alloc(nv);
+      if (prm_.extrapolate) {
+        dprev_.alloc(nv);
+        dprev2_.alloc(nv);
+        xg_.alloc(nv);
+        dlast_ = dprev_.p;
+        dnext_ = dprev2_.p;
+      }
     }
     // partial sums: one row per workgroup, sized for the widest tiling the
     // autotuner may pick
@@ -118,6 +125,10 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
 
     k::fill_f64(u_.p, 0.0, nv, s_);
     k::fill_f64(r64_.p, 0.0, nv, s_);
+    if (dlast_) {
+      k::fill_f32(dlast_, 0.0f, nv, s_);
+      k::fill_f32(dnext_, 0.0f, nv, s_);
+    }
     k::fill_f64(colf_.p, 0.0, colf_.n, s_);
     k::fill_i32(coli_.p, 0, coli_.n, s_);
     k::fill_i32(ring_.p, 0, ring_.n, s_);
@@ -397,7 +408,7 @@ void Solver::sync() { SP_HIP(hipStreamSynchronize(s_)); }
 
 void Solver::upload_host(const double* u0, bool normalise) {
   SP_REQUIRE(u0 != nullptr, SP_EINVAL, "NULL u0");
-  have_dprev_ = false;
+  n_prev_ = 0;
   lam_fresh_ = false;
   const size_t cnt = size_t(R_) * mesh_->n;
   for (size_t i = 0; i < cnt; ++i)
@@ -413,7 +424,7 @@ void Solver::upload_host(const double* u0, bool normalise) {
 
 void Solver::upload_device(const double* d_u0, bool normalise, bool check_norms) {
   SP_REQUIRE(d_u0 != nullptr, SP_EINVAL, "NULL u0");
-  have_dprev_ = false;
+  n_prev_ = 0;
   lam_fresh_ = false;
   k::pack(args_.t, 0, R_, d_u0, mesh_->perm_d.p, u_.p, s_);
   if (normalise) {
@@ -445,7 +456,7 @@ void Solver::normalise_columns() {
 
 void Solver::pack_range(int c_lo, int Rq, const double* d_src) {
   SP_REQUIRE(c_lo >= 0 && Rq >= 0 && c_lo + Rq <= rp_, SP_EINVAL, "column range");
-  have_dprev_ = false;  // the new columns have no previous increment
+  n_prev_ = 0;  // the new columns have no previous increment
   lam_fresh_ = false;
   k::pack(args_.t, c_lo, Rq, d_src, mesh_->perm_d.p, u_.p, s_);
 }
@@ -495,20 +506,24 @@ void Solver::heat_fp64() {
       if (poll(ring_.p + last % kRing) == 0) break;
   }
   k::flag_nonconv(args_, ring_.p + last % kRing, s_);
+  heat_x_ = u_.p;
 }
 
 void Solver::heat_mixed() {
   const bool extrap = prm_.extrapolate != 0;
+  double* x = u_.p;
   k::fill_i32(ring_.p, 0, ring_.n, s_);
-  k::init_outer(args_, u_.p, r64_.p, s_);
-  if (extrap) {
-    // start from u + (previous step's increment); the refinement sweeps then
-    // accumulate this step's increment in the same buffer
-    if (have_dprev_)
-      k::apply_guess(args_, u_.p, r64_.p, dprev_.p, s_);
-    else
-      k::fill_f32(dprev_.p, 0.0f, dprev_.n, s_);
-    have_dprev_ = true;
+  if (extrap && n_prev_ >= 1) {
+    // start from x0 = u + g with g extrapolated from the last heat increments
+    // (g = 2 d_k - d_{k-1}, or d_k after the first step), into the separate
+    // iterate xg_; the refinement sweeps then accumulate this step's
+    // increment on top of g in dnext_
+    k::extrap(args_, n_prev_ >= 2 ? 2.0f : 1.0f, n_prev_ >= 2 ? -1.0f : 0.0f, dlast_, dnext_, s_);
+    k::init_outer(args_, u_.p, dnext_, xg_.p, r64_.p, s_);
+    x = xg_.p;
+  } else {
+    k::init_outer(args_, u_.p, nullptr, nullptr, r64_.p, s_);
+    if (extrap) k::fill_f32(dnext_, 0.0f, dprev2_.n, s_);
   }
   k::red_outer_init(args_, s_);
   int olast = 0;
@@ -522,16 +537,21 @@ void Solver::heat_mixed() {
       if (prm_.check_every > 0 && last % prm_.check_every == 0 && last < prm_.cg_max_iter)
         if (poll(ring_.p + last % kRing) == 0) break;
     }
-    k::outer_update(args_, o, u_.p, r64_.p, d32_.p, extrap ? dprev_.p : nullptr, s_);
+    k::outer_update(args_, o, x, r64_.p, d32_.p, extrap ? dnext_ : nullptr, s_);
     k::red_outer(args_, o, s_);
     olast = o + 1;
     if (prm_.check_every > 0 && olast < prm_.max_outer)
       if (poll(args_.oring + olast % kRing) == 0) break;
   }
   k::flag_nonconv(args_, args_.oring + olast % kRing, s_);
+  if (extrap) {
+    std::swap(dlast_, dnext_);
+    n_prev_ = std::min(n_prev_ + 1, 2);
+  }
+  heat_x_ = x;
 }
 
-void Solver::stage_heat() {
+void Solver::heat() {
   lam_fresh_ = false;
   if (prm_.precision == SP_FP64)
     heat_fp64();
@@ -539,7 +559,18 @@ void Solver::stage_heat() {
     heat_mixed();
 }
 
-void Solver::node_to_r() { k::nodal(args_, u_.p, r64_.p, s_); }
+void Solver::stage_heat() {
+  heat();
+  if (heat_x_ != u_.p)
+    SP_HIP(hipMemcpyAsync(u_.p, heat_x_, u_.n * sizeof(double), hipMemcpyDeviceToDevice, s_));
+  heat_x_ = u_.p;
+}
+
+// node step of the heat solution (the iterate the last solve left, u or xg_)
+void Solver::node_to_r() {
+  k::nodal(args_, heat_x_, r64_.p, s_);
+  heat_x_ = u_.p;
+}
 
 void Solver::norm_dot_scale(const double* v) {
   k::norm_dot(args_, v, s_);
@@ -581,7 +612,7 @@ void Solver::step(int64_t k) {
   const int nres = int(spec_.m.size());
   std::vector<double> E(nres);
   for (int64_t i = 0; i < k; ++i) {
-    stage_heat();
+    heat();
     node_to_r();
     norm_dot_scale(r64_.p);
     ++steps_done_;

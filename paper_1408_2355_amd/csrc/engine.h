@@ -100,12 +100,13 @@ class Solver {
   // Skip the stream synchronisation in the destructor (work already done).
   void detach() { detached_ = true; }
   // Forget the previous heat increment (the next step starts from x0 = u).
-  void reset_guess() { have_dprev_ = false; }
+  void reset_guess() { n_prev_ = 0; }
 
   bool record_history = true;          // copy energies to the host at the cadence
   std::vector<int64_t> restart_steps;  // per restart: steps taken (stop mode)
 
  private:
+  void heat();  // heat solve; its result is left in heat_x_
   void heat_fp64();
   void heat_mixed();
   void node_to_r();
@@ -127,8 +128,15 @@ class Solver {
 
   DevBuf<double> u_, r64_, p64_, q64_;
   DevBuf<float> d32_, r32_, p32_, q32_;
-  DevBuf<float> dprev_;      // previous step's heat increment (extrapolated start)
-  bool have_dprev_ = false;
+  // heat increments of the last two steps (extrapolated start): dlast_ holds
+  // the latest, dnext_ the one before and, during a solve, the increment
+  // being accumulated; the two swap after each solve
+  DevBuf<float> dprev_, dprev2_;
+  float* dlast_ = nullptr;
+  float* dnext_ = nullptr;
+  int n_prev_ = 0;  // increments available (0, 1 or 2)
+  DevBuf<double> xg_;          // iterate of a solve started from u + g (u stays b's source)
+  double* heat_x_ = nullptr;   // where the last heat solve left its result (u_ or xg_)
   bool lam_fresh_ = false;  // lam holds the Rayleigh quotients of the current state
   bool all_live_ = true;    // every real column is live
   DevBuf<double> part_, part_s_;

@@ -89,7 +89,10 @@ void cg_iter(const StepArgs& a, int it, T* x, T* r, T* p, T* q, const T* K, cons
 template <typename T>
 void matvec(const StepArgs& a, const T* K, const T* p, T* q, hipStream_t s);
 // mixed precision refinement
-void init_outer(const StepArgs& a, const double* u, double* r64, hipStream_t s);
+// r64 = M u - K x0 with x0 = u + g (g nullable: x0 = u, nothing written to
+// x0); x0 must not alias u
+void init_outer(const StepArgs& a, const double* u, const float* g, double* x0, double* r64,
+                hipStream_t s);
 void red_outer_init(const StepArgs& a, hipStream_t s);
 void inner_init(const StepArgs& a, int o, const double* r64, float* d, float* r, float* p,
                 hipStream_t s);
@@ -97,9 +100,8 @@ void red_inner_init(const StepArgs& a, int o, hipStream_t s);
 // u += d, r64 -= K d on the columns still refining; dacc (nullable) += d
 void outer_update(const StepArgs& a, int o, double* u, double* r64, const float* d, float* dacc,
                   hipStream_t s);
-// start from x0 = u + delta on every live column: u += delta, r64 -= K delta,
-// ||r64||^2 into partial slot 1 (call between init_outer and red_outer_init)
-void apply_guess(const StepArgs& a, double* u, double* r64, const float* delta, hipStream_t s);
+// y = ca x + cb y on the live columns, 0 on the others (cb == 0: y not read)
+void extrap(const StepArgs& a, float ca, float cb, const float* x, float* y, hipStream_t s);
 void red_outer(const StepArgs& a, int o, hipStream_t s);
 // node step and normalisation
 void nodal(const StepArgs& a, const double* u, double* out, hipStream_t s);

@@ -430,6 +430,28 @@ __global__ void k_red_beta(StepArgs a, int slot, int next) {
   count_active(still, a.ring + next);
 }
 
+// y = ca x + cb y on the live columns, 0 elsewhere (cb == 0: y is not read)
+__global__ __launch_bounds__(kBlock) void k_extrap(StepArgs a, float ca, float cb,
+                                                   const float* __restrict__ x,
+                                                   float* __restrict__ y) {
+  const Tile& t = a.t;
+  for (int ct = 0; ct < t.nct; ++ct) {
+    const int g = ct * t.tg + threadIdx.x % t.tg;
+    if (g >= t.G) continue;
+    const int c0 = 4 * g;
+    bool lv[4];
+    for (int j = 0; j < 4; ++j) lv[j] = a.ct.live[c0 + j] != 0;
+    for_rows(t, [&](int row) {
+      const size_t o = size_t(row) * t.rp + c0;
+      const V4<float> xv = ld4(x + o);
+      V4<float> yv = {};
+      if (cb != 0.0f) yv = ld4(y + o);
+      for (int j = 0; j < 4; ++j) yv.v[j] = lv[j] ? ca * xv.v[j] + cb * yv.v[j] : 0.0f;
+      st4(y + o, yv);
+    });
+  }
+}
+
 // p = D r + beta p
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cg_update_p(StepArgs a, int next, T* __restrict__ p,
@@ -464,7 +486,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_p(StepArgs a, int next, T*
 
 // ------------------------------------------------- mixed-precision refinement --
 // Outer residual r64 = -tau A u (float64), partials ||M u||^2 and ||r64||^2.
+// Start of the float64 refinement.  b = M u; with a start guess g (nullable)
+// the iterate is x0 = u + g, written to x0, and r64 = b - K x0 = -tau A u - K g
+// (no cancellation); without one x0 = u and r64 = -tau A u.  Partials:
+// ||M u||^2 and ||r64||^2.  x0 must not alias u (u is gathered).
 __global__ __launch_bounds__(kBlock) void k_init_outer(StepArgs a, const double* __restrict__ u,
+                                                       const float* __restrict__ gd,
+                                                       double* __restrict__ x0,
                                                        double* __restrict__ r64) {
   const Tile& t = a.tm;
   for (int ct = 0; ct < t.nct; ++ct) {
@@ -475,21 +503,33 @@ __global__ __launch_bounds__(kBlock) void k_init_outer(StepArgs a, const double*
     double lv[4];
     for (int j = 0; j < 4; ++j) lv[j] = a.ct.live[c0 + j] ? 1.0 : 0.0;
     for_rows(t, [&](int row) {
-      double au[4] = {}, mu[4] = {};
-      for_neighbors(a, row, c0, u, [&](int, const V4<double>& x, size_t o) {
+      double au[4] = {}, mu[4] = {}, kg[4] = {};
+      V4<double> uo = {};
+      for_neighbors(a, row, c0, u, [&](int k, const V4<double>& x, size_t o) {
         const double va = ldm(a.A64 + o), vm = ldm(a.M64 + o);
+        if (k == 0) uo = x;
         for (int j = 0; j < 4; ++j) {
           au[j] = fma(va, x.v[j], au[j]);
           mu[j] = fma(vm, x.v[j], mu[j]);
         }
       });
-      V4<double> rv;
+      V4<float> go = {};
+      if (gd)
+        for_neighbors(a, row, c0, gd, [&](int k, const V4<float>& x, size_t o) {
+          const double v = ldm(a.K64 + o);
+          if (k == 0) go = x;
+          for (int j = 0; j < 4; ++j) kg[j] = fma(v, double(x.v[j]), kg[j]);
+        });
+      V4<double> rv, xv;
       for (int j = 0; j < 4; ++j) {
-        rv.v[j] = -a.tau * au[j] * lv[j];
+        rv.v[j] = (-a.tau * au[j] - kg[j]) * lv[j];
+        xv.v[j] = uo.v[j] + double(go.v[j]) * lv[j];
         s[0][j] += mu[j] * mu[j] * lv[j];
         s[1][j] += rv.v[j] * rv.v[j];
       }
-      st4(r64 + size_t(row) * t.rp + c0, rv);
+      const size_t o = size_t(row) * t.rp + c0;
+      st4(r64 + o, rv);
+      if (gd) st4(x0 + o, xv);
     });
   }
   block_store<2>(t, s, a.part, blockIdx.x, ct);
@@ -570,23 +610,19 @@ __global__ void k_red_inner_init(StepArgs a, int oslot, int onext) {
 }
 
 // x64 += d; r64 -= K64 d (float64 product of the float32 correction);
-// partial ||r64||^2.
-//
-// The same kernel applies the extrapolated start x0 = u + delta (guess
-// mode: every live column, no sweep gating, partial written to slot 1 next to
-// the ||M u||^2 of slot 0).  In refinement mode, dacc (if given) accumulates
-// this step's corrections, so after the last sweep it holds the step's heat
-// increment x - u used as the next step's start.
-__global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot, bool guess,
+// partial ||r64||^2, on the columns still refining.  dacc (if given)
+// accumulates the corrections on top of the start guess, so after the last
+// sweep it holds the step's heat increment x - u.
+__global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot,
                                                          double* __restrict__ u,
                                                          double* __restrict__ r64,
                                                          const float* __restrict__ d,
                                                          float* __restrict__ dacc) {
-  if (!guess && a.oring[oslot] == 0) return;
+  if (a.oring[oslot] == 0) return;
   const Tile& t = a.tm;
   for (int ct = 0; ct < t.nct; ++ct) {
   const int g = ct * t.tg + threadIdx.x % t.tg;
-  const int* mask = guess ? a.ct.live : a.cg.act_o;
+  const int* mask = a.cg.act_o;
   double s[1][4] = {};
   if (g < t.G) {
     const int c0 = 4 * g;
@@ -625,7 +661,7 @@ __global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot, 
       });
     }
   }
-  block_store<1>(t, s, a.part + (guess ? part_off(t, 1) : 0), blockIdx.x, ct);
+  block_store<1>(t, s, a.part, blockIdx.x, ct);
   }
 }
 
@@ -1133,8 +1169,9 @@ template void cg_iter<double>(const StepArgs&, int, double*, double*, double*, d
 template void cg_iter<float>(const StepArgs&, int, float*, float*, float*, float*, const float*,
                              const float*, hipStream_t, const hipEvent_t*);
 
-void init_outer(const StepArgs& a, const double* u, double* r64, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_outer, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, u, r64);
+void init_outer(const StepArgs& a, const double* u, const float* g, double* x0, double* r64,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_init_outer, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, u, g, x0, r64);
   SP_LAUNCH_CHECK();
 }
 
@@ -1157,14 +1194,13 @@ void red_inner_init(const StepArgs& a, int o, hipStream_t s) {
 
 void outer_update(const StepArgs& a, int o, double* u, double* r64, const float* d, float* dacc,
                   hipStream_t s) {
-  hipLaunchKernelGGL(k_outer_update, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, o % kRing, false, u,
+  hipLaunchKernelGGL(k_outer_update, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, o % kRing, u,
                      r64, d, dacc);
   SP_LAUNCH_CHECK();
 }
 
-void apply_guess(const StepArgs& a, double* u, double* r64, const float* delta, hipStream_t s) {
-  hipLaunchKernelGGL(k_outer_update, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, 0, true, u, r64, delta,
-                     (float*)nullptr);
+void extrap(const StepArgs& a, float ca, float cb, const float* x, float* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_extrap, dim3(a.t.nblk), dim3(kBlock), 0, s, a, ca, cb, x, y);
   SP_LAUNCH_CHECK();
 }
 
