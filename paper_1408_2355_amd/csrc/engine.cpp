@@ -85,8 +85,9 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     const size_t nv = size_t(n) * rp_;
     Tile t = make_tile(n, rp_, 64, 1, 128);
     sp_.nt = int(mesh_->nt);
-    sp_.tchunk = std::max(256, int((mesh_->nt + 1023) / 1024 + 3) / 4 * 4);
+    sp_.tchunk = 64;
     sp_.nchunk = int((mesh_->nt + sp_.tchunk - 1) / sp_.tchunk);
+    sp_.nper = std::max(1, std::min(64, (sp_.nchunk + 7) / 8));
     sp_.nres_p = nres_p_;
     seps_tiles_.alloc(nres_p_);
     u_.alloc(nv);
@@ -113,7 +114,7 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     int max_blk = t.nblk;
     for (const Tile& c : tile_candidates()) max_blk = std::max(max_blk, c.nblk);
     part_.alloc(3 * size_t(max_blk) * rp_);
-    part_s_.alloc(size_t(sp_.nchunk) * nres_p_);
+    part_s_.alloc(size_t(8 * sp_.nper) * nres_p_);
     colf_.alloc(size_t(CF_N) * rp_ + nres_p_);
     coli_.alloc(size_t(CI_N) * rp_ + 3 * size_t(nres_p_));
     ring_.alloc(2 * kRing);

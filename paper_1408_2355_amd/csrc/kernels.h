@@ -67,6 +67,7 @@ struct SepsPlan {
   int ntile = 0;
   int nchunk = 0;  // triangle chunks
   int tchunk = 0;  // triangles per chunk
+  int nper = 0;    // workgroups per XCD (8 * nper partial rows per restart)
   int nt = 0;      // triangles
   int nres_p = 0;  // row stride of the partial sums
   int direct = 0;  // 1 = corners read from global memory, 0 = staged in LDS

@@ -840,6 +840,22 @@ __global__ __launch_bounds__(kBlock) void k_energy_rq(StepArgs a, const double* 
   }
 }
 
+// Triangle traversal of the S_eps kernels.  Triangles are cut into chunks
+// of sp.tchunk (they are sorted by their lowest vertex, so a chunk touches a
+// compact set of rows); the chunks are split into 8 contiguous ranges, one
+// per XCD (workgroup b runs on XCD b % 8), and an XCD's sp.nper workgroups
+// take the chunks of its range cyclically, restart tile by restart tile, so
+// at any moment an XCD works on one window of rows, which stays in its L2.
+// f(tile, first chunk, end chunk, stride) runs once per tile; each
+// workgroup writes one partial row (its index) per tile.
+template <typename F>
+__device__ __forceinline__ void for_seps_chunks(const SepsPlan& sp, F&& f) {
+  const int xcd = blockIdx.x & 7, kb = blockIdx.x >> 3;
+  const int cpx = (sp.nchunk + 7) / 8;
+  const int cbeg = xcd * cpx, cend = min(cbeg + cpx, sp.nchunk);
+  for (int tile = 0; tile < sp.ntile; ++tile) f(tile, cbeg + kb, cend, sp.nper);
+}
+
 // S_eps element kernel.  On a triangle T the P1 functions are u_i = sum_p
 // a_ip b_p in the barycentric coordinates b_p, and
 //   int_T b^alpha = 2|T| alpha! / (|alpha| + 2)!.
@@ -900,54 +916,60 @@ __global__ __launch_bounds__(kBlock) void k_energy_seps(StepArgs a, SepsPlan sp,
                                                         double* __restrict__ part_s) {
   __shared__ double sh[kSepsTri * 3 * kSepsCols];
   __shared__ double red[kBlock];
-  const int tile = blockIdx.x / sp.nchunk, chunk = blockIdx.x % sp.nchunk;
-  const int4 tl = sp.tiles[tile];
-  const int r0 = tl.x, nr = tl.y - tl.x, c0 = tl.z, ncol = tl.w - tl.z;
-  const bool staged = ncol <= kSepsCols;
-  const int TB = max(1, min(kSepsTri, kBlock / max(nr, 1)));
-  const int tid = threadIdx.x, tb = tid / max(nr, 1), rr = tid % max(nr, 1);
-  const bool worker = tid < TB * nr;
   const int rp = a.t.rp;
-  const int t_beg = chunk * sp.tchunk, t_end = min(t_beg + sp.tchunk, sp.nt);
-  int lo = 0, m = 0;
-  if (worker) {
-    lo = a.ct.res_lo[r0 + rr];
-    m = a.ct.res_len[r0 + rr];
-  }
-  double acc = 0.0;
-  for (int t0 = t_beg; t0 < t_end; t0 += TB) {
-    if (staged) {
-      const int per_tri = 3 * ncol;
-      for (int idx = tid; idx < TB * per_tri; idx += kBlock) {
-        const int b = idx / per_tri, rem = idx - b * per_tri;
-        const int k = rem / ncol, c = rem - k * ncol;
-        const int t = t0 + b;
-        sh[(b * 3 + k) * kSepsCols + c] =
-            t < t_end ? u[size_t(tri[3 * t + k]) * rp + c0 + c] : 0.0;
-      }
-      __syncthreads();
+  const int tid = threadIdx.x;
+  for_seps_chunks(sp, [&](int tile, int cb, int ce, int stride) {
+    const int4 tl = sp.tiles[tile];
+    const int r0 = tl.x, nr = tl.y - tl.x, c0 = tl.z, ncol = tl.w - tl.z;
+    const bool staged = ncol <= kSepsCols;
+    const int TB = max(1, min(kSepsTri, kBlock / max(nr, 1)));
+    const int tb = tid / max(nr, 1), rr = tid % max(nr, 1);
+    const bool worker = tid < TB * nr;
+    int lo = 0, m = 0;
+    if (worker) {
+      lo = a.ct.res_lo[r0 + rr];
+      m = a.ct.res_len[r0 + rr];
     }
-    const int t = t0 + tb;
-    if (worker && t < t_end && m > 0) {
-      double q;
-      if (staged) {
-        const double* base = sh + size_t(tb) * 3 * kSepsCols + (lo - c0);
-        q = quartic_pairs(base, base + kSepsCols, base + 2 * kSepsCols, m);
-      } else {
-        q = quartic_pairs(u + size_t(tri[3 * t + 0]) * rp + lo, u + size_t(tri[3 * t + 1]) * rp + lo,
-                          u + size_t(tri[3 * t + 2]) * rp + lo, m);
+    double acc = 0.0;
+    for (int chunk = cb; chunk < ce; chunk += stride) {
+      const int t_beg = chunk * sp.tchunk, t_end = min(t_beg + sp.tchunk, sp.nt);
+      for (int t0 = t_beg; t0 < t_end; t0 += TB) {
+        if (staged) {
+          const int per_tri = 3 * ncol;
+          for (int idx = tid; idx < TB * per_tri; idx += kBlock) {
+            const int bq = idx / per_tri, rem = idx - bq * per_tri;
+            const int k = rem / ncol, c = rem - k * ncol;
+            const int t = t0 + bq;
+            sh[(bq * 3 + k) * kSepsCols + c] =
+                t < t_end ? u[size_t(tri[3 * t + k]) * rp + c0 + c] : 0.0;
+          }
+          __syncthreads();
+        }
+        const int t = t0 + tb;
+        if (worker && t < t_end && m > 0) {
+          double q;
+          if (staged) {
+            const double* base = sh + size_t(tb) * 3 * kSepsCols + (lo - c0);
+            q = quartic_pairs(base, base + kSepsCols, base + 2 * kSepsCols, m);
+          } else {
+            q = quartic_pairs(u + size_t(tri[3 * t + 0]) * rp + lo,
+                              u + size_t(tri[3 * t + 1]) * rp + lo,
+                              u + size_t(tri[3 * t + 2]) * rp + lo, m);
+          }
+          acc += q * tarea[t] * (1.0 / 180.0);
+        }
+        if (staged) __syncthreads();
       }
-      acc += q * tarea[t] * (1.0 / 180.0);
     }
-    if (staged) __syncthreads();
-  }
-  red[tid] = acc;
-  __syncthreads();
-  if (tid < nr) {
-    double s = 0.0;
-    for (int b = 0; b < TB; ++b) s += red[b * nr + tid];
-    part_s[size_t(chunk) * sp.nres_p + r0 + tid] = s;
-  }
+    red[tid] = acc;
+    __syncthreads();
+    if (tid < nr) {
+      double s = 0.0;
+      for (int bq = 0; bq < TB; ++bq) s += red[bq * nr + tid];
+      part_s[size_t(blockIdx.x) * sp.nres_p + r0 + tid] = s;
+    }
+    __syncthreads();
+  });
 }
 
 // Direct variant: no staging.  A workgroup holds 256/nrp triangles x nrp
@@ -960,34 +982,39 @@ __global__ __launch_bounds__(kBlock) void k_energy_seps_direct(StepArgs a, SepsP
                                                                const double* __restrict__ u,
                                                                double* __restrict__ part_s) {
   __shared__ double red[kBlock];
-  const int tile = blockIdx.x / sp.nchunk, chunk = blockIdx.x % sp.nchunk;
-  const int4 tl = sp.tiles[tile];
-  const int r0 = tl.x, nr = tl.y - tl.x;
-  int nrp = 1;
-  while (nrp < nr) nrp <<= 1;
-  const int TB = kBlock / nrp;
-  const int tid = threadIdx.x, tb = tid / nrp, rr = tid % nrp;
   const int rp = a.t.rp;
-  int lo = 0, m = 0;
-  if (rr < nr) {
-    lo = a.ct.res_lo[r0 + rr];
-    m = a.ct.res_len[r0 + rr];
-  }
-  const int t_beg = chunk * sp.tchunk, t_end = min(t_beg + sp.tchunk, sp.nt);
-  double acc = 0.0;
-  if (m > 0)
-    for (int t = t_beg + tb; t < t_end; t += TB)
-      acc += quartic_pairs(u + size_t(tri[3 * t + 0]) * rp + lo,
-                           u + size_t(tri[3 * t + 1]) * rp + lo,
-                           u + size_t(tri[3 * t + 2]) * rp + lo, m) *
-             tarea[t] * (1.0 / 180.0);
-  red[tid] = acc;
-  for (int st = TB >> 1; st >= 1; st >>= 1) {
+  const int tid = threadIdx.x;
+  for_seps_chunks(sp, [&](int tile, int cb, int ce, int stride) {
+    const int4 tl = sp.tiles[tile];
+    const int r0 = tl.x, nr = tl.y - tl.x;
+    int nrp = 1;
+    while (nrp < nr) nrp <<= 1;
+    const int TB = kBlock / nrp;
+    const int tb = tid / nrp, rr = tid % nrp;
+    int lo = 0, m = 0;
+    if (rr < nr) {
+      lo = a.ct.res_lo[r0 + rr];
+      m = a.ct.res_len[r0 + rr];
+    }
+    double acc = 0.0;
+    if (m > 0)
+      for (int chunk = cb; chunk < ce; chunk += stride) {
+        const int t_beg = chunk * sp.tchunk, t_end = min(t_beg + sp.tchunk, sp.nt);
+        for (int t = t_beg + tb; t < t_end; t += TB)
+          acc += quartic_pairs(u + size_t(tri[3 * t + 0]) * rp + lo,
+                               u + size_t(tri[3 * t + 1]) * rp + lo,
+                               u + size_t(tri[3 * t + 2]) * rp + lo, m) *
+                 tarea[t] * (1.0 / 180.0);
+      }
+    red[tid] = acc;
+    for (int st = TB >> 1; st >= 1; st >>= 1) {
+      __syncthreads();
+      if (tb < st) red[tid] += red[tid + st * nrp];
+    }
     __syncthreads();
-    if (tb < st) red[tid] += red[tid + st * nrp];
-  }
-  __syncthreads();
-  if (tb == 0 && rr < nr) part_s[size_t(chunk) * sp.nres_p + r0 + rr] = red[tid];
+    if (tb == 0 && rr < nr) part_s[size_t(blockIdx.x) * sp.nres_p + r0 + rr] = red[tid];
+    __syncthreads();
+  });
 }
 
 __global__ void k_red_lambda(StepArgs a, double* __restrict__ lam) {
@@ -1005,7 +1032,7 @@ __global__ void k_red_seps(StepArgs a, SepsPlan sp, const double* __restrict__ p
                            double* __restrict__ energy) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= a.ct.nres) return;
-  const double s = sum_chunks(part_s, sp.nchunk, sp.nres_p, r) * a.ct.res_ieps2[r];
+  const double s = sum_chunks(part_s, 8 * sp.nper, sp.nres_p, r) * a.ct.res_ieps2[r];
   double e = s;
   const int lo = a.ct.res_lo[r], m = a.ct.res_len[r];
   for (int i = 0; i < m; ++i) e += lam[lo + i];
@@ -1239,11 +1266,11 @@ void energy_seps(const StepArgs& a, const SepsPlan& sp, const int32_t* tri, cons
                  const double* u, double* part_s, hipStream_t s) {
   if (sp.ntile == 0) return;
   if (sp.direct)
-    hipLaunchKernelGGL(k_energy_seps_direct, dim3(unsigned(sp.ntile) * sp.nchunk), dim3(kBlock), 0,
-                       s, a, sp, tri, tarea, u, part_s);
+    hipLaunchKernelGGL(k_energy_seps_direct, dim3(8 * sp.nper), dim3(kBlock), 0, s, a, sp, tri,
+                       tarea, u, part_s);
   else
-    hipLaunchKernelGGL(k_energy_seps, dim3(unsigned(sp.ntile) * sp.nchunk), dim3(kBlock), 0, s, a,
-                       sp, tri, tarea, u, part_s);
+    hipLaunchKernelGGL(k_energy_seps, dim3(8 * sp.nper), dim3(kBlock), 0, s, a, sp, tri, tarea, u,
+                       part_s);
   SP_LAUNCH_CHECK();
 }
 
