@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 
 namespace sp {
 
@@ -140,7 +141,8 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
 
     StepArgs& a = args_;
     a.t = t;   // streaming kernels: widest tiling (most workgroups in flight)
-    a.tm = t;  // gathering kernels: replaced by the autotuner's pick
+    a.tm = t;   // gathering kernels: replaced by the autotuner's picks
+    a.t64 = t;
     a.W = mesh_->W;
     a.cols = mesh_->cols.p;
     a.M64 = mesh_->M64.p;
@@ -242,9 +244,50 @@ std::vector<Tile> Solver::tile_candidates() const {
   return out;
 }
 
-// Pick the tiling of the row-parallel kernels by timing the CG matrix
-// product (the kernel with the gathers) for every candidate, once per
-// (mesh size, ELL width, columns, precision, device); see autotune.h.
+// Time `launch` under every candidate tiling placed in args_.*field and
+// return the fastest (cached under key; see autotune.h).
+TuneChoice Solver::tune_tiling(const std::string& key, Tile StepArgs::*field,
+                               const std::function<void()>& launch) {
+  TuneChoice best;
+  if (tune_lookup(key, &best)) return best;
+  hipEvent_t e0, e1;
+  SP_HIP(hipEventCreate(&e0));
+  SP_HIP(hipEventCreate(&e1));
+  best.us = 1e30;
+  const Tile keep = args_.*field;
+  for (const Tile& c : tile_candidates()) {
+    args_.*field = c;
+    launch();
+    SP_HIP(hipEventRecord(e0, s_));
+    for (int i = 0; i < 3; ++i) launch();
+    SP_HIP(hipEventRecord(e1, s_));
+    SP_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    SP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    const double us = 1e3 * ms / 3.0;
+    if (std::getenv("SEGPART_TUNE_VERBOSE"))
+      std::fprintf(stderr, "[segpart tune] %s lanes=%d chunk=%d groups/xcd=%d: %.1f us\n",
+                   key.c_str(), c.tg, c.ch, c.nper, us);
+    if (us < best.us) {
+      best.us = us;
+      best.tg_cap = c.tg;
+      best.passes = c.ch / c.tr;
+      best.nper_cap = c.nper;
+    }
+  }
+  args_.*field = keep;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  SP_HIP(hipStreamSynchronize(s_));
+  tune_store(key, best);
+  return best;
+}
+
+// Pick the tilings of the row-parallel gathering kernels by timing, once per
+// (mesh size, ELL width, columns, precision, device): the CG matrix product
+// sets the tiling of the product and the refinement update; in mixed
+// precision the float64 gathers (solve set-up, norms) get their own, timed
+// on the norm pass.
 void Solver::autotune() {
   const size_t work = size_t(mesh_->n) * size_t(rp_);
   if (!tune_enabled(work >= (size_t(1) << 22))) return;
@@ -254,57 +297,31 @@ void Solver::autotune() {
   const std::string key = "n" + std::to_string(mesh_->n) + "_W" + std::to_string(mesh_->W) +
                           "_rp" + std::to_string(rp_) + (f64 ? "_f64" : "_f32") + "_dev" +
                           std::to_string(dev);
-  TuneChoice best;
-  if (!tune_lookup(key, &best)) {
-    // every column active, a nonzero iteration counter, p = 1
-    k::fill_i32(args_.cg.act, 1, rp_, s_);
-    k::fill_i32(ring_.p, 1, 1, s_);
-    const size_t nv = size_t(mesh_->n) * rp_;
+  // matrix product: every column active, a nonzero iteration counter, p = 1
+  k::fill_i32(args_.cg.act, 1, rp_, s_);
+  k::fill_i32(ring_.p, 1, 1, s_);
+  const size_t nv = size_t(mesh_->n) * rp_;
+  if (f64)
+    k::fill_f64(p64_.p, 1.0, nv, s_);
+  else
+    k::fill_f32(p32_.p, 1.0f, nv, s_);
+  const TuneChoice best = tune_tiling(key, &StepArgs::tm, [&] {
     if (f64)
-      k::fill_f64(p64_.p, 1.0, nv, s_);
+      k::matvec<double>(args_, km_->K64.p, p64_.p, q64_.p, s_);
     else
-      k::fill_f32(p32_.p, 1.0f, nv, s_);
-    hipEvent_t e0, e1;
-    SP_HIP(hipEventCreate(&e0));
-    SP_HIP(hipEventCreate(&e1));
-    best.us = 1e30;
-    const Tile keep = args_.tm;
-    for (const Tile& c : tile_candidates()) {
-      args_.tm = c;
-      auto launch = [&] {
-        if (f64)
-          k::matvec<double>(args_, km_->K64.p, p64_.p, q64_.p, s_);
-        else
-          k::matvec<float>(args_, km_->K32.p, p32_.p, q32_.p, s_);
-      };
-      launch();
-      SP_HIP(hipEventRecord(e0, s_));
-      for (int i = 0; i < 3; ++i) launch();
-      SP_HIP(hipEventRecord(e1, s_));
-      SP_HIP(hipEventSynchronize(e1));
-      float ms = 0.f;
-      SP_HIP(hipEventElapsedTime(&ms, e0, e1));
-      const double us = 1e3 * ms / 3.0;
-      if (std::getenv("SEGPART_TUNE_VERBOSE"))
-        std::fprintf(stderr, "[segpart tune] %s lanes=%d chunk=%d groups/xcd=%d: %.1f us\n",
-                     key.c_str(), c.tg, c.ch, c.nper, us);
-      if (us < best.us) {
-        best.us = us;
-        best.tg_cap = c.tg;
-        best.passes = c.ch / c.tr;
-        best.nper_cap = c.nper;
-      }
-    }
-    args_.tm = keep;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    k::fill_i32(args_.cg.act, 0, rp_, s_);
-    k::fill_i32(ring_.p, 0, ring_.n, s_);
-    SP_HIP(hipStreamSynchronize(s_));
-    tune_store(key, best);
-  }
+      k::matvec<float>(args_, km_->K32.p, p32_.p, q32_.p, s_);
+  });
+  k::fill_i32(args_.cg.act, 0, rp_, s_);
+  k::fill_i32(ring_.p, 0, ring_.n, s_);
   args_.tm = make_tile(int(mesh_->n), rp_, best.tg_cap, best.passes, best.nper_cap);
   tuned_ = best;
+  if (f64) {
+    args_.t64 = args_.tm;
+  } else {
+    const TuneChoice b64 = tune_tiling(key + "_gather64", &StepArgs::t64,
+                                       [&] { k::norm_dot(args_, u_.p, s_); });
+    args_.t64 = make_tile(int(mesh_->n), rp_, b64.tg_cap, b64.passes, b64.nper_cap);
+  }
 
   // S_eps element kernel: LDS-staged or direct corner reads, whichever is
   // faster for this batch's restart tiles

@@ -5,6 +5,8 @@
 
 #include <array>
 #include <utility>
+#include <functional>
+#include <string>
 #include <vector>
 
 #include "autotune.h"
@@ -114,6 +116,8 @@ class Solver {
   int poll(const int* dev_counter);
   void push_tables();
   std::vector<Tile> tile_candidates() const;
+  TuneChoice tune_tiling(const std::string& key, Tile StepArgs::*field,
+                         const std::function<void()>& launch);
   void autotune();
   TuneChoice tuned_{};
 

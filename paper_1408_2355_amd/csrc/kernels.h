@@ -40,7 +40,10 @@ struct CgCols {
 
 struct StepArgs {
   Tile t;   // tiling of the streaming row kernels (no neighbour gathers)
-  Tile tm;  // tiling of the gathering row kernels (matrix products); same n, rp
+  Tile tm;  // tiling of the CG matrix product and the refinement update (gathers
+            // float32 in mixed precision); same n, rp
+  Tile t64;  // tiling of the kernels that gather float64 values (solve set-up,
+             // norms, Rayleigh quotients); same n, rp
   int W;
   const int* cols;
   const double* M64;

@@ -266,7 +266,7 @@ __global__ void k_fill(T* p, T v, size_t n) {
 __global__ __launch_bounds__(kBlock) void k_init_fp64(StepArgs a, const double* __restrict__ u,
                                                       double* __restrict__ r,
                                                       double* __restrict__ p) {
-  const Tile& t = a.tm;
+  const Tile& t = a.t64;
   for (int ct = 0; ct < t.nct; ++ct) {
   const int g = ct * t.tg + threadIdx.x % t.tg;
   double s[3][4] = {};
@@ -302,12 +302,12 @@ __global__ __launch_bounds__(kBlock) void k_init_fp64(StepArgs a, const double* 
 
 __global__ void k_red_init_fp64(StepArgs a) {
   const int c = red_col();
-  const Tile& t = a.tm;
+  const Tile& t = a.t64;
   const double bb = red_sum(a.part + part_off(t, 0), t.nchunk, t.rp, c);
   const double rz = red_sum(a.part + part_off(t, 1), t.nchunk, t.rp, c);
   const double rr = red_sum(a.part + part_off(t, 2), t.nchunk, t.rp, c);
   int act = 0;
-  if (red_lead() && c < a.tm.rp) {
+  if (red_lead() && c < a.t64.rp) {
     a.cg.bb[c] = bb;
     a.cg.rz[c] = rz;
     a.cg.tol2[c] = a.rtol2 * bb;
@@ -494,7 +494,7 @@ __global__ __launch_bounds__(kBlock) void k_init_outer(StepArgs a, const double*
                                                        const float* __restrict__ gd,
                                                        double* __restrict__ x0,
                                                        double* __restrict__ r64) {
-  const Tile& t = a.tm;
+  const Tile& t = a.t64;
   for (int ct = 0; ct < t.nct; ++ct) {
   const int g = ct * t.tg + threadIdx.x % t.tg;
   double s[2][4] = {};
@@ -538,7 +538,7 @@ __global__ __launch_bounds__(kBlock) void k_init_outer(StepArgs a, const double*
 
 __global__ void k_red_outer_init(StepArgs a) {
   const int c = red_col();
-  const Tile& t = a.tm;
+  const Tile& t = a.t64;
   const double bb = red_sum(a.part + part_off(t, 0), t.nchunk, t.rp, c);
   const double rr = red_sum(a.part + part_off(t, 1), t.nchunk, t.rp, c);
   int act = 0;
@@ -727,7 +727,7 @@ __global__ __launch_bounds__(kBlock) void k_nodal(StepArgs a, const double* __re
 
 // ---------------------------------------------------------- normalisation --
 __global__ __launch_bounds__(kBlock) void k_norm_dot(StepArgs a, const double* __restrict__ v) {
-  const Tile& t = a.tm;
+  const Tile& t = a.t64;
   for (int ct = 0; ct < t.nct; ++ct) {
   const int g = ct * t.tg + threadIdx.x % t.tg;
   double s[2][4] = {};
@@ -767,7 +767,7 @@ __global__ __launch_bounds__(kBlock) void k_norm_dot(StepArgs a, const double* _
 // estimates of the normalised state).
 __global__ void k_red_norm(StepArgs a, double* __restrict__ lam) {
   const int c = red_col();
-  const Tile& t = a.tm;
+  const Tile& t = a.t64;
   const bool lv = c < t.rp && a.ct.live[c];
   const double s = red_sum(a.part, lv ? t.nchunk : 0, t.rp, c);
   const double sa = red_sum(a.part + part_off(t, 1), lv ? t.nchunk : 0, t.rp, c);
@@ -791,10 +791,12 @@ __global__ __launch_bounds__(kBlock) void k_scale(StepArgs a, const double* __re
     inv[j] = 1.0 / a.cg.nrm[c0 + j];
   }
   if (!any) continue;
+  const bool all = lv[0] && lv[1] && lv[2] && lv[3];
   for_rows(t, [&](int row) {
     const size_t o = size_t(row) * t.rp + c0;
     const V4<double> vv = ld4(v + o);
-    V4<double> uv = ld4(u + o);
+    // columns that are not live keep their value (read only where needed)
+    V4<double> uv = all ? vv : ld4(u + o);
     for (int j = 0; j < 4; ++j)
       if (lv[j]) uv.v[j] = vv.v[j] * inv[j];
     st4(u + o, uv);
@@ -805,7 +807,7 @@ __global__ __launch_bounds__(kBlock) void k_scale(StepArgs a, const double* __re
 // ---------------------------------------------------------------- energies --
 // Rayleigh quotient parts u.Au and u.Mu per column.
 __global__ __launch_bounds__(kBlock) void k_energy_rq(StepArgs a, const double* __restrict__ u) {
-  const Tile& t = a.tm;
+  const Tile& t = a.t64;
   for (int ct = 0; ct < t.nct; ++ct) {
   const int g = ct * t.tg + threadIdx.x % t.tg;
   double s[2][4] = {};
@@ -1019,7 +1021,7 @@ __global__ __launch_bounds__(kBlock) void k_energy_seps_direct(StepArgs a, SepsP
 
 __global__ void k_red_lambda(StepArgs a, double* __restrict__ lam) {
   const int c = red_col();
-  const Tile& t = a.tm;
+  const Tile& t = a.t64;
   const bool real = c < t.rp && a.ct.seg_len[c] > 0;
   const double num = red_sum(a.part + part_off(t, 0), real ? t.nchunk : 0, t.rp, c);
   const double den = red_sum(a.part + part_off(t, 1), real ? t.nchunk : 0, t.rp, c);
@@ -1154,7 +1156,7 @@ void flag_nonconv(const StepArgs& a, const int* counter, hipStream_t s) {
 }
 
 void init_fp64(const StepArgs& a, const double* u, double* r, double* p, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_fp64, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, u, r, p);
+  hipLaunchKernelGGL(k_init_fp64, dim3(a.t64.nblk), dim3(kBlock), 0, s, a, u, r, p);
   SP_LAUNCH_CHECK();
 }
 
@@ -1198,7 +1200,7 @@ template void cg_iter<float>(const StepArgs&, int, float*, float*, float*, float
 
 void init_outer(const StepArgs& a, const double* u, const float* g, double* x0, double* r64,
                 hipStream_t s) {
-  hipLaunchKernelGGL(k_init_outer, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, u, g, x0, r64);
+  hipLaunchKernelGGL(k_init_outer, dim3(a.t64.nblk), dim3(kBlock), 0, s, a, u, g, x0, r64);
   SP_LAUNCH_CHECK();
 }
 
@@ -1243,7 +1245,7 @@ void nodal(const StepArgs& a, const double* u, double* out, hipStream_t s) {
 }
 
 void norm_dot(const StepArgs& a, const double* v, hipStream_t s) {
-  hipLaunchKernelGGL(k_norm_dot, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, v);
+  hipLaunchKernelGGL(k_norm_dot, dim3(a.t64.nblk), dim3(kBlock), 0, s, a, v);
   SP_LAUNCH_CHECK();
 }
 
@@ -1258,7 +1260,7 @@ void scale(const StepArgs& a, const double* v, double* u, hipStream_t s) {
 }
 
 void energy_rq(const StepArgs& a, const double* u, hipStream_t s) {
-  hipLaunchKernelGGL(k_energy_rq, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, u);
+  hipLaunchKernelGGL(k_energy_rq, dim3(a.t64.nblk), dim3(kBlock), 0, s, a, u);
   SP_LAUNCH_CHECK();
 }
 
