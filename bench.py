@@ -191,8 +191,9 @@ def main():
                     help="relative reduction of each float32 inner solve")
     ap.add_argument("--check-every", type=int, default=8,
                     help="CG iterations between host convergence polls")
-    ap.add_argument("--no-extrapolate", action="store_true",
-                    help="start every heat solve from u (not u + previous increment)")
+    ap.add_argument("--extrapolate", type=int, default=3, choices=(0, 1, 2, 3),
+                    help="previous heat increments used for each solve's start "
+                         "(0: start from u)")
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark instead: a seeded Poisson request stream over every "
                          "mesh kind through the continuous-batching server; prints latency "
@@ -236,7 +237,7 @@ def main():
     mesh = sp.Mesh(v, f)
     prm = sp.params(tau, precision="mixed", n_steps=1, energy_every=1, cg_rtol=1e-10,
                     inner_rtol=args.inner_rtol, max_outer=8, cg_max_iter=500,
-                    check_every=args.check_every, extrapolate=int(not args.no_extrapolate))
+                    check_every=args.check_every, extrapolate=args.extrapolate)
     st = sp.State(mesh, prm, ms, np.full(nres, eps), u0)
     del u0
     log(f"[bench] warmup {args.warmup} steps")

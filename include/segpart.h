@@ -122,17 +122,20 @@ typedef struct {
   int32_t check_every;  /* CG iterations between host-side convergence polls; 0 = no
                            polling (cg_max_iter device iterations are enqueued and the
                            kernels exit at once after convergence)                  */
-  int32_t extrapolate;  /* SP_MIXED only: 1 = start each heat solve from u + g, g the
-                           increment (u~ - u) extrapolated linearly from the last two
-                           steps (2 d_k - d_{k-1}; d_k alone after the first step),
-                           instead of from u; the solution is the same to cg_rtol,
-                           only the start differs.  Costs two float32 vectors per
-                           batch.  Ignored in SP_FP64 (which always starts from u) */
+  int32_t extrapolate;  /* SP_MIXED only: number q (0..3) of previous heat increments
+                           d = u~ - u used to start each heat solve from u + g
+                           instead of from u: g = d_k (q = 1), 2 d_k - d_{k-1}
+                           (q = 2) or 3 d_k - 3 d_{k-1} + d_{k-2} (q = 3), with
+                           fewer terms while fewer steps have been taken.  The
+                           solution is the same to cg_rtol, only the start moves.
+                           Costs q float32 vectors and one float64 vector per
+                           batch.  0 = start from u.  Ignored in SP_FP64 (which
+                           always starts from u)                                    */
 } sp_params;
 
 /* Fill *p with defaults for time step tau: n_steps 100, stop_tol 1e-6,
  * max_steps 10^6, energy_every = round(0.1 / tau), SP_MIXED, cg_rtol 1e-10,
- * cg_max_iter 500, inner_rtol 1e-5, max_outer 8, check_every 8, extrapolate 1. */
+ * cg_max_iter 500, inner_rtol 1e-5, max_outer 8, check_every 8, extrapolate 3. */
 void sp_params_default(sp_params* p, double tau);
 
 typedef struct {

@@ -4,6 +4,9 @@
 // (mesh size, ELL width, column count, precision, device); the winner is kept
 // in a process-wide table and, when SEGPART_TUNE_CACHE names a file, in that
 // JSON file as well (read at first use, rewritten after each new entry).
+// SEGPART_AUTOTUNE=0/1 switches the search off/on (default: on for batches of
+// at least 2^22 vertex-column values), SEGPART_TUNE_VERBOSE prints the
+// timings, SEGPART_SEPS_KERNEL=staged|direct forces the S_eps element kernel.
 #pragma once
 
 #include <string>

@@ -42,8 +42,8 @@ void validate_params(const sp_params& p) {
              "params: cg_rtol must be in (0, 1)");
   SP_REQUIRE(p.cg_max_iter >= 1, SP_EINVAL, "params: cg_max_iter must be >= 1");
   SP_REQUIRE(p.check_every >= 0, SP_EINVAL, "params: check_every must be >= 0");
-  SP_REQUIRE(p.extrapolate == 0 || p.extrapolate == 1, SP_EINVAL,
-             "params: extrapolate must be 0 or 1");
+  SP_REQUIRE(p.extrapolate >= 0 && p.extrapolate <= 3, SP_EINVAL,
+             "params: extrapolate must be 0, 1, 2 or 3");
   if (p.precision == SP_MIXED) {
     SP_REQUIRE(std::isfinite(p.inner_rtol) && p.inner_rtol > 0 && p.inner_rtol < 1, SP_EINVAL,
                "params: inner_rtol must be in (0, 1)");
@@ -102,13 +102,11 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
       r32_.alloc(nv);
       p32_.alloc(nv);
       q32_.alloc(nv);
-      if (prm_.extrapolate) {
-        dprev_.alloc(nv);
-        dprev2_.alloc(nv);
-        xg_.alloc(nv);
-        dlast_ = dprev_.p;
-        dnext_ = dprev2_.p;
+      for (int i = 0; i < prm_.extrapolate; ++i) {
+        dbuf_[i].alloc(nv);
+        dh_[i] = dbuf_[i].p;
       }
+      if (prm_.extrapolate) xg_.alloc(nv);
     }
     // partial sums: one row per workgroup, sized for the widest tiling the
     // autotuner may pick
@@ -127,10 +125,8 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
 
     k::fill_f64(u_.p, 0.0, nv, s_);
     k::fill_f64(r64_.p, 0.0, nv, s_);
-    if (dlast_) {
-      k::fill_f32(dlast_, 0.0f, nv, s_);
-      k::fill_f32(dnext_, 0.0f, nv, s_);
-    }
+    for (int i = 0; i < 3; ++i)
+      if (dh_[i]) k::fill_f32(dh_[i], 0.0f, nv, s_);
     k::fill_f64(colf_.p, 0.0, colf_.n, s_);
     k::fill_i32(coli_.p, 0, coli_.n, s_);
     k::fill_i32(ring_.p, 0, ring_.n, s_);
@@ -210,6 +206,12 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     push_tables();
     hist_.assign(nres, {});
     autotune();
+    // SEGPART_SEPS_KERNEL=staged|direct forces the S_eps element kernel
+    // (otherwise the autotuner's pick; the staged one when it did not run)
+    if (const char* e = std::getenv("SEGPART_SEPS_KERNEL")) {
+      if (std::strcmp(e, "direct") == 0) sp_.direct = 1;
+      if (std::strcmp(e, "staged") == 0) sp_.direct = 0;
+    }
   } catch (...) {
     if (h_poll_) (void)hipHostFree(h_poll_);
     h_poll_ = nullptr;
@@ -531,17 +533,26 @@ void Solver::heat_mixed() {
   const bool extrap = prm_.extrapolate != 0;
   double* x = u_.p;
   k::fill_i32(ring_.p, 0, ring_.n, s_);
+  const int q = prm_.extrapolate;
+  float* acc = extrap ? dh_[q - 1] : nullptr;  // receives g, then this step's increment
   if (extrap && n_prev_ >= 1) {
-    // start from x0 = u + g with g extrapolated from the last heat increments
-    // (g = 2 d_k - d_{k-1}, or d_k after the first step), into the separate
-    // iterate xg_; the refinement sweeps then accumulate this step's
-    // increment on top of g in dnext_
-    k::extrap(args_, n_prev_ >= 2 ? 2.0f : 1.0f, n_prev_ >= 2 ? -1.0f : 0.0f, dlast_, dnext_, s_);
-    k::init_outer(args_, u_.p, dnext_, xg_.p, r64_.p, s_);
+    // start from x0 = u + g, g extrapolated from the last heat increments d_k,
+    // d_{k-1}, d_{k-2} (as many as kept and available): d_k, 2 d_k - d_{k-1}
+    // or 3 d_k - 3 d_{k-1} + d_{k-2}; x0 goes to the separate iterate xg_
+    const int use = std::min(n_prev_, q);
+    if (use == 2 && acc == dh_[1])
+      k::extrap(args_, 2.0f, 0.0f, -1.0f, dh_[0], nullptr, acc, s_);
+    else if (use == 2)
+      k::extrap(args_, 2.0f, -1.0f, 0.0f, dh_[0], dh_[1], acc, s_);
+    else if (use == 3)
+      k::extrap(args_, 3.0f, -3.0f, 1.0f, dh_[0], dh_[1], acc, s_);
+    else if (acc != dh_[0])
+      k::extrap(args_, 1.0f, 0.0f, 0.0f, dh_[0], nullptr, acc, s_);
+    k::init_outer(args_, u_.p, acc, xg_.p, r64_.p, s_);
     x = xg_.p;
   } else {
     k::init_outer(args_, u_.p, nullptr, nullptr, r64_.p, s_);
-    if (extrap) k::fill_f32(dnext_, 0.0f, dprev2_.n, s_);
+    if (extrap) k::fill_f32(acc, 0.0f, dbuf_[0].n, s_);
   }
   k::red_outer_init(args_, s_);
   int olast = 0;
@@ -555,7 +566,7 @@ void Solver::heat_mixed() {
       if (prm_.check_every > 0 && last % prm_.check_every == 0 && last < prm_.cg_max_iter)
         if (poll(ring_.p + last % kRing) == 0) break;
     }
-    k::outer_update(args_, o, x, r64_.p, d32_.p, extrap ? dnext_ : nullptr, s_);
+    k::outer_update(args_, o, x, r64_.p, d32_.p, acc, s_);
     k::red_outer(args_, o, s_);
     olast = o + 1;
     if (prm_.check_every > 0 && olast < prm_.max_outer)
@@ -563,8 +574,9 @@ void Solver::heat_mixed() {
   }
   k::flag_nonconv(args_, args_.oring + olast % kRing, s_);
   if (extrap) {
-    std::swap(dlast_, dnext_);
-    n_prev_ = std::min(n_prev_ + 1, 2);
+    for (int i = q - 1; i > 0; --i) dh_[i] = dh_[i - 1];
+    dh_[0] = acc;
+    n_prev_ = std::min(n_prev_ + 1, q);
   }
   heat_x_ = x;
 }

@@ -132,13 +132,13 @@ class Solver {
 
   DevBuf<double> u_, r64_, p64_, q64_;
   DevBuf<float> d32_, r32_, p32_, q32_;
-  // heat increments of the last two steps (extrapolated start): dlast_ holds
-  // the latest, dnext_ the one before and, during a solve, the increment
-  // being accumulated; the two swap after each solve
-  DevBuf<float> dprev_, dprev2_;
-  float* dlast_ = nullptr;
-  float* dnext_ = nullptr;
-  int n_prev_ = 0;  // increments available (0, 1 or 2)
+  // heat increments of the last prm_.extrapolate steps (extrapolated start):
+  // dh_[0] the latest, dh_[q-1] the oldest; a solve overwrites the oldest
+  // with its start guess g and accumulates its own increment on top of it,
+  // then the ring rotates so that buffer becomes dh_[0]
+  DevBuf<float> dbuf_[3];
+  float* dh_[3] = {nullptr, nullptr, nullptr};
+  int n_prev_ = 0;  // increments available (0 .. prm_.extrapolate)
   DevBuf<double> xg_;          // iterate of a solve started from u + g (u stays b's source)
   double* heat_x_ = nullptr;   // where the last heat solve left its result (u_ or xg_)
   bool lam_fresh_ = false;  // lam holds the Rayleigh quotients of the current state

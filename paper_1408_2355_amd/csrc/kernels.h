@@ -104,8 +104,10 @@ void red_inner_init(const StepArgs& a, int o, hipStream_t s);
 // u += d, r64 -= K d on the columns still refining; dacc (nullable) += d
 void outer_update(const StepArgs& a, int o, double* u, double* r64, const float* d, float* dacc,
                   hipStream_t s);
-// y = ca x + cb y on the live columns, 0 on the others (cb == 0: y not read)
-void extrap(const StepArgs& a, float ca, float cb, const float* x, float* y, hipStream_t s);
+// y = c0 x0 + c1 x1 + c2 y on the live columns, 0 on the others (x1 read only
+// if c1 != 0, y only if c2 != 0); x0, x1 must not alias y
+void extrap(const StepArgs& a, float c0, float c1, float c2, const float* x0, const float* x1,
+            float* y, hipStream_t s);
 void red_outer(const StepArgs& a, int o, hipStream_t s);
 // node step and normalisation
 void nodal(const StepArgs& a, const double* u, double* out, hipStream_t s);

@@ -430,23 +430,27 @@ __global__ void k_red_beta(StepArgs a, int slot, int next) {
   count_active(still, a.ring + next);
 }
 
-// y = ca x + cb y on the live columns, 0 elsewhere (cb == 0: y is not read)
-__global__ __launch_bounds__(kBlock) void k_extrap(StepArgs a, float ca, float cb,
-                                                   const float* __restrict__ x,
+// y = c0 x0 + c1 x1 + c2 y on the live columns, 0 elsewhere (x1 is read only
+// when c1 != 0, y only when c2 != 0)
+__global__ __launch_bounds__(kBlock) void k_extrap(StepArgs a, float c0, float c1, float c2,
+                                                   const float* __restrict__ x0,
+                                                   const float* __restrict__ x1,
                                                    float* __restrict__ y) {
   const Tile& t = a.t;
   for (int ct = 0; ct < t.nct; ++ct) {
     const int g = ct * t.tg + threadIdx.x % t.tg;
     if (g >= t.G) continue;
-    const int c0 = 4 * g;
+    const int cb = 4 * g;
     bool lv[4];
-    for (int j = 0; j < 4; ++j) lv[j] = a.ct.live[c0 + j] != 0;
+    for (int j = 0; j < 4; ++j) lv[j] = a.ct.live[cb + j] != 0;
     for_rows(t, [&](int row) {
-      const size_t o = size_t(row) * t.rp + c0;
-      const V4<float> xv = ld4(x + o);
-      V4<float> yv = {};
-      if (cb != 0.0f) yv = ld4(y + o);
-      for (int j = 0; j < 4; ++j) yv.v[j] = lv[j] ? ca * xv.v[j] + cb * yv.v[j] : 0.0f;
+      const size_t o = size_t(row) * t.rp + cb;
+      const V4<float> av = ld4(x0 + o);
+      V4<float> bv = {}, yv = {};
+      if (c1 != 0.0f) bv = ld4(x1 + o);
+      if (c2 != 0.0f) yv = ld4(y + o);
+      for (int j = 0; j < 4; ++j)
+        yv.v[j] = lv[j] ? c0 * av.v[j] + c1 * bv.v[j] + c2 * yv.v[j] : 0.0f;
       st4(y + o, yv);
     });
   }
@@ -870,13 +874,11 @@ __device__ __forceinline__ void for_seps_chunks(const SepsPlan& sp, F&& f) {
 //   int_T sum_{i != j} u_i^2 u_j^2 = (2|T|/360) sum_i B(G_{<i}, a_i a_i^T),
 //   G_{<i} = sum_{j<i} a_j a_j^T,
 // a sum of nonnegative terms for nonnegative u (no cancellation).
-// quartic_pairs returns sum_i B(G_{<i}, a_i a_i^T) for one restart of m
-// components whose values at the three corners start at u0, u1, u2.
-__device__ __forceinline__ double quartic_pairs(const double* u0, const double* u1,
-                                                const double* u2, int m) {
+// QuarticPairs accumulates sum_i B(G_{<i}, a_i a_i^T) over the components of
+// one restart, fed in component order with their three corner values.
+struct QuarticPairs {
   double g00 = 0, g11 = 0, g22 = 0, g01 = 0, g02 = 0, g12 = 0, acc = 0;
-  for (int i = 0; i < m; ++i) {
-    const double x0 = u0[i], x1 = u1[i], x2 = u2[i];
+  __device__ __forceinline__ void add(double x0, double x1, double x2) {
     const double s1 = x0 + x1 + x2;
     const double q0 = x0 * x0, q1 = x1 * x1, q2 = x2 * x2;
     const double s2 = q0 + q1 + q2;
@@ -897,37 +899,59 @@ __device__ __forceinline__ double quartic_pairs(const double* u0, const double* 
     g02 += x0 * x2;
     g12 += x1 * x2;
   }
-  return acc;
+};
+
+// The sum for one restart of m components whose corner values start at u0,
+// u1, u2 (rows of global memory).  With 16-byte aligned starts the values
+// are read two at a time (half the load instructions; each lane's loads walk
+// one cache line).
+__device__ __forceinline__ double quartic_pairs(const double* u0, const double* u1,
+                                                const double* u2, int m) {
+  QuarticPairs qp;
+  int i = 0;
+  if (((reinterpret_cast<size_t>(u0) | reinterpret_cast<size_t>(u1) |
+        reinterpret_cast<size_t>(u2)) & 15) == 0) {
+    for (; i + 1 < m; i += 2) {
+      const double2 a0 = *reinterpret_cast<const double2*>(u0 + i);
+      const double2 a1 = *reinterpret_cast<const double2*>(u1 + i);
+      const double2 a2 = *reinterpret_cast<const double2*>(u2 + i);
+      qp.add(a0.x, a1.x, a2.x);
+      qp.add(a0.y, a1.y, a2.y);
+    }
+  }
+  for (; i < m; ++i) qp.add(u0[i], u1[i], u2[i]);
+  return qp.acc;
 }
 
-// Element kernel with LDS staging.  A workgroup takes one restart tile (a
-// run of restarts whose columns fit in kSepsCols) and one chunk of triangles.
-// Per pass it stages the three corner rows of up to 4 triangles, columns
-// [c0, c1), into LDS with coalesced loads (the triangles are sorted by
-// vertex, so neighbouring passes share rows in L2), then one thread per
-// (triangle, restart) runs the quartic over the staged values.  A tile wider
-// than kSepsCols reads its corners straight from global memory instead.
-// Partials per (triangle chunk, restart), reduced over the pass in fixed order.
-constexpr int kSepsCols = 256;
-constexpr int kSepsTri = 4;
+// Element kernel with LDS staging.  Thread (tb, rr) of a workgroup runs the
+// quartic of restart rr of the tile on triangle tb of the current pass (TB =
+// 256 / nr triangles per pass, so every thread works).  The components are
+// taken kSepsPiece at a time: the workgroup first copies, for every
+// (triangle, corner, restart), the restart's next kSepsPiece values of that
+// corner row (contiguous in memory, 16-byte loads) into LDS rows padded to an
+// odd length, so the threads of a wave read different banks; the quartic
+// state stays in registers between pieces.
+constexpr int kSepsPiece = 8;
+constexpr int kSepsPad = kSepsPiece + 1;
+constexpr int kSepsCols = 256;  // column budget of a restart tile
 
 __global__ __launch_bounds__(kBlock) void k_energy_seps(StepArgs a, SepsPlan sp,
                                                         const int* __restrict__ tri,
                                                         const double* __restrict__ tarea,
                                                         const double* __restrict__ u,
                                                         double* __restrict__ part_s) {
-  __shared__ double sh[kSepsTri * 3 * kSepsCols];
+  __shared__ double sh[kBlock * 3 * kSepsPad];
   __shared__ double red[kBlock];
   const int rp = a.t.rp;
   const int tid = threadIdx.x;
   for_seps_chunks(sp, [&](int tile, int cb, int ce, int stride) {
     const int4 tl = sp.tiles[tile];
-    const int r0 = tl.x, nr = tl.y - tl.x, c0 = tl.z, ncol = tl.w - tl.z;
-    const bool staged = ncol <= kSepsCols;
-    const int TB = max(1, min(kSepsTri, kBlock / max(nr, 1)));
-    const int tb = tid / max(nr, 1), rr = tid % max(nr, 1);
-    const bool worker = tid < TB * nr;
-    int lo = 0, m = 0;
+    const int r0 = tl.x, nr = max(tl.y - tl.x, 1);
+    const int TB = kBlock / nr;
+    const int tb = tid / nr, rr = tid % nr;
+    const bool worker = tb < TB;
+    int lo = 0, m = 0, mmax = 0;
+    for (int q = 0; q < nr; ++q) mmax = max(mmax, a.ct.res_len[r0 + q]);
     if (worker) {
       lo = a.ct.res_lo[r0 + rr];
       m = a.ct.res_len[r0 + rr];
@@ -936,31 +960,45 @@ __global__ __launch_bounds__(kBlock) void k_energy_seps(StepArgs a, SepsPlan sp,
     for (int chunk = cb; chunk < ce; chunk += stride) {
       const int t_beg = chunk * sp.tchunk, t_end = min(t_beg + sp.tchunk, sp.nt);
       for (int t0 = t_beg; t0 < t_end; t0 += TB) {
-        if (staged) {
-          const int per_tri = 3 * ncol;
-          for (int idx = tid; idx < TB * per_tri; idx += kBlock) {
-            const int bq = idx / per_tri, rem = idx - bq * per_tri;
-            const int k = rem / ncol, c = rem - k * ncol;
-            const int t = t0 + bq;
-            sh[(bq * 3 + k) * kSepsCols + c] =
-                t < t_end ? u[size_t(tri[3 * t + k]) * rp + c0 + c] : 0.0;
+        const int t = t0 + tb;
+        QuarticPairs qp;
+        for (int i0 = 0; i0 < mmax; i0 += kSepsPiece) {
+          // stage: item (triangle bq, corner k, restart q, half-piece h) of
+          // 2 doubles; TB * 3 * nr * (kSepsPiece / 2) items
+          const int nitem = TB * 3 * nr * (kSepsPiece / 2);
+          for (int it = tid; it < nitem; it += kBlock) {
+            const int h = it % (kSepsPiece / 2);
+            const int row3 = it / (kSepsPiece / 2);  // (bq * 3 + k) * nr + q
+            const int q = row3 % nr, bk = row3 / nr;
+            const int bq = bk / 3, k = bk - 3 * bq;
+            const int tt = t0 + bq;
+            const int ql = a.ct.res_lo[r0 + q], qm = a.ct.res_len[r0 + q];
+            const int i = i0 + 2 * h;
+            double2 v = make_double2(0.0, 0.0);
+            if (tt < t_end) {
+              const double* src = u + size_t(tri[3 * tt + k]) * rp + ql + i;
+              if (i + 1 < qm) {
+                v.x = src[0];
+                v.y = src[1];
+              } else if (i < qm) {
+                v.x = src[0];
+              }
+            }
+            double* dst = sh + size_t(row3) * kSepsPad + 2 * h;
+            dst[0] = v.x;
+            dst[1] = v.y;
+          }
+          __syncthreads();
+          if (worker && t < t_end) {
+            const double* b0 = sh + size_t((tb * 3 + 0) * nr + rr) * kSepsPad;
+            const double* b1 = sh + size_t((tb * 3 + 1) * nr + rr) * kSepsPad;
+            const double* b2 = sh + size_t((tb * 3 + 2) * nr + rr) * kSepsPad;
+            const int n = min(kSepsPiece, m - i0);
+            for (int i = 0; i < n; ++i) qp.add(b0[i], b1[i], b2[i]);
           }
           __syncthreads();
         }
-        const int t = t0 + tb;
-        if (worker && t < t_end && m > 0) {
-          double q;
-          if (staged) {
-            const double* base = sh + size_t(tb) * 3 * kSepsCols + (lo - c0);
-            q = quartic_pairs(base, base + kSepsCols, base + 2 * kSepsCols, m);
-          } else {
-            q = quartic_pairs(u + size_t(tri[3 * t + 0]) * rp + lo,
-                              u + size_t(tri[3 * t + 1]) * rp + lo,
-                              u + size_t(tri[3 * t + 2]) * rp + lo, m);
-          }
-          acc += q * tarea[t] * (1.0 / 180.0);
-        }
-        if (staged) __syncthreads();
+        if (worker && t < t_end && m > 0) acc += qp.acc * tarea[t] * (1.0 / 180.0);
       }
     }
     red[tid] = acc;
@@ -1228,8 +1266,9 @@ void outer_update(const StepArgs& a, int o, double* u, double* r64, const float*
   SP_LAUNCH_CHECK();
 }
 
-void extrap(const StepArgs& a, float ca, float cb, const float* x, float* y, hipStream_t s) {
-  hipLaunchKernelGGL(k_extrap, dim3(a.t.nblk), dim3(kBlock), 0, s, a, ca, cb, x, y);
+void extrap(const StepArgs& a, float c0, float c1, float c2, const float* x0, const float* x1,
+            float* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_extrap, dim3(a.t.nblk), dim3(kBlock), 0, s, a, c0, c1, c2, x0, x1, y);
   SP_LAUNCH_CHECK();
 }
 

@@ -1,0 +1,109 @@
+"""The level-7 batched workload at full size, in the launch configuration the
+throughput benchmark times, against the oracle on sampled restarts.
+
+Unit sphere, icosahedral level 7 (163842 vertices), m in {4, 8, 12, 16} with
+64 restarts each (2560 columns, u0 seeds 3000 + m), eps = 0.01, tau = 5e-5,
+float32 CG in float64 refinement (outer rtol 1e-10, inner 1e-6, poll every 8
+iterations), start extrapolated from three increments, energy every step.
+Four steps (the fourth uses the three-increment start), once with each S_eps
+element kernel.
+
+Checks: the two runs give the same state (the S_eps kernel does not touch
+the flow) and the same S_eps to 1e-12; restart 0 of every m group matches the
+oracle run of that restart alone (u, every lambda_i, S_eps, E) within 1e-5,
+the mixed-precision bar; every restart's E equals its sum lambda + S_eps.
+"""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import flow  # noqa: E402
+from paper_1408_2355_amd import segpart as sp  # noqa: E402
+from workloads import batch_u0, icosphere  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+GROUPS = [(3004, 64, 4), (3008, 64, 8), (3012, 64, 12), (3016, 64, 16)]
+EPS, TAU, STEPS = 0.01, 5e-5, 4
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def runs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    v, f = icosphere(7)
+    n = v.shape[0]
+    u0, ms = batch_u0(n, GROUPS)
+    mesh = sp.Mesh(v, f)
+    first = np.concatenate([[0], np.cumsum([g[1] for g in GROUPS])[:-1]])  # restart 0 of each group
+    col0 = np.concatenate([[0], np.cumsum(ms)])
+    out = {}
+    old = os.environ.get("SEGPART_SEPS_KERNEL")
+    try:
+        for kern in ("staged", "direct"):
+            os.environ["SEGPART_SEPS_KERNEL"] = kern
+            print(f"level 7 batch, {STEPS} steps, S_eps kernel {kern}", flush=True)
+            prm = sp.params(TAU, precision="mixed", n_steps=1, energy_every=1, cg_rtol=1e-10,
+                            inner_rtol=1e-6, max_outer=8, cg_max_iter=500, check_every=8,
+                            extrapolate=3)
+            st = sp.State(mesh, prm, ms, np.full(ms.size, EPS), u0)
+            try:
+                assert st.step(STEPS) == sp.SP_OK
+                lam, s, e = st.energy()
+                u, k = st.read()
+                assert k == STEPS
+                rows = np.concatenate([np.arange(col0[r], col0[r + 1]) for r in first])
+                out[kern] = dict(lam=lam, s_eps=s, energy=e, u_sample=u[rows].copy(),
+                                 u_sum=np.abs(u).sum(axis=1))
+                del u
+            finally:
+                st.close()
+    finally:
+        if old is None:
+            os.environ.pop("SEGPART_SEPS_KERNEL", None)
+        else:
+            os.environ["SEGPART_SEPS_KERNEL"] = old
+    return v, f, u0, ms, first, col0, out
+
+
+def test_seps_kernels_agree_and_flow_is_unchanged(runs):
+    v, f, u0, ms, first, col0, out = runs
+    a, b = out["staged"], out["direct"]
+    assert rel(b["u_sample"], a["u_sample"]) < 1e-14
+    assert rel(b["u_sum"], a["u_sum"]) < 1e-14
+    assert rel(b["lam"], a["lam"]) < 1e-13
+    assert rel(b["s_eps"], a["s_eps"]) < 1e-12
+    for kern in ("staged", "direct"):
+        r = out[kern]
+        lo = 0
+        for i, m in enumerate(ms):
+            assert abs(r["energy"][i] - (r["lam"][lo:lo + m].sum() + r["s_eps"][i])) <= \
+                1e-12 * abs(r["energy"][i])
+            lo += m
+        assert np.all(np.isfinite(r["lam"])) and np.all(r["lam"] > 0) and np.all(r["s_eps"] > 0)
+
+
+def test_sampled_restarts_match_oracle(runs):
+    v, f, u0, ms, first, col0, out = runs
+    print("oracle factorisation (level 7)", flush=True)
+    prob = flow.Problem(v, f, TAU)
+    res = out["direct"]
+    off = 0
+    for r in first:
+        m = int(ms[r])
+        print(f"  oracle restart {r} (m = {m})", flush=True)
+        ref = flow.run(prob, u0[col0[r]:col0[r + 1]], [m], [EPS], STEPS)
+        got_u = res["u_sample"][off:off + m]
+        off += m
+        assert rel(got_u, ref["u"]) < 1e-5
+        assert rel(res["lam"][col0[r]:col0[r + 1]], ref["lam"]) < 1e-5
+        assert abs(res["s_eps"][r] - ref["s_eps"][0]) < 1e-5 * ref["s_eps"][0]
+        assert abs(res["energy"][r] - ref["energy"][0]) < 1e-5 * ref["energy"][0]

@@ -193,26 +193,28 @@ def test_config1_mixed_end_to_end():
 
 
 def test_extrapolated_start_gives_the_same_flow():
-    """The extrapolated CG start changes only where each solve begins: the
-    flow matches the plain start (and the oracle) to the solver tolerance."""
+    """The extrapolated CG start (from 1, 2 or 3 previous increments) changes
+    only where each solve begins: the flow matches the plain start (and the
+    oracle) to the solver tolerance, in fewer iterations."""
     v, f = icosphere(4)
     u0, ms = batch_u0(v.shape[0], [(41, 2, 4), (42, 1, 8)])
     eps = np.array([0.05, 0.05, 0.03])
     tau = 2e-4
     mesh = sp.Mesh(v, f)
-    outs = []
-    for ex in (0, 1):
+    outs = {}
+    for ex in (0, 1, 2, 3):
         say("extrapolate", ex)
         prm = sp.params(tau, precision="mixed", n_steps=40, cg_rtol=1e-12, energy_every=0,
                         extrapolate=ex)
         rc, out = sp.solve(mesh, prm, ms, eps, u0)
         assert rc == sp.SP_OK
-        outs.append(out)
-    assert rel(outs[1]["u"], outs[0]["u"]) < 1e-8
-    assert outs[1]["stats"]["cg_iters"] < outs[0]["stats"]["cg_iters"]
+        outs[ex] = out
     ref = flow.run(flow.Problem(v, f, tau), u0, ms, eps, 40)
-    assert rel(outs[1]["lam"], ref["lam"]) < 1e-8
-    assert rel(outs[1]["s_eps"], ref["s_eps"]) < 1e-8
+    for ex in (1, 2, 3):
+        assert rel(outs[ex]["u"], outs[0]["u"]) < 1e-8
+        assert outs[ex]["stats"]["cg_iters"] < outs[0]["stats"]["cg_iters"]
+        assert rel(outs[ex]["lam"], ref["lam"]) < 1e-8
+        assert rel(outs[ex]["s_eps"], ref["s_eps"]) < 1e-8
 
 
 def test_batch_of_mixed_m_equals_each_restart_alone():
