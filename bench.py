@@ -191,7 +191,7 @@ def main():
                     help="relative reduction of each float32 inner solve")
     ap.add_argument("--check-every", type=int, default=8,
                     help="CG iterations between host convergence polls")
-    ap.add_argument("--extrapolate", type=int, default=3, choices=(0, 1, 2, 3),
+    ap.add_argument("--extrapolate", type=int, default=5, choices=range(9),
                     help="previous heat increments used for each solve's start "
                          "(0: start from u)")
     ap.add_argument("--serve", action="store_true",

@@ -122,20 +122,21 @@ typedef struct {
   int32_t check_every;  /* CG iterations between host-side convergence polls; 0 = no
                            polling (cg_max_iter device iterations are enqueued and the
                            kernels exit at once after convergence)                  */
-  int32_t extrapolate;  /* SP_MIXED only: number q (0..3) of previous heat increments
+  int32_t extrapolate;  /* SP_MIXED only: number q (0..8) of previous heat increments
                            d = u~ - u used to start each heat solve from u + g
-                           instead of from u: g = d_k (q = 1), 2 d_k - d_{k-1}
-                           (q = 2) or 3 d_k - 3 d_{k-1} + d_{k-2} (q = 3), with
-                           fewer terms while fewer steps have been taken.  The
-                           solution is the same to cg_rtol, only the start moves.
-                           Costs q float32 vectors and one float64 vector per
-                           batch.  0 = start from u.  Ignored in SP_FP64 (which
-                           always starts from u)                                    */
+                           instead of from u; g extrapolates the increments with a
+                           polynomial through the last q of them,
+                           g = sum_{j<q} (-1)^j C(q, j+1) d_{k-j} (q = 1: d_k;
+                           q = 3: 3 d_k - 3 d_{k-1} + d_{k-2}), with fewer terms
+                           while fewer steps have been taken.  The solution is the
+                           same to cg_rtol, only the start moves.  Costs q float32
+                           vectors and one float64 vector per batch.  0 = start
+                           from u.  Ignored in SP_FP64 (always starts from u)       */
 } sp_params;
 
 /* Fill *p with defaults for time step tau: n_steps 100, stop_tol 1e-6,
  * max_steps 10^6, energy_every = round(0.1 / tau), SP_MIXED, cg_rtol 1e-10,
- * cg_max_iter 500, inner_rtol 1e-5, max_outer 8, check_every 8, extrapolate 3. */
+ * cg_max_iter 500, inner_rtol 1e-5, max_outer 8, check_every 8, extrapolate 5. */
 void sp_params_default(sp_params* p, double tau);
 
 typedef struct {

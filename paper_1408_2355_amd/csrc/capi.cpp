@@ -87,7 +87,7 @@ void sp_params_default(sp_params* p, double tau) {
   p->inner_rtol = 1e-5;
   p->max_outer = 8;
   p->check_every = 8;
-  p->extrapolate = 3;
+  p->extrapolate = 5;
 }
 
 int sp_mesh_create(int64_t n_vert, const double* xyz, int64_t n_tri, const int32_t* tri,

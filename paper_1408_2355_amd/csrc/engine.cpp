@@ -42,8 +42,8 @@ void validate_params(const sp_params& p) {
              "params: cg_rtol must be in (0, 1)");
   SP_REQUIRE(p.cg_max_iter >= 1, SP_EINVAL, "params: cg_max_iter must be >= 1");
   SP_REQUIRE(p.check_every >= 0, SP_EINVAL, "params: check_every must be >= 0");
-  SP_REQUIRE(p.extrapolate >= 0 && p.extrapolate <= 3, SP_EINVAL,
-             "params: extrapolate must be 0, 1, 2 or 3");
+  SP_REQUIRE(p.extrapolate >= 0 && p.extrapolate <= kMaxExtrap, SP_EINVAL,
+             "params: extrapolate must be in 0..8");
   if (p.precision == SP_MIXED) {
     SP_REQUIRE(std::isfinite(p.inner_rtol) && p.inner_rtol > 0 && p.inner_rtol < 1, SP_EINVAL,
                "params: inner_rtol must be in (0, 1)");
@@ -125,7 +125,7 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
 
     k::fill_f64(u_.p, 0.0, nv, s_);
     k::fill_f64(r64_.p, 0.0, nv, s_);
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < kMaxExtrap; ++i)
       if (dh_[i]) k::fill_f32(dh_[i], 0.0f, nv, s_);
     k::fill_f64(colf_.p, 0.0, colf_.n, s_);
     k::fill_i32(coli_.p, 0, coli_.n, s_);
@@ -536,18 +536,22 @@ void Solver::heat_mixed() {
   const int q = prm_.extrapolate;
   float* acc = extrap ? dh_[q - 1] : nullptr;  // receives g, then this step's increment
   if (extrap && n_prev_ >= 1) {
-    // start from x0 = u + g, g extrapolated from the last heat increments d_k,
-    // d_{k-1}, d_{k-2} (as many as kept and available): d_k, 2 d_k - d_{k-1}
-    // or 3 d_k - 3 d_{k-1} + d_{k-2}; x0 goes to the separate iterate xg_
+    // start from x0 = u + g, g the polynomial extrapolation of the last heat
+    // increments d_k, d_{k-1}, ... (as many as kept and available):
+    // g = sum_j (-1)^j C(use, j+1) d_{k-j}, e.g. 3 d_k - 3 d_{k-1} + d_{k-2};
+    // g overwrites the oldest kept increment (acc) and x0 goes to xg_
     const int use = std::min(n_prev_, q);
-    if (use == 2 && acc == dh_[1])
-      k::extrap(args_, 2.0f, 0.0f, -1.0f, dh_[0], nullptr, acc, s_);
-    else if (use == 2)
-      k::extrap(args_, 2.0f, -1.0f, 0.0f, dh_[0], dh_[1], acc, s_);
-    else if (use == 3)
-      k::extrap(args_, 3.0f, -3.0f, 1.0f, dh_[0], dh_[1], acc, s_);
-    else if (acc != dh_[0])
-      k::extrap(args_, 1.0f, 0.0f, 0.0f, dh_[0], nullptr, acc, s_);
+    if (!(use == 1 && acc == dh_[0])) {
+      ExtrapArgs e;
+      e.n = use;
+      int binom = 1;  // C(use, j + 1), built up from C(use, 0) = 1
+      for (int j = 0; j < use; ++j) {
+        binom = binom * (use - j) / (j + 1);
+        e.x[j] = dh_[j];
+        e.c[j] = float((j % 2 == 0) ? binom : -binom);
+      }
+      k::extrap(args_, e, acc, s_);
+    }
     k::init_outer(args_, u_.p, acc, xg_.p, r64_.p, s_);
     x = xg_.p;
   } else {

@@ -136,8 +136,8 @@ class Solver {
   // dh_[0] the latest, dh_[q-1] the oldest; a solve overwrites the oldest
   // with its start guess g and accumulates its own increment on top of it,
   // then the ring rotates so that buffer becomes dh_[0]
-  DevBuf<float> dbuf_[3];
-  float* dh_[3] = {nullptr, nullptr, nullptr};
+  DevBuf<float> dbuf_[kMaxExtrap];
+  float* dh_[kMaxExtrap] = {};
   int n_prev_ = 0;  // increments available (0 .. prm_.extrapolate)
   DevBuf<double> xg_;          // iterate of a solve started from u + g (u stays b's source)
   double* heat_x_ = nullptr;   // where the last heat solve left its result (u_ or xg_)

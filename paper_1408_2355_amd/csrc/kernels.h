@@ -64,6 +64,14 @@ struct StepArgs {
                        // [3] active columns summed over CG iterations
 };
 
+// Linear combination of up to kMaxExtrap float32 vectors (start guess).
+constexpr int kMaxExtrap = 8;
+struct ExtrapArgs {
+  const float* x[kMaxExtrap] = {};
+  float c[kMaxExtrap] = {};
+  int n = 0;
+};
+
 // Triangle-chunk x restart-tile plan of the S_eps element kernel.
 struct SepsPlan {
   const int4* tiles = nullptr;  // (r0, r1, c0, c1): restarts [r0, r1) use columns [c0, c1)
@@ -104,10 +112,9 @@ void red_inner_init(const StepArgs& a, int o, hipStream_t s);
 // u += d, r64 -= K d on the columns still refining; dacc (nullable) += d
 void outer_update(const StepArgs& a, int o, double* u, double* r64, const float* d, float* dacc,
                   hipStream_t s);
-// y = c0 x0 + c1 x1 + c2 y on the live columns, 0 on the others (x1 read only
-// if c1 != 0, y only if c2 != 0); x0, x1 must not alias y
-void extrap(const StepArgs& a, float c0, float c1, float c2, const float* x0, const float* x1,
-            float* y, hipStream_t s);
+// y = sum_j e.c[j] e.x[j] on the live columns, 0 on the others; y may be
+// one of the sources
+void extrap(const StepArgs& a, const ExtrapArgs& e, float* y, hipStream_t s);
 void red_outer(const StepArgs& a, int o, hipStream_t s);
 // node step and normalisation
 void nodal(const StepArgs& a, const double* u, double* out, hipStream_t s);

@@ -430,12 +430,9 @@ __global__ void k_red_beta(StepArgs a, int slot, int next) {
   count_active(still, a.ring + next);
 }
 
-// y = c0 x0 + c1 x1 + c2 y on the live columns, 0 elsewhere (x1 is read only
-// when c1 != 0, y only when c2 != 0)
-__global__ __launch_bounds__(kBlock) void k_extrap(StepArgs a, float c0, float c1, float c2,
-                                                   const float* __restrict__ x0,
-                                                   const float* __restrict__ x1,
-                                                   float* __restrict__ y) {
+// y = sum_j e.c[j] e.x[j] on the live columns, 0 elsewhere.  y may be one of
+// the sources (each element is read before it is written, by the same thread).
+__global__ __launch_bounds__(kBlock) void k_extrap(StepArgs a, ExtrapArgs e, float* y) {
   const Tile& t = a.t;
   for (int ct = 0; ct < t.nct; ++ct) {
     const int g = ct * t.tg + threadIdx.x % t.tg;
@@ -445,12 +442,13 @@ __global__ __launch_bounds__(kBlock) void k_extrap(StepArgs a, float c0, float c
     for (int j = 0; j < 4; ++j) lv[j] = a.ct.live[cb + j] != 0;
     for_rows(t, [&](int row) {
       const size_t o = size_t(row) * t.rp + cb;
-      const V4<float> av = ld4(x0 + o);
-      V4<float> bv = {}, yv = {};
-      if (c1 != 0.0f) bv = ld4(x1 + o);
-      if (c2 != 0.0f) yv = ld4(y + o);
-      for (int j = 0; j < 4; ++j)
-        yv.v[j] = lv[j] ? c0 * av.v[j] + c1 * bv.v[j] + c2 * yv.v[j] : 0.0f;
+      float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+      for (int q = 0; q < e.n; ++q) {
+        const V4<float> v = ld4(e.x[q] + o);
+        for (int j = 0; j < 4; ++j) acc[j] = fmaf(e.c[q], v.v[j], acc[j]);
+      }
+      V4<float> yv;
+      for (int j = 0; j < 4; ++j) yv.v[j] = lv[j] ? acc[j] : 0.0f;
       st4(y + o, yv);
     });
   }
@@ -1266,9 +1264,8 @@ void outer_update(const StepArgs& a, int o, double* u, double* r64, const float*
   SP_LAUNCH_CHECK();
 }
 
-void extrap(const StepArgs& a, float c0, float c1, float c2, const float* x0, const float* x1,
-            float* y, hipStream_t s) {
-  hipLaunchKernelGGL(k_extrap, dim3(a.t.nblk), dim3(kBlock), 0, s, a, c0, c1, c2, x0, x1, y);
+void extrap(const StepArgs& a, const ExtrapArgs& e, float* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_extrap, dim3(a.t.nblk), dim3(kBlock), 0, s, a, e, y);
   SP_LAUNCH_CHECK();
 }
 

@@ -4,8 +4,8 @@ throughput benchmark times, against the oracle on sampled restarts.
 Unit sphere, icosahedral level 7 (163842 vertices), m in {4, 8, 12, 16} with
 64 restarts each (2560 columns, u0 seeds 3000 + m), eps = 0.01, tau = 5e-5,
 float32 CG in float64 refinement (outer rtol 1e-10, inner 1e-6, poll every 8
-iterations), start extrapolated from three increments, energy every step.
-Four steps (the fourth uses the three-increment start), once with each S_eps
+iterations), start extrapolated from five increments, energy every step.
+Six steps (the sixth uses the five-increment start), once with each S_eps
 element kernel.
 
 Checks: the two runs give the same state (the S_eps kernel does not touch
@@ -27,7 +27,7 @@ from workloads import batch_u0, icosphere  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 GROUPS = [(3004, 64, 4), (3008, 64, 8), (3012, 64, 12), (3016, 64, 16)]
-EPS, TAU, STEPS = 0.01, 5e-5, 4
+EPS, TAU, STEPS = 0.01, 5e-5, 6
 
 
 def rel(a, b):
@@ -53,7 +53,7 @@ def runs():
             print(f"level 7 batch, {STEPS} steps, S_eps kernel {kern}", flush=True)
             prm = sp.params(TAU, precision="mixed", n_steps=1, energy_every=1, cg_rtol=1e-10,
                             inner_rtol=1e-6, max_outer=8, cg_max_iter=500, check_every=8,
-                            extrapolate=3)
+                            extrapolate=5)
             st = sp.State(mesh, prm, ms, np.full(ms.size, EPS), u0)
             try:
                 assert st.step(STEPS) == sp.SP_OK
