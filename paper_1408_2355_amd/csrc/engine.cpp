@@ -23,7 +23,7 @@
 namespace sp {
 
 namespace {
-enum { CF_BB, CF_RZ, CF_TOL2, CF_ALPHA, CF_BETA, CF_RRO, CF_NRM, CF_COEF, CF_N };
+enum { CF_BB, CF_RZ, CF_TOL2, CF_ALPHA, CF_BETA, CF_RRO, CF_NRM, CF_BBN, CF_COEF, CF_N };
 enum { CI_ACT, CI_ACTO, CI_ITERS, CI_SWEEPS, CI_SEGLO, CI_SEGLEN, CI_LIVE, CI_N };
 }  // namespace
 
@@ -159,6 +159,7 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     a.cg.beta = cf + CF_BETA * rp_;
     a.cg.rr_o = cf + CF_RRO * rp_;
     a.cg.nrm = cf + CF_NRM * rp_;
+    a.cg.bb_next = cf + CF_BBN * rp_;
     a.ct.coef = cf + CF_COEF * rp_;
     a.ct.res_ieps2 = cf + CF_N * rp_;
     a.cg.act = ci + CI_ACT * rp_;
@@ -321,7 +322,7 @@ void Solver::autotune() {
     args_.t64 = args_.tm;
   } else {
     const TuneChoice b64 = tune_tiling(key + "_gather64", &StepArgs::t64,
-                                       [&] { k::norm_dot(args_, u_.p, s_); });
+                                       [&] { k::norm_dot(args_, u_.p, nullptr, s_); });
     args_.t64 = make_tile(int(mesh_->n), rp_, b64.tg_cap, b64.passes, b64.nper_cap);
   }
 
@@ -408,6 +409,7 @@ void Solver::set_columns(const std::vector<int>& seg_lo, const std::vector<int>&
   }
   args_.ct.nres = int(res_lo.size());
   push_tables();
+  aw_fresh_ = false;
 }
 
 void Solver::set_restart_live(int r, bool live) {
@@ -416,6 +418,7 @@ void Solver::set_restart_live(int r, bool live) {
   for (int j = 0; j < m; ++j) h_live_[lo + j] = live ? 1 : 0;
   h_res_live_[r] = live ? 1 : 0;
   push_tables();
+  aw_fresh_ = false;
 }
 
 int Solver::poll(const int* dev_counter) {
@@ -427,6 +430,7 @@ int Solver::poll(const int* dev_counter) {
 void Solver::sync() { SP_HIP(hipStreamSynchronize(s_)); }
 
 void Solver::upload_host(const double* u0, bool normalise) {
+  aw_fresh_ = false;
   SP_REQUIRE(u0 != nullptr, SP_EINVAL, "NULL u0");
   n_prev_ = 0;
   lam_fresh_ = false;
@@ -443,6 +447,7 @@ void Solver::upload_host(const double* u0, bool normalise) {
 }
 
 void Solver::upload_device(const double* d_u0, bool normalise, bool check_norms) {
+  aw_fresh_ = false;
   SP_REQUIRE(d_u0 != nullptr, SP_EINVAL, "NULL u0");
   n_prev_ = 0;
   lam_fresh_ = false;
@@ -451,7 +456,7 @@ void Solver::upload_device(const double* d_u0, bool normalise, bool check_norms)
     if (check_norms) {
       normalise_columns();
     } else {
-      k::norm_dot(args_, u_.p, s_);
+      k::norm_dot(args_, u_.p, nullptr, s_);
       k::red_norm(args_, lam_.p, s_);
       k::scale(args_, u_.p, u_.p, s_);
       lam_fresh_ = all_live_;
@@ -460,7 +465,7 @@ void Solver::upload_device(const double* d_u0, bool normalise, bool check_norms)
 }
 
 void Solver::normalise_columns() {
-  k::norm_dot(args_, u_.p, s_);
+  k::norm_dot(args_, u_.p, nullptr, s_);
   k::red_norm(args_, lam_.p, s_);
   std::vector<double> nrm(rp_);
   SP_HIP(hipMemcpyAsync(nrm.data(), args_.cg.nrm, rp_ * sizeof(double), hipMemcpyDeviceToHost, s_));
@@ -475,6 +480,7 @@ void Solver::normalise_columns() {
 }
 
 void Solver::pack_range(int c_lo, int Rq, const double* d_src) {
+  aw_fresh_ = false;
   SP_REQUIRE(c_lo >= 0 && Rq >= 0 && c_lo + Rq <= rp_, SP_EINVAL, "column range");
   n_prev_ = 0;  // the new columns have no previous increment
   lam_fresh_ = false;
@@ -487,6 +493,7 @@ void Solver::unpack_range(int c_lo, int Rq, double* d_dst) {
 }
 
 void Solver::normalise_range(int c_lo, int Rq) {
+  aw_fresh_ = false;
   std::vector<int> saved = h_live_;
   for (int c = 0; c < rp_; ++c) h_live_[c] = (c >= c_lo && c < c_lo + Rq) ? saved[c] : 0;
   push_tables();
@@ -535,6 +542,9 @@ void Solver::heat_mixed() {
   k::fill_i32(ring_.p, 0, ring_.n, s_);
   const int q = prm_.extrapolate;
   float* acc = extrap ? dh_[q - 1] : nullptr;  // receives g, then this step's increment
+  // the norm pass that scaled u left A u (times ||v||_M) in xg_
+  const bool fast = aw_fresh_ && extrap && n_prev_ >= 1;
+  aw_fresh_ = false;
   if (extrap && n_prev_ >= 1) {
     // start from x0 = u + g, g the polynomial extrapolation of the last heat
     // increments d_k, d_{k-1}, ... (as many as kept and available):
@@ -552,17 +562,25 @@ void Solver::heat_mixed() {
       }
       k::extrap(args_, e, acc, s_);
     }
-    k::init_outer(args_, u_.p, acc, xg_.p, r64_.p, s_);
+    if (fast) {
+      // A u and ||M u||^2 from the last step's norm pass: no float64 gather
+      k::refine_start(args_, u_.p, xg_.p, acc, r64_.p, d32_.p, r32_.p, p32_.p, s_);
+    } else {
+      k::init_outer(args_, u_.p, acc, xg_.p, r64_.p, s_);
+      k::red_outer_init(args_, s_);
+    }
     x = xg_.p;
   } else {
     k::init_outer(args_, u_.p, nullptr, nullptr, r64_.p, s_);
+    k::red_outer_init(args_, s_);
     if (extrap) k::fill_f32(acc, 0.0f, dbuf_[0].n, s_);
   }
-  k::red_outer_init(args_, s_);
   int olast = 0;
   for (int o = 0; o < prm_.max_outer; ++o) {
-    k::inner_init(args_, o, r64_.p, d32_.p, r32_.p, p32_.p, s_);
-    k::red_inner_init(args_, o, s_);
+    if (!(fast && o == 0)) {
+      k::inner_init(args_, o, r64_.p, d32_.p, r32_.p, p32_.p, s_);
+      k::red_inner_init(args_, o, s_);
+    }
     for (int it = 0; it < prm_.cg_max_iter; ++it) {
       k::cg_iter<float>(args_, it, d32_.p, r32_.p, p32_.p, q32_.p, km_->K32.p, km_->dinv32.p, s_,
                         prof_events());
@@ -594,6 +612,7 @@ void Solver::heat() {
 }
 
 void Solver::stage_heat() {
+  aw_fresh_ = false;
   heat();
   if (heat_x_ != u_.p)
     SP_HIP(hipMemcpyAsync(u_.p, heat_x_, u_.n * sizeof(double), hipMemcpyDeviceToDevice, s_));
@@ -607,20 +626,28 @@ void Solver::node_to_r() {
 }
 
 void Solver::norm_dot_scale(const double* v) {
-  k::norm_dot(args_, v, s_);
+  // in a step the norm pass also leaves A v in xg_ (free after the node
+  // step) for the next step's refinement start
+  double* w = (xg_.p && v == r64_.p) ? xg_.p : nullptr;
+  k::norm_dot(args_, v, w, s_);
   k::red_norm(args_, lam_.p, s_);
   k::scale(args_, v, u_.p, s_);
   lam_fresh_ = all_live_;
+  aw_fresh_ = w != nullptr;
 }
 
 void Solver::stage_node() {
+  aw_fresh_ = false;
   lam_fresh_ = false;
   node_to_r();
   k::fill_f64(args_.cg.nrm, 1.0, rp_, s_);
   k::scale(args_, r64_.p, u_.p, s_);
 }
 
-void Solver::stage_norm() { norm_dot_scale(u_.p); }
+void Solver::stage_norm() {
+  aw_fresh_ = false;
+  norm_dot_scale(u_.p);
+}
 
 void Solver::energy() {
   if (args_.ct.nres == 0) return;

@@ -102,7 +102,10 @@ class Solver {
   // Skip the stream synchronisation in the destructor (work already done).
   void detach() { detached_ = true; }
   // Forget the previous heat increment (the next step starts from x0 = u).
-  void reset_guess() { n_prev_ = 0; }
+  void reset_guess() {
+    n_prev_ = 0;
+    aw_fresh_ = false;
+  }
 
   bool record_history = true;          // copy energies to the host at the cadence
   std::vector<int64_t> restart_steps;  // per restart: steps taken (stop mode)
@@ -141,6 +144,9 @@ class Solver {
   int n_prev_ = 0;  // increments available (0 .. prm_.extrapolate)
   DevBuf<double> xg_;          // iterate of a solve started from u + g (u stays b's source)
   double* heat_x_ = nullptr;   // where the last heat solve left its result (u_ or xg_)
+  bool aw_fresh_ = false;      // xg_ holds A v of the norm pass that produced u (and
+                               // cg.bb_next its ||M u||^2): the next solve can start
+                               // without gathering u
   bool lam_fresh_ = false;  // lam holds the Rayleigh quotients of the current state
   bool all_live_ = true;    // every real column is live
   DevBuf<double> part_, part_s_;

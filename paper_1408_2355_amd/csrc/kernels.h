@@ -32,6 +32,7 @@ struct CgCols {
   double* beta;
   double* rr_o;   // outer residual norm^2 (mixed)
   double* nrm;    // M-norms (normalisation)
+  double* bb_next;  // ||M u||^2 of the state the last norm pass scaled
   int* act;       // column active in the current (inner) CG
   int* act_o;     // column active in the outer refinement (mixed)
   int* iters;     // CG iterations taken (cumulative)
@@ -108,6 +109,11 @@ void init_outer(const StepArgs& a, const double* u, const float* g, double* x0, 
 void red_outer_init(const StepArgs& a, hipStream_t s);
 void inner_init(const StepArgs& a, int o, const double* r64, float* d, float* r, float* p,
                 hipStream_t s);
+// refinement start and first inner start from the norm pass's A v (in w_x0,
+// overwritten by x0 = u + g) and ||M u||^2; replaces init_outer,
+// red_outer_init, inner_init and red_inner_init of sweep 0
+void refine_start(const StepArgs& a, const double* u, double* w_x0, const float* g, double* r64,
+                  float* d, float* r, float* p, hipStream_t s);
 void red_inner_init(const StepArgs& a, int o, hipStream_t s);
 // u += d, r64 -= K d on the columns still refining; dacc (nullable) += d
 void outer_update(const StepArgs& a, int o, double* u, double* r64, const float* d, float* dacc,
@@ -118,7 +124,8 @@ void extrap(const StepArgs& a, const ExtrapArgs& e, float* y, hipStream_t s);
 void red_outer(const StepArgs& a, int o, hipStream_t s);
 // node step and normalisation
 void nodal(const StepArgs& a, const double* u, double* out, hipStream_t s);
-void norm_dot(const StepArgs& a, const double* v, hipStream_t s);
+// v.Mv, v.Av, ||Mv||^2 partials; w (nullable) receives A v
+void norm_dot(const StepArgs& a, const double* v, double* w, hipStream_t s);
 // M-norms of the live columns of the vector norm_dot saw; lam (nullable)
 // receives their Rayleigh quotients
 void red_norm(const StepArgs& a, double* lam, hipStream_t s);

@@ -554,6 +554,97 @@ __global__ void k_red_outer_init(StepArgs a) {
   count_active(act, a.oring + 0);
 }
 
+// Refinement start and first inner start in one pass, from the previous
+// step's norm pass: the state u = v / n is already scaled and w holds A v, so
+// A u = w / n needs no float64 gather.  With the start guess g:
+//   x0 = u + g (written over w), r64 = b - K x0 = -tau A u - K64 g,
+//   r32 = float(r64), p = D r32, d = 0,
+// partials ||r64||^2, r32.p, ||r32||^2.  Columns that are not live get x0 = u
+// and zeros.  Tiling tm (the float32 gather of g).
+__global__ __launch_bounds__(kBlock) void k_refine_start(StepArgs a, const double* __restrict__ u,
+                                                         double* w_x0,
+                                                         const float* __restrict__ gd,
+                                                         double* __restrict__ r64,
+                                                         float* __restrict__ d,
+                                                         float* __restrict__ r,
+                                                         float* __restrict__ p) {
+  const Tile& t = a.tm;
+  for (int ct = 0; ct < t.nct; ++ct) {
+  const int g = ct * t.tg + threadIdx.x % t.tg;
+  double s[3][4] = {};
+  if (g < t.G) {
+    const int c0 = 4 * g;
+    bool lv[4];
+    double inv[4];
+    for (int j = 0; j < 4; ++j) {
+      lv[j] = a.ct.live[c0 + j] != 0;
+      inv[j] = 1.0 / a.cg.nrm[c0 + j];
+    }
+    for_rows(t, [&](int row) {
+      double kg[4] = {};
+      V4<float> go = {};
+      for_neighbors(a, row, c0, gd, [&](int k, const V4<float>& x, size_t o) {
+        const double v = ldm(a.K64 + o);
+        if (k == 0) go = x;
+        for (int j = 0; j < 4; ++j) kg[j] = fma(v, double(x.v[j]), kg[j]);
+      });
+      const size_t o = size_t(row) * t.rp + c0;
+      const V4<double> uv = ld4(u + o), wv = ld4(w_x0 + o);
+      const float di = a.dinv32[row];
+      V4<double> xv, rv;
+      V4<float> r32, pv, dv = {};
+      for (int j = 0; j < 4; ++j) {
+        if (lv[j]) {
+          rv.v[j] = -a.tau * (wv.v[j] * inv[j]) - kg[j];
+          xv.v[j] = uv.v[j] + double(go.v[j]);
+        } else {
+          rv.v[j] = 0.0;
+          xv.v[j] = uv.v[j];
+        }
+        r32.v[j] = float(rv.v[j]);
+        pv.v[j] = di * r32.v[j];
+        s[0][j] += rv.v[j] * rv.v[j];
+        s[1][j] += double(r32.v[j]) * double(pv.v[j]);
+        s[2][j] += double(r32.v[j]) * double(r32.v[j]);
+      }
+      st4(w_x0 + o, xv);
+      st4(r64 + o, rv);
+      st4(r + o, r32);
+      st4(p + o, pv);
+      st4(d + o, dv);
+    });
+  }
+  block_store<3>(t, s, a.part, blockIdx.x, ct);
+  }
+}
+
+// Reductions of the fused start: the refinement's activity (with ||b||^2
+// from the norm pass) and the first inner solve's scalars and tolerance.
+__global__ void k_red_refine_start(StepArgs a) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.oring[1] = 0;
+  const int c = red_col();
+  const Tile& t = a.tm;
+  const double rr = red_sum(a.part + part_off(t, 0), t.nchunk, t.rp, c);
+  const double rz = red_sum(a.part + part_off(t, 1), t.nchunk, t.rp, c);
+  const double r2 = red_sum(a.part + part_off(t, 2), t.nchunk, t.rp, c);
+  int act_o = 0, act = 0;
+  if (red_lead() && c < t.rp) {
+    const double bb = a.cg.bb_next[c];
+    a.cg.bb[c] = bb;
+    a.cg.rr_o[c] = rr;
+    act_o = (a.ct.live[c] && rr > a.rtol2 * bb) ? 1 : 0;
+    a.cg.act_o[c] = act_o;
+    a.cg.rz[c] = rz;
+    a.cg.tol2[c] = fmax(a.inner_rtol2 * r2, 0.0625 * a.rtol2 * bb);
+    act = (act_o && r2 > 0.0) ? 1 : 0;
+    a.cg.act[c] = act;
+    a.cg.alpha[c] = 0.0;
+    a.cg.beta[c] = 0.0;
+  }
+  count_active(act_o, a.oring + 0);
+  count_active(act, a.ring + 0);
+}
+
 // Start of an inner float32 solve K d = r64: d = 0, r = float(r64), p = D r.
 __global__ __launch_bounds__(kBlock) void k_inner_init(StepArgs a, int oslot,
                                                        const double* __restrict__ r64,
@@ -728,11 +819,14 @@ __global__ __launch_bounds__(kBlock) void k_nodal(StepArgs a, const double* __re
 }
 
 // ---------------------------------------------------------- normalisation --
-__global__ __launch_bounds__(kBlock) void k_norm_dot(StepArgs a, const double* __restrict__ v) {
+// Norm pass: per column v.Mv, v.Av and ||M v||^2 (partials); w (nullable)
+// receives A v, which the next step's refinement start reuses.
+__global__ __launch_bounds__(kBlock) void k_norm_dot(StepArgs a, const double* __restrict__ v,
+                                                     double* __restrict__ w) {
   const Tile& t = a.t64;
   for (int ct = 0; ct < t.nct; ++ct) {
   const int g = ct * t.tg + threadIdx.x % t.tg;
-  double s[2][4] = {};
+  double s[3][4] = {};
   if (g < t.G) {
     const int c0 = 4 * g;
     int lv[4], any = 0;
@@ -742,40 +836,45 @@ __global__ __launch_bounds__(kBlock) void k_norm_dot(StepArgs a, const double* _
     }
     if (any) {
       for_rows(t, [&](int row) {
-        double mv[4] = {}, av[4] = {};
-        V4<double> vd = {};
+        double mv[4] = {};
+        V4<double> av = {}, vd = {};
         for_neighbors(a, row, c0, v, [&](int k, const V4<double>& x, size_t o) {
-          const double w = ldm(a.M64 + o), z = ldm(a.A64 + o);
+          const double wm = ldm(a.M64 + o), z = ldm(a.A64 + o);
           if (k == 0) vd = x;
           for (int j = 0; j < 4; ++j) {
-            mv[j] = fma(w, x.v[j], mv[j]);
-            av[j] = fma(z, x.v[j], av[j]);
+            mv[j] = fma(wm, x.v[j], mv[j]);
+            av.v[j] = fma(z, x.v[j], av.v[j]);
           }
         });
         for (int j = 0; j < 4; ++j)
           if (lv[j]) {
             s[0][j] += vd.v[j] * mv[j];
-            s[1][j] += vd.v[j] * av[j];
+            s[1][j] += vd.v[j] * av.v[j];
+            s[2][j] += mv[j] * mv[j];
           }
+        if (w) st4(w + size_t(row) * t.rp + c0, av);
       });
     }
   }
-  block_store<2>(t, s, a.part, blockIdx.x, ct);
+  block_store<3>(t, s, a.part, blockIdx.x, ct);
   }
 }
 
-// M-norms of the live columns, and their Rayleigh quotients v.Av / v.Mv
+// M-norms of the live columns, their Rayleigh quotients v.Av / v.Mv
 // (unchanged by the scaling that follows, so they are the eigenvalue
-// estimates of the normalised state).
+// estimates of the normalised state) and ||M u||^2 of the scaled state.
 __global__ void k_red_norm(StepArgs a, double* __restrict__ lam) {
   const int c = red_col();
   const Tile& t = a.t64;
   const bool lv = c < t.rp && a.ct.live[c];
   const double s = red_sum(a.part, lv ? t.nchunk : 0, t.rp, c);
   const double sa = red_sum(a.part + part_off(t, 1), lv ? t.nchunk : 0, t.rp, c);
+  const double sm = red_sum(a.part + part_off(t, 2), lv ? t.nchunk : 0, t.rp, c);
   if (!red_lead() || c >= t.rp) return;
   a.cg.nrm[c] = lv ? sqrt(s) : 1.0;
   if (lv && lam) lam[c] = sa / s;
+  // ||M u||^2 of the scaled state u = v / ||v||_M (the next solve's ||b||^2)
+  if (lv) a.cg.bb_next[c] = sm / s;
 }
 
 __global__ __launch_bounds__(kBlock) void k_scale(StepArgs a, const double* __restrict__ v,
@@ -1245,6 +1344,14 @@ void red_outer_init(const StepArgs& a, hipStream_t s) {
   SP_LAUNCH_CHECK();
 }
 
+void refine_start(const StepArgs& a, const double* u, double* w_x0, const float* g, double* r64,
+                  float* d, float* r, float* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_refine_start, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, u, w_x0, g, r64, d, r,
+                     p);
+  hipLaunchKernelGGL(k_red_refine_start, dim3(colblocks(a.t)), dim3(kBlock), 0, s, a);
+  SP_LAUNCH_CHECK();
+}
+
 void inner_init(const StepArgs& a, int o, const double* r64, float* d, float* r, float* p,
                 hipStream_t s) {
   hipLaunchKernelGGL(k_inner_init, dim3(a.t.nblk), dim3(kBlock), 0, s, a, o % kRing, r64, d, r, p);
@@ -1280,8 +1387,8 @@ void nodal(const StepArgs& a, const double* u, double* out, hipStream_t s) {
   SP_LAUNCH_CHECK();
 }
 
-void norm_dot(const StepArgs& a, const double* v, hipStream_t s) {
-  hipLaunchKernelGGL(k_norm_dot, dim3(a.t64.nblk), dim3(kBlock), 0, s, a, v);
+void norm_dot(const StepArgs& a, const double* v, double* w, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm_dot, dim3(a.t64.nblk), dim3(kBlock), 0, s, a, v, w);
   SP_LAUNCH_CHECK();
 }
 
