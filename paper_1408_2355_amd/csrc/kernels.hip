@@ -1037,7 +1037,11 @@ __global__ __launch_bounds__(kBlock) void k_energy_seps(StepArgs a, SepsPlan sp,
                                                         const double* __restrict__ tarea,
                                                         const double* __restrict__ u,
                                                         double* __restrict__ part_s) {
-  __shared__ double sh[kBlock * 3 * kSepsPad];
+  constexpr int kHalves = kSepsPiece / 2;        // 16-byte items per staged row
+  __shared__ double sh[kBlock * 3 * kSepsPad];   // staged rows (triangle, corner, restart)
+  __shared__ long long s_off[kBlock * 3];        // their source offsets (-1: no triangle)
+  __shared__ int s_len[kBlock * 3];              // and their restart's m
+  __shared__ int s_lo[64], s_m[64];              // the tile's restarts
   __shared__ double red[kBlock];
   const int rp = a.t.rp;
   const int tid = threadIdx.x;
@@ -1047,63 +1051,63 @@ __global__ __launch_bounds__(kBlock) void k_energy_seps(StepArgs a, SepsPlan sp,
     const int TB = kBlock / nr;
     const int tb = tid / nr, rr = tid % nr;
     const bool worker = tb < TB;
-    int lo = 0, m = 0, mmax = 0;
-    for (int q = 0; q < nr; ++q) mmax = max(mmax, a.ct.res_len[r0 + q]);
-    if (worker) {
-      lo = a.ct.res_lo[r0 + rr];
-      m = a.ct.res_len[r0 + rr];
+    const int nrow = TB * 3 * nr;
+    if (tid < nr) {
+      s_lo[tid] = a.ct.res_lo[r0 + tid];
+      s_m[tid] = a.ct.res_len[r0 + tid];
     }
+    __syncthreads();
+    int mmax = 0;
+    for (int q = 0; q < nr; ++q) mmax = max(mmax, s_m[q]);
+    const int lo = worker ? s_lo[rr] : 0, m = worker ? s_m[rr] : 0;
     double acc = 0.0;
     for (int chunk = cb; chunk < ce; chunk += stride) {
       const int t_beg = chunk * sp.tchunk, t_end = min(t_beg + sp.tchunk, sp.nt);
       for (int t0 = t_beg; t0 < t_end; t0 += TB) {
+        // row (bq * 3 + k) * nr + q: corner k of triangle t0 + bq, restart q
+        for (int row3 = tid; row3 < nrow; row3 += kBlock) {
+          const int q = row3 % nr, bk = row3 / nr;
+          const int bq = bk / 3, k = bk - 3 * bq;
+          const int tt = t0 + bq;
+          s_off[row3] = tt < t_end ? (long long)tri[3 * tt + k] * rp + s_lo[q] : -1;
+          s_len[row3] = s_m[q];
+        }
         const int t = t0 + tb;
         QuarticPairs qp;
         for (int i0 = 0; i0 < mmax; i0 += kSepsPiece) {
-          // stage: item (triangle bq, corner k, restart q, half-piece h) of
-          // 2 doubles; TB * 3 * nr * (kSepsPiece / 2) items
-          const int nitem = TB * 3 * nr * (kSepsPiece / 2);
-          for (int it = tid; it < nitem; it += kBlock) {
-            const int h = it % (kSepsPiece / 2);
-            const int row3 = it / (kSepsPiece / 2);  // (bq * 3 + k) * nr + q
-            const int q = row3 % nr, bk = row3 / nr;
-            const int bq = bk / 3, k = bk - 3 * bq;
-            const int tt = t0 + bq;
-            const int ql = a.ct.res_lo[r0 + q], qm = a.ct.res_len[r0 + q];
-            const int i = i0 + 2 * h;
-            double2 v = make_double2(0.0, 0.0);
-            if (tt < t_end) {
-              const double* src = u + size_t(tri[3 * tt + k]) * rp + ql + i;
-              if (i + 1 < qm) {
-                v.x = src[0];
-                v.y = src[1];
-              } else if (i < qm) {
-                v.x = src[0];
-              }
+          __syncthreads();
+          for (int it = tid; it < nrow * kHalves; it += kBlock) {
+            const int row3 = it / kHalves, h = it % kHalves;
+            const long long off = s_off[row3];
+            const int i = i0 + 2 * h, len = s_len[row3];
+            double vx = 0.0, vy = 0.0;
+            if (off >= 0) {
+              if (i < len) vx = u[off + i];
+              if (i + 1 < len) vy = u[off + i + 1];
             }
-            double* dst = sh + size_t(row3) * kSepsPad + 2 * h;
-            dst[0] = v.x;
-            dst[1] = v.y;
+            double* dst = sh + row3 * kSepsPad + 2 * h;
+            dst[0] = vx;
+            dst[1] = vy;
           }
           __syncthreads();
           if (worker && t < t_end) {
-            const double* b0 = sh + size_t((tb * 3 + 0) * nr + rr) * kSepsPad;
-            const double* b1 = sh + size_t((tb * 3 + 1) * nr + rr) * kSepsPad;
-            const double* b2 = sh + size_t((tb * 3 + 2) * nr + rr) * kSepsPad;
+            const double* b0 = sh + ((tb * 3 + 0) * nr + rr) * kSepsPad;
+            const double* b1 = sh + ((tb * 3 + 1) * nr + rr) * kSepsPad;
+            const double* b2 = sh + ((tb * 3 + 2) * nr + rr) * kSepsPad;
             const int n = min(kSepsPiece, m - i0);
             for (int i = 0; i < n; ++i) qp.add(b0[i], b1[i], b2[i]);
           }
-          __syncthreads();
         }
         if (worker && t < t_end && m > 0) acc += qp.acc * tarea[t] * (1.0 / 180.0);
+        __syncthreads();
       }
     }
     red[tid] = acc;
     __syncthreads();
     if (tid < nr) {
-      double s = 0.0;
-      for (int bq = 0; bq < TB; ++bq) s += red[bq * nr + tid];
-      part_s[size_t(blockIdx.x) * sp.nres_p + r0 + tid] = s;
+      double sum = 0.0;
+      for (int bq = 0; bq < TB; ++bq) sum += red[bq * nr + tid];
+      part_s[size_t(blockIdx.x) * sp.nres_p + r0 + tid] = sum;
     }
     __syncthreads();
   });
