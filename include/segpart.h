@@ -114,7 +114,11 @@ typedef struct {
   int64_t max_steps;    /* cap for n_steps == 0                                      */
   int64_t energy_every; /* energy cadence in steps (paper: M_tau with M_tau tau = 0.1);
                            0 = energy only at the end (not allowed with n_steps == 0) */
-  int32_t precision;    /* SP_FP64 or SP_MIXED                                       */
+  int32_t precision;    /* SP_FP64 or SP_MIXED.  Small batches (vertices x columns
+                           padded to 4 <= 16384, <= 256 columns, <= 64 restarts) run
+                           whole steps in one resident workgroup with float64 CG
+                           whatever this says (at that size it costs nothing more);
+                           the environment variable SEGPART_SMALL=0 turns that off */
   double cg_rtol;       /* per column stop when ||b - (M+tau A) x||_2 <= cg_rtol ||M u||_2 */
   int32_t cg_max_iter;  /* cap on CG iterations per solve (per inner solve in SP_MIXED) */
   double inner_rtol;    /* SP_MIXED: relative residual reduction of each float32 solve */

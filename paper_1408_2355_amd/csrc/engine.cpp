@@ -94,10 +94,17 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     u_.alloc(nv);
     heat_x_ = u_.p;
     r64_.alloc(nv);
-    if (prm_.precision == SP_FP64) {
+    // small batches run whole steps in one workgroup (float64 CG) unless
+    // SEGPART_SMALL=0
+    const char* sm_env = std::getenv("SEGPART_SMALL");
+    small_ = nv <= size_t(kSmallMaxValues) && rp_ <= kSmallMaxCols &&
+             nres_p_ <= kSmallMaxRestarts && !(sm_env && std::strcmp(sm_env, "0") == 0);
+    if (prm_.precision == SP_FP64 || small_) {
       p64_.alloc(nv);
       q64_.alloc(nv);
-    } else {
+    }
+    if (small_) small_hist_.alloc(size_t(kSmallChunk) * nres_p_);
+    if (prm_.precision != SP_FP64) {
       d32_.alloc(nv);
       r32_.alloc(nv);
       p32_.alloc(nv);
@@ -668,8 +675,59 @@ void Solver::energy_to_host(double* lam, double* seps, double* E) {
   SP_HIP(hipStreamSynchronize(s_));
 }
 
+// Steps of a small batch: chunks of up to kSmallChunk steps, one launch each
+// (the float64 form whatever the precision setting: at this size it costs
+// nothing more); energies at the cadence come back from the device history.
+void Solver::step_small(int64_t k) {
+  const int nres = int(spec_.m.size());
+  while (k > 0) {
+    const int chunk = int(std::min<int64_t>(k, kSmallChunk));
+    SmallArgs sa;
+    sa.nsteps = chunk;
+    sa.every = int(prm_.energy_every);
+    sa.step0 = steps_done_;
+    sa.max_iter = prm_.cg_max_iter;
+    sa.u = u_.p;
+    sa.r = r64_.p;
+    sa.p = p64_.p;
+    sa.q = q64_.p;
+    sa.tri = mesh_->tri.p;
+    sa.tarea = mesh_->tarea.p;
+    sa.nt = int(mesh_->nt);
+    sa.lam = lam_.p;
+    sa.seps = seps_.p;
+    sa.energy = energy_.p;
+    sa.hist = small_hist_.p;
+    k::small_steps(args_, sa, s_);
+    if (record_history && prm_.energy_every > 0 && nres > 0) {
+      std::vector<int> due;
+      for (int i = 0; i < chunk; ++i)
+        if ((steps_done_ + i + 1) % prm_.energy_every == 0) due.push_back(i);
+      if (!due.empty()) {
+        std::vector<double> h(size_t(chunk) * nres_p_);
+        SP_HIP(hipMemcpyAsync(h.data(), small_hist_.p, h.size() * sizeof(double),
+                              hipMemcpyDeviceToHost, s_));
+        SP_HIP(hipStreamSynchronize(s_));
+        for (int i : due)
+          for (int r = 0; r < nres; ++r)
+            if (h_res_live_[r]) hist_[r].push_back({steps_done_ + i + 1, h[size_t(i) * nres_p_ + r]});
+      }
+    }
+    steps_done_ += chunk;
+    k -= chunk;
+  }
+  lam_fresh_ = all_live_;
+  n_prev_ = 0;
+  aw_fresh_ = false;
+  heat_x_ = u_.p;
+}
+
 void Solver::step(int64_t k) {
   SP_REQUIRE(k >= 0, SP_EINVAL, "step count must be >= 0");
+  if (small_) {
+    step_small(k);
+    return;
+  }
   const int nres = int(spec_.m.size());
   std::vector<double> E(nres);
   for (int64_t i = 0; i < k; ++i) {

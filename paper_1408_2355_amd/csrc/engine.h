@@ -112,6 +112,7 @@ class Solver {
 
  private:
   void heat();  // heat solve; its result is left in heat_x_
+  void step_small(int64_t k);
   void heat_fp64();
   void heat_mixed();
   void node_to_r();
@@ -144,6 +145,9 @@ class Solver {
   int n_prev_ = 0;  // increments available (0 .. prm_.extrapolate)
   DevBuf<double> xg_;          // iterate of a solve started from u + g (u stays b's source)
   double* heat_x_ = nullptr;   // where the last heat solve left its result (u_ or xg_)
+  bool small_ = false;         // whole steps in one workgroup (small batches)
+  static constexpr int kSmallChunk = 128;  // steps per launch of the small path
+  DevBuf<double> small_hist_;  // [kSmallChunk][nres_p] energies at the cadence
   bool aw_fresh_ = false;      // xg_ holds A v of the norm pass that produced u (and
                                // cg.bb_next its ||M u||^2): the next solve can start
                                // without gathering u

@@ -73,6 +73,30 @@ struct ExtrapArgs {
   int n = 0;
 };
 
+// Batches with n * rp <= kSmallMaxValues, rp <= kSmallMaxCols and at most
+// kSmallMaxRestarts restarts can run whole time steps in one resident
+// workgroup (small_steps).
+constexpr int kSmallMaxValues = 16384;
+constexpr int kSmallMaxCols = 256;
+constexpr int kSmallMaxRestarts = 64;
+struct SmallArgs {
+  int nsteps = 0;
+  int every = 0;        // energy cadence (0: none)
+  long long step0 = 0;  // steps taken before this launch
+  int max_iter = 0;     // CG iteration cap per solve
+  double* u = nullptr;  // state (also the CG iterate)
+  double* r = nullptr;  // residual, then the node-step output
+  double* p = nullptr;
+  double* q = nullptr;
+  const int* tri = nullptr;
+  const double* tarea = nullptr;
+  int nt = 0;
+  double* lam = nullptr;     // per column
+  double* seps = nullptr;    // per restart
+  double* energy = nullptr;  // per restart
+  double* hist = nullptr;    // [nsteps][nres_p] energies at the cadence (nullable)
+};
+
 // Triangle-chunk x restart-tile plan of the S_eps element kernel.
 struct SepsPlan {
   const int4* tiles = nullptr;  // (r0, r1, c0, c1): restarts [r0, r1) use columns [c0, c1)
@@ -137,6 +161,8 @@ void energy_seps(const StepArgs& a, const SepsPlan& sp, const int32_t* tri, cons
 void red_energy(const StepArgs& a, const SepsPlan& sp, const double* part_s, bool with_lambda,
                 double* lam,
                 double* seps, double* energy, hipStream_t s);
+// nsteps whole time steps (float64 CG) of a small batch in one workgroup
+void small_steps(const StepArgs& a, const SmallArgs& sa, hipStream_t s);
 // labels and layout changes
 void labels(const StepArgs& a, const double* u, const int32_t* perm, int32_t* lab,
             int32_t* lab_am, hipStream_t s);

@@ -1181,6 +1181,320 @@ __global__ void k_red_seps(StepArgs a, SepsPlan sp, const double* __restrict__ p
   energy[r] = e;
 }
 
+// ------------------------------------------------ small batches, one launch --
+// Whole time steps of a small batch (n * rp <= kSmallMaxValues) in one
+// workgroup that stays resident for all the steps of the launch: the float64
+// CG from x0 = u (as the plain float64 form), the node step, the norm pass,
+// the scaling and, at the energy cadence, Rayleigh quotients (from the norm
+// pass), S_eps and E.  Phases are separated by workgroup barriers instead of
+// kernel launches, and there is no host round trip per CG iteration.
+//
+// Thread mapping: column group g = tid % gp (gp = G rounded up to a power of
+// two; lanes with g >= G idle) and row lane tid / gp, rows row-lane, + RL, ...
+// Per-column sums: each thread's 4 partials, then a tree over tid with
+// strides that are multiples of gp (fixed order, so results do not depend on
+// timing).
+constexpr int kSmallBlock = 512;
+
+struct SmallScal {
+  double rz[kSmallMaxCols], tol2[kSmallMaxCols], alpha[kSmallMaxCols], beta[kSmallMaxCols];
+  double nrm[kSmallMaxCols];
+  int act[kSmallMaxCols];
+  int nact;
+};
+
+// Sum v (4 columns per thread) over the threads of each column group; the
+// total of column c is left in red[c].  Every thread must call it.
+__device__ __forceinline__ void small_sum(double* red, const double (&v)[4], int gp) {
+  const int tid = threadIdx.x;
+  for (int j = 0; j < 4; ++j) red[tid * 4 + j] = v[j];
+  for (int st = kSmallBlock / 2; st >= gp; st >>= 1) {
+    __syncthreads();
+    if (tid < st)
+      for (int j = 0; j < 4; ++j) red[tid * 4 + j] += red[(tid + st) * 4 + j];
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kSmallBlock) void k_small_steps(StepArgs a, SmallArgs sa) {
+  __shared__ double red[kSmallBlock * 4];
+  __shared__ SmallScal cs;
+  const int tid = threadIdx.x;
+  const int n = a.t.n, rp = a.t.rp, G = rp / 4, W = a.W;
+  int gp = 1;
+  while (gp < G) gp <<= 1;
+  const int g = tid % gp, RL = kSmallBlock / gp, rl = tid / gp;
+  const bool valid = g < G;
+  const int c0 = 4 * g;
+  double* u = sa.u;
+  double* r = sa.r;
+  double* p = sa.p;
+  double* q = sa.q;
+  int lv[4] = {0, 0, 0, 0}, seg_lo[4] = {0, 0, 0, 0}, seg_len[4] = {0, 0, 0, 0};
+  double coef[4] = {0, 0, 0, 0};
+  int any_live = 0;
+  if (valid)
+    for (int j = 0; j < 4; ++j) {
+      lv[j] = a.ct.live[c0 + j];
+      seg_lo[j] = a.ct.seg_lo[c0 + j];
+      seg_len[j] = a.ct.seg_len[c0 + j];
+      coef[j] = a.ct.coef[c0 + j];
+      any_live |= lv[j];
+    }
+  // gather helper: acc_k += sum over the row's slots of mat[slot] * x[col]
+  auto gather = [&](int row, const double* x, auto&& f) {
+    for (int k = 0; k < W; ++k) {
+      const size_t o = size_t(k) * n + row;
+      const int cidx = ldm(a.cols + o);
+      f(k, o, ld4(x + size_t(cidx) * rp + c0));
+    }
+  };
+
+  for (int step = 0; step < sa.nsteps; ++step) {
+    // ---- heat: CG on (M + tau A) x = M u from x = u, r = -tau A u
+    {
+      double sb[4] = {}, sz[4] = {}, sr[4] = {};
+      if (valid && any_live)
+        for (int row = rl; row < n; row += RL) {
+          double au[4] = {}, mu[4] = {};
+          gather(row, u, [&](int, size_t o, const V4<double>& x) {
+            const double va = ldm(a.A64 + o), vm = ldm(a.M64 + o);
+            for (int j = 0; j < 4; ++j) {
+              au[j] = fma(va, x.v[j], au[j]);
+              mu[j] = fma(vm, x.v[j], mu[j]);
+            }
+          });
+          const double di = a.dinv64[row];
+          V4<double> rv, pv;
+          for (int j = 0; j < 4; ++j) {
+            rv.v[j] = lv[j] ? -a.tau * au[j] : 0.0;
+            pv.v[j] = di * rv.v[j];
+            if (lv[j]) sb[j] += mu[j] * mu[j];
+            sz[j] += rv.v[j] * pv.v[j];
+            sr[j] += rv.v[j] * rv.v[j];
+          }
+          st4(r + size_t(row) * rp + c0, rv);
+          st4(p + size_t(row) * rp + c0, pv);
+        }
+      double bb = 0, rz = 0, rr = 0;
+      small_sum(red, sb, gp);
+      if (tid < rp) bb = red[tid];
+      __syncthreads();
+      small_sum(red, sz, gp);
+      if (tid < rp) rz = red[tid];
+      __syncthreads();
+      small_sum(red, sr, gp);
+      if (tid < rp) rr = red[tid];
+      if (tid == 0) cs.nact = 0;
+      __syncthreads();
+      if (tid < rp) {
+        const int act = (a.ct.live[tid] && rr > a.rtol2 * bb) ? 1 : 0;
+        a.cg.bb[tid] = bb;
+        cs.rz[tid] = rz;
+        cs.tol2[tid] = a.rtol2 * bb;
+        cs.act[tid] = act;
+        cs.alpha[tid] = 0.0;
+        cs.beta[tid] = 0.0;
+        if (act) atomicAdd(&cs.nact, 1);
+      }
+      __syncthreads();
+    }
+    for (int it = 0; it < sa.max_iter && cs.nact > 0; ++it) {
+      if (tid == 0) {
+        a.stat[0] += 1;
+        a.stat[3] += cs.nact;
+      }
+      int act[4] = {0, 0, 0, 0}, any = 0;
+      if (valid)
+        for (int j = 0; j < 4; ++j) {
+          act[j] = cs.act[c0 + j];
+          any |= act[j];
+        }
+      // q = K p, p.q
+      double spq[4] = {};
+      if (any)
+        for (int row = rl; row < n; row += RL) {
+          V4<double> acc = {}, pd = {};
+          gather(row, p, [&](int k, size_t o, const V4<double>& x) {
+            const double v = ldm(a.K64 + o);
+            if (k == 0) pd = x;
+            for (int j = 0; j < 4; ++j) acc.v[j] = fma(v, x.v[j], acc.v[j]);
+          });
+          st4(q + size_t(row) * rp + c0, acc);
+          for (int j = 0; j < 4; ++j)
+            if (act[j]) spq[j] += pd.v[j] * acc.v[j];
+        }
+      small_sum(red, spq, gp);
+      if (tid < rp) cs.alpha[tid] = (cs.act[tid] && red[tid] > 0.0) ? cs.rz[tid] / red[tid] : 0.0;
+      __syncthreads();
+      // x += alpha p, r -= alpha q, z = D r; r.z and r.r
+      double al[4] = {0, 0, 0, 0};
+      for (int j = 0; j < 4; ++j) al[j] = valid ? cs.alpha[c0 + j] : 0.0;
+      double szn[4] = {}, srn[4] = {};
+      if (any)
+        for (int row = rl; row < n; row += RL) {
+          const size_t o = size_t(row) * rp + c0;
+          V4<double> xv = ld4(u + o), rv = ld4(r + o);
+          const V4<double> pv = ld4(p + o), qv = ld4(q + o);
+          const double di = a.dinv64[row];
+          for (int j = 0; j < 4; ++j)
+            if (act[j]) {
+              xv.v[j] = fma(al[j], pv.v[j], xv.v[j]);
+              rv.v[j] = fma(-al[j], qv.v[j], rv.v[j]);
+              szn[j] += rv.v[j] * (di * rv.v[j]);
+              srn[j] += rv.v[j] * rv.v[j];
+            }
+          st4(u + o, xv);
+          st4(r + o, rv);
+        }
+      double rzn = 0, rrn = 0;
+      small_sum(red, szn, gp);
+      if (tid < rp) rzn = red[tid];
+      __syncthreads();
+      small_sum(red, srn, gp);
+      if (tid < rp) rrn = red[tid];
+      if (tid == 0) cs.nact = 0;
+      __syncthreads();
+      if (tid < rp && cs.act[tid]) {
+        a.cg.iters[tid] += 1;
+        if (rrn <= cs.tol2[tid] || !(rrn == rrn)) {
+          cs.act[tid] = 0;
+          cs.beta[tid] = 0.0;
+        } else {
+          cs.beta[tid] = rzn / cs.rz[tid];
+          cs.rz[tid] = rzn;
+          atomicAdd(&cs.nact, 1);
+        }
+      }
+      __syncthreads();
+      // p = D r + beta p on the columns still iterating
+      int still[4] = {0, 0, 0, 0}, anys = 0;
+      double be[4] = {0, 0, 0, 0};
+      if (valid)
+        for (int j = 0; j < 4; ++j) {
+          still[j] = cs.act[c0 + j];
+          be[j] = cs.beta[c0 + j];
+          anys |= still[j];
+        }
+      if (anys)
+        for (int row = rl; row < n; row += RL) {
+          const size_t o = size_t(row) * rp + c0;
+          V4<double> pv = ld4(p + o);
+          const V4<double> rv = ld4(r + o);
+          const double di = a.dinv64[row];
+          for (int j = 0; j < 4; ++j)
+            if (still[j]) pv.v[j] = fma(be[j], pv.v[j], di * rv.v[j]);
+          st4(p + o, pv);
+        }
+      __syncthreads();
+    }
+    if (tid == 0 && cs.nact > 0) a.stat[2] = 1;  // iteration cap hit
+    __syncthreads();
+    // ---- node step (into r): u^_i = u~_i exp(-coef (S - u~_i^2))
+    if (valid && any_live)
+      for (int row = rl; row < n; row += RL) {
+        const double* ur = u + size_t(row) * rp;
+        V4<double> uv = ld4(ur + c0), ov = uv;
+        double S = 0.0;
+        int cur = -1;
+        for (int j = 0; j < 4; ++j) {
+          if (!lv[j]) continue;
+          if (seg_lo[j] != cur) {
+            cur = seg_lo[j];
+            S = 0.0;
+            for (int i = 0; i < seg_len[j]; ++i) {
+              const double w = ur[seg_lo[j] + i];
+              S = fma(w, w, S);
+            }
+          }
+          const double x = uv.v[j];
+          ov.v[j] = x * exp(-coef[j] * (S - x * x));
+        }
+        st4(r + size_t(row) * rp + c0, ov);
+      }
+    __syncthreads();
+    // ---- norm pass: v.Mv, v.Av of v = u^ (gathered from r)
+    {
+      double sm[4] = {}, sa2[4] = {};
+      if (valid && any_live)
+        for (int row = rl; row < n; row += RL) {
+          double mv[4] = {}, av[4] = {};
+          V4<double> vd = {};
+          gather(row, r, [&](int k, size_t o, const V4<double>& x) {
+            const double wm = ldm(a.M64 + o), z = ldm(a.A64 + o);
+            if (k == 0) vd = x;
+            for (int j = 0; j < 4; ++j) {
+              mv[j] = fma(wm, x.v[j], mv[j]);
+              av[j] = fma(z, x.v[j], av[j]);
+            }
+          });
+          for (int j = 0; j < 4; ++j)
+            if (lv[j]) {
+              sm[j] += vd.v[j] * mv[j];
+              sa2[j] += vd.v[j] * av[j];
+            }
+        }
+      double vm = 0, va = 0;
+      small_sum(red, sm, gp);
+      if (tid < rp) vm = red[tid];
+      __syncthreads();
+      small_sum(red, sa2, gp);
+      if (tid < rp) va = red[tid];
+      if (tid < rp) {
+        const bool l = a.ct.live[tid] != 0;
+        cs.nrm[tid] = l ? sqrt(vm) : 1.0;
+        a.cg.nrm[tid] = cs.nrm[tid];
+        if (l) sa.lam[tid] = va / vm;
+      }
+      __syncthreads();
+    }
+    // ---- scale: u = u^ / ||u^||_M on the live columns
+    if (valid && any_live) {
+      double inv[4];
+      for (int j = 0; j < 4; ++j) inv[j] = 1.0 / cs.nrm[c0 + j];
+      for (int row = rl; row < n; row += RL) {
+        const size_t o = size_t(row) * rp + c0;
+        const V4<double> vv = ld4(r + o);
+        V4<double> uv = ld4(u + o);
+        for (int j = 0; j < 4; ++j)
+          if (lv[j]) uv.v[j] = vv.v[j] * inv[j];
+        st4(u + o, uv);
+      }
+    }
+    __syncthreads();
+    // ---- energy at the cadence: S_eps per restart, E = sum lambda + S_eps
+    if (sa.every > 0 && (sa.step0 + step + 1) % sa.every == 0) {
+      const int nres = a.ct.nres;
+      int np2 = 1;
+      while (np2 < nres) np2 <<= 1;
+      const int rr = tid % np2, tl = tid / np2, TL = kSmallBlock / np2;
+      double acc[4] = {0, 0, 0, 0};
+      if (rr < nres) {
+        const int lo = a.ct.res_lo[rr], m = a.ct.res_len[rr];
+        if (m > 0)
+          for (int t = tl; t < sa.nt; t += TL)
+            acc[0] += quartic_pairs(u + size_t(sa.tri[3 * t + 0]) * rp + lo,
+                                    u + size_t(sa.tri[3 * t + 1]) * rp + lo,
+                                    u + size_t(sa.tri[3 * t + 2]) * rp + lo, m) *
+                      sa.tarea[t] * (1.0 / 180.0);
+      }
+      // the tree needs strides that are multiples of np2: reuse small_sum
+      // with np2 as the group width (column slots 1..3 carry zeros)
+      small_sum(red, acc, np2);
+      if (tid < nres) {
+        const double se = red[tid * 4] * a.ct.res_ieps2[tid];
+        const int lo = a.ct.res_lo[tid], m = a.ct.res_len[tid];
+        double e = se;
+        for (int i = 0; i < m; ++i) e += sa.lam[lo + i];
+        sa.seps[tid] = se;
+        sa.energy[tid] = e;
+        if (sa.hist) sa.hist[size_t(step) * a.ct.nres_p + tid] = e;
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // ----------------------------------------------------------------- labels --
 // Equation (vi): v_i = u_i - sum_{j != i} u_j = 2 u_i - sum_j u_j; label =
 // argmax_i v_i if positive else -1; second labelling = argmax_i u_i (lowest
@@ -1457,6 +1771,11 @@ std::vector<int4> seps_tiles(const std::vector<int>& res_lo, const std::vector<i
     r = r1;
   }
   return tiles;
+}
+
+void small_steps(const StepArgs& a, const SmallArgs& sa, hipStream_t s) {
+  hipLaunchKernelGGL(k_small_steps, dim3(1), dim3(kSmallBlock), 0, s, a, sa);
+  SP_LAUNCH_CHECK();
 }
 
 void labels(const StepArgs& a, const double* u, const int32_t* perm, int32_t* lab, int32_t* lab_am,

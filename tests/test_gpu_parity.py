@@ -160,12 +160,23 @@ def _noise_floor(v, f, u0, ms, eps, tau, steps, ref):
                rel(alt["s_eps"], ref["s_eps"]))
 
 
-def test_config1_sphere_l3_fp64_end_to_end():
+@pytest.fixture(params=["one-workgroup", "multi-kernel"])
+def step_path(request, monkeypatch):
+    """Small batches run whole steps in one resident workgroup; SEGPART_SMALL=0
+    sends them through the multi-kernel path the large batches use."""
+    if request.param == "multi-kernel":
+        monkeypatch.setenv("SEGPART_SMALL", "0")
+    else:
+        monkeypatch.delenv("SEGPART_SMALL", raising=False)
+    return request.param
+
+
+def test_config1_sphere_l3_fp64_end_to_end(step_path):
     """Unit sphere level 3 (642 vertices), m = 3, eps = 0.1, tau = 1e-3, 200
     steps, float64, CG rtol 1e-12, u0 iid U[0,1) from seed 1003."""
     v, f = icosphere(3)
     u0 = uniform_u0(1003, 1, 3, v.shape[0])
-    say("config 1 fp64")
+    say("config 1 fp64", step_path)
     out, ref = _run_both(v, f, u0, [3], [0.1], 1e-3, 200, "fp64", 1e-12, 10)
     floor = _noise_floor(v, f, u0, [3], [0.1], 1e-3, 200, ref)
     bar = max(1e-10, 10 * floor)
@@ -181,15 +192,48 @@ def test_config1_sphere_l3_fp64_end_to_end():
     assert out["stats"]["converged"] == 1 and out["stats"]["steps_done"] == 200
 
 
-def test_config1_mixed_end_to_end():
+def test_config1_mixed_end_to_end(step_path):
     v, f = icosphere(3)
     u0 = uniform_u0(1003, 1, 3, v.shape[0])
-    say("config 1 mixed")
+    say("config 1 mixed", step_path)
     out, ref = _run_both(v, f, u0, [3], [0.1], 1e-3, 200, "mixed", 1e-12, 10)
     assert rel(out["lam"], ref["lam"]) < 1e-5
     assert rel(out["s_eps"], ref["s_eps"]) < 1e-5
     assert rel(out["energy"], ref["energy"]) < 1e-5
     assert rel(out["u"], ref["u"]) < 1e-5
+
+
+def test_small_path_history_and_stop_rule_match_multi_kernel(monkeypatch):
+    """The one-workgroup path and the multi-kernel path give the same flow,
+    energy history and stop step (float64)."""
+    v, f = icosphere(2)
+    u0 = uniform_u0(9, 2, 3, v.shape[0])
+    tau = 2e-2
+    mesh = sp.Mesh(v, f)
+    solved, hist = [], []
+    for env in (None, "0"):
+        if env is None:
+            monkeypatch.delenv("SEGPART_SMALL", raising=False)
+        else:
+            monkeypatch.setenv("SEGPART_SMALL", env)
+        say("small path" if env is None else "multi-kernel path")
+        prm = sp.params(tau, precision="fp64", n_steps=0, energy_every=20, stop_tol=1e-6,
+                        cg_rtol=1e-12, max_steps=5000)
+        rc, out = sp.solve(mesh, prm, [3, 3], [0.5, 0.4], u0)
+        solved.append(out)
+        prm = sp.params(tau, precision="fp64", n_steps=1, energy_every=5, cg_rtol=1e-12)
+        st = sp.State(mesh, prm, [3, 3], [0.5, 0.4], u0)
+        assert st.step(300) == sp.SP_OK
+        hist.append([st.history(r) for r in range(2)])
+        st.close()
+    a, b = solved
+    assert a["stats"]["steps_done"] == b["stats"]["steps_done"]
+    assert rel(a["u"], b["u"]) < 1e-11
+    assert rel(a["energy"], b["energy"]) < 1e-11
+    for (ka, ea), (kb, eb) in zip(hist[0], hist[1]):
+        np.testing.assert_array_equal(ka, kb)
+        assert len(ka) == 60
+        assert rel(ea, eb) < 1e-11
 
 
 def test_extrapolated_start_gives_the_same_flow():
