@@ -1191,9 +1191,8 @@ __global__ void k_red_seps(StepArgs a, SepsPlan sp, const double* __restrict__ p
 //
 // Thread mapping: column group g = tid % gp (gp = G rounded up to a power of
 // two; lanes with g >= G idle) and row lane tid / gp, rows row-lane, + RL, ...
-// Per-column sums: each thread's 4 partials, then a tree over tid with
-// strides that are multiples of gp (fixed order, so results do not depend on
-// timing).
+// Per-column sums in a fixed order (small_sum), so results do not depend on
+// timing.
 constexpr int kSmallBlock = 512;
 
 struct SmallScal {
@@ -1203,21 +1202,34 @@ struct SmallScal {
   int nact;
 };
 
-// Sum v (4 columns per thread) over the threads of each column group; the
-// total of column c is left in red[c].  Every thread must call it.
-__device__ __forceinline__ void small_sum(double* red, const double (&v)[4], int gp) {
-  const int tid = threadIdx.x;
-  for (int j = 0; j < 4; ++j) red[tid * 4 + j] = v[j];
-  for (int st = kSmallBlock / 2; st >= gp; st >>= 1) {
-    __syncthreads();
-    if (tid < st)
-      for (int j = 0; j < 4; ++j) red[tid * 4 + j] += red[(tid + st) * 4 + j];
+// Sum v (4 columns per thread) over the threads of each column group: a
+// butterfly inside each wavefront (lanes l and l ^ off, off a multiple of gp,
+// share the group), the sums of lane l < gp of every wavefront into LDS, then
+// one thread per column adds the wavefronts in order.  The total of column c
+// is left in tot[c].  Every thread must call it.
+constexpr int kSmallWaves = kSmallBlock / 64;
+
+__device__ __forceinline__ void small_sum(double* red, double* tot, double v0, double v1,
+                                          double v2, double v3, int gp) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double v[4] = {v0, v1, v2, v3};
+  for (int off = 32; off >= gp; off >>= 1)
+    for (int j = 0; j < 4; ++j) v[j] += __shfl_xor(v[j], off);
+  if (lane < gp)
+    for (int j = 0; j < 4; ++j) red[(wave * gp + lane) * 4 + j] = v[j];
+  __syncthreads();
+  if (tid < 4 * gp) {
+    const int gq = tid >> 2, j = tid & 3;
+    double sum = 0.0;
+    for (int w = 0; w < kSmallWaves; ++w) sum += red[(w * gp + gq) * 4 + j];
+    tot[tid] = sum;
   }
   __syncthreads();
 }
 
 __global__ __launch_bounds__(kSmallBlock) void k_small_steps(StepArgs a, SmallArgs sa) {
-  __shared__ double red[kSmallBlock * 4];
+  __shared__ double red[kSmallWaves * 64 * 4];
+  __shared__ double tot[4 * 64];
   __shared__ SmallScal cs;
   const int tid = threadIdx.x;
   const int n = a.t.n, rp = a.t.rp, G = rp / 4, W = a.W;
@@ -1277,14 +1289,14 @@ __global__ __launch_bounds__(kSmallBlock) void k_small_steps(StepArgs a, SmallAr
           st4(p + size_t(row) * rp + c0, pv);
         }
       double bb = 0, rz = 0, rr = 0;
-      small_sum(red, sb, gp);
-      if (tid < rp) bb = red[tid];
+      small_sum(red, tot, sb[0], sb[1], sb[2], sb[3], gp);
+      if (tid < rp) bb = tot[tid];
       __syncthreads();
-      small_sum(red, sz, gp);
-      if (tid < rp) rz = red[tid];
+      small_sum(red, tot, sz[0], sz[1], sz[2], sz[3], gp);
+      if (tid < rp) rz = tot[tid];
       __syncthreads();
-      small_sum(red, sr, gp);
-      if (tid < rp) rr = red[tid];
+      small_sum(red, tot, sr[0], sr[1], sr[2], sr[3], gp);
+      if (tid < rp) rr = tot[tid];
       if (tid == 0) cs.nact = 0;
       __syncthreads();
       if (tid < rp) {
@@ -1324,8 +1336,8 @@ __global__ __launch_bounds__(kSmallBlock) void k_small_steps(StepArgs a, SmallAr
           for (int j = 0; j < 4; ++j)
             if (act[j]) spq[j] += pd.v[j] * acc.v[j];
         }
-      small_sum(red, spq, gp);
-      if (tid < rp) cs.alpha[tid] = (cs.act[tid] && red[tid] > 0.0) ? cs.rz[tid] / red[tid] : 0.0;
+      small_sum(red, tot, spq[0], spq[1], spq[2], spq[3], gp);
+      if (tid < rp) cs.alpha[tid] = (cs.act[tid] && tot[tid] > 0.0) ? cs.rz[tid] / tot[tid] : 0.0;
       __syncthreads();
       // x += alpha p, r -= alpha q, z = D r; r.z and r.r
       double al[4] = {0, 0, 0, 0};
@@ -1348,11 +1360,11 @@ __global__ __launch_bounds__(kSmallBlock) void k_small_steps(StepArgs a, SmallAr
           st4(r + o, rv);
         }
       double rzn = 0, rrn = 0;
-      small_sum(red, szn, gp);
-      if (tid < rp) rzn = red[tid];
+      small_sum(red, tot, szn[0], szn[1], szn[2], szn[3], gp);
+      if (tid < rp) rzn = tot[tid];
       __syncthreads();
-      small_sum(red, srn, gp);
-      if (tid < rp) rrn = red[tid];
+      small_sum(red, tot, srn[0], srn[1], srn[2], srn[3], gp);
+      if (tid < rp) rrn = tot[tid];
       if (tid == 0) cs.nact = 0;
       __syncthreads();
       if (tid < rp && cs.act[tid]) {
@@ -1435,11 +1447,11 @@ __global__ __launch_bounds__(kSmallBlock) void k_small_steps(StepArgs a, SmallAr
             }
         }
       double vm = 0, va = 0;
-      small_sum(red, sm, gp);
-      if (tid < rp) vm = red[tid];
+      small_sum(red, tot, sm[0], sm[1], sm[2], sm[3], gp);
+      if (tid < rp) vm = tot[tid];
       __syncthreads();
-      small_sum(red, sa2, gp);
-      if (tid < rp) va = red[tid];
+      small_sum(red, tot, sa2[0], sa2[1], sa2[2], sa2[3], gp);
+      if (tid < rp) va = tot[tid];
       if (tid < rp) {
         const bool l = a.ct.live[tid] != 0;
         cs.nrm[tid] = l ? sqrt(vm) : 1.0;
@@ -1478,11 +1490,10 @@ __global__ __launch_bounds__(kSmallBlock) void k_small_steps(StepArgs a, SmallAr
                                     u + size_t(sa.tri[3 * t + 2]) * rp + lo, m) *
                       sa.tarea[t] * (1.0 / 180.0);
       }
-      // the tree needs strides that are multiples of np2: reuse small_sum
-      // with np2 as the group width (column slots 1..3 carry zeros)
-      small_sum(red, acc, np2);
+      // per-restart sums: small_sum with np2 as the group width (slot 0)
+      small_sum(red, tot, acc[0], 0.0, 0.0, 0.0, np2);
       if (tid < nres) {
-        const double se = red[tid * 4] * a.ct.res_ieps2[tid];
+        const double se = tot[tid * 4] * a.ct.res_ieps2[tid];
         const int lo = a.ct.res_lo[tid], m = a.ct.res_len[tid];
         double e = se;
         for (int i = 0; i < m; ++i) e += sa.lam[lo + i];
