@@ -49,17 +49,16 @@ def test_mesh_validation_errors():
     v, f = icosphere(1)
     bad = f.copy()
     bad[3, 1] = v.shape[0]          # index out of range
-    assert "out of range" in _expect(sp.SP_EMESH if hasattr(sp, "SP_EMESH") else -2,
-                                     sp.sp_mesh_create, v, bad)
-    _expect(-2, sp.sp_mesh_create, v, f[1:])             # open surface
+    assert "out of range" in _expect(sp.SP_EMESH, sp.sp_mesh_create, v, bad)
+    _expect(sp.SP_EMESH, sp.sp_mesh_create, v, f[1:])    # open surface
     deg = f.copy()
     deg[0] = [deg[0, 0], deg[0, 0], deg[0, 2]]           # repeated corner
-    _expect(-2, sp.sp_mesh_create, v, deg)
+    _expect(sp.SP_EMESH, sp.sp_mesh_create, v, deg)
     flat = v.copy()
     a, b, c = f[5]
     flat[c] = 0.5 * (flat[a] + flat[b])                  # zero-area triangle
-    _expect(-2, sp.sp_mesh_create, flat, f)
+    _expect(sp.SP_EMESH, sp.sp_mesh_create, flat, f)
     nanv = v.copy()
     nanv[2, 0] = np.nan
-    _expect(-1, sp.sp_mesh_create, nanv, f)
-    _expect(-1, sp.sp_mesh_create, v[:2], f[:1])
+    _expect(sp.SP_EINVAL, sp.sp_mesh_create, nanv, f)
+    _expect(sp.SP_EINVAL, sp.sp_mesh_create, v[:2], f[:1])
