@@ -35,7 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
-KERNEL_NAMES = ("matvec q=(M+tau A)p", "update x,r", "direction p")
+KERNEL_NAMES = ("matvec q=(M+tau A)p", "update r", "direction p")
 
 WORKLOADS = {
     # name: (mesh kind, [(seed, restarts, m)], eps, tau)

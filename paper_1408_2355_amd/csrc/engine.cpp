@@ -109,6 +109,13 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
       r32_.alloc(nv);
       p32_.alloc(nv);
       q32_.alloc(nv);
+      // direction ring of the inner CG: p32_ is slot 0
+      pring_[0] = p32_.p;
+      for (int i = 1; i < kPRing; ++i) {
+        pbuf_[i].alloc(nv);
+        pring_[i] = pbuf_[i].p;
+      }
+      ah_.alloc(size_t(kPRing) * rp_);
       for (int i = 0; i < prm_.extrapolate; ++i) {
         dbuf_[i].alloc(nv);
         dh_[i] = dbuf_[i].p;
@@ -134,6 +141,9 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     k::fill_f64(r64_.p, 0.0, nv, s_);
     for (int i = 0; i < kMaxExtrap; ++i)
       if (dh_[i]) k::fill_f32(dh_[i], 0.0f, nv, s_);
+    for (int i = 0; i < kPRing; ++i)
+      if (pring_[i]) k::fill_f32(pring_[i], 0.0f, nv, s_);
+    if (ah_.p) k::fill_f64(ah_.p, 0.0, ah_.n, s_);
     k::fill_f64(colf_.p, 0.0, colf_.n, s_);
     k::fill_i32(coli_.p, 0, coli_.n, s_);
     k::fill_i32(ring_.p, 0, ring_.n, s_);
@@ -588,13 +598,17 @@ void Solver::heat_mixed() {
       k::inner_init(args_, o, r64_.p, d32_.p, r32_.p, p32_.p, s_);
       k::red_inner_init(args_, o, s_);
     }
+    // inner CG in direction-ring form: d is formed from the stored
+    // directions when the ring fills and after the last iteration
+    int flushed = 0, last = 0;
     for (int it = 0; it < prm_.cg_max_iter; ++it) {
-      k::cg_iter<float>(args_, it, d32_.p, r32_.p, p32_.p, q32_.p, km_->K32.p, km_->dinv32.p, s_,
-                        prof_events());
-      const int last = it + 1;
+      k::cg_iter_ring(args_, it, r32_.p, pring_, q32_.p, ah_.p, d32_.p, &flushed, s_,
+                      prof_events());
+      last = it + 1;
       if (prm_.check_every > 0 && last % prm_.check_every == 0 && last < prm_.cg_max_iter)
         if (poll(ring_.p + last % kRing) == 0) break;
     }
+    if (last % kPRing) k::materialize(args_, pring_, ah_.p, 0, last % kPRing, flushed, d32_.p, s_);
     k::outer_update(args_, o, x, r64_.p, d32_.p, acc, s_);
     k::red_outer(args_, o, s_);
     olast = o + 1;
@@ -861,6 +875,7 @@ void Solver::kernel_time(int which, int64_t* launches, double* ms, double* bytes
     // their count.  Per column that is still iterating:
     //   0  q = K p            read p, write q; + the matrix (indices, values)
     //   1  x += a p, r -= a q read x, r, p, q, write x, r; + the diagonal
+    //      (mixed: r -= a q   read r, q, write r; + the diagonal)
     //   2  p = D r + b p      read r, p, write p; + the diagonal
     // Launches after convergence exit at once and move no data.
     long long st[4];
@@ -869,7 +884,8 @@ void Solver::kernel_time(int which, int64_t* launches, double* ms, double* bytes
     const double col_iters = double(st[3] - prof_stat0_[3]);
     const double s = prm_.precision == SP_FP64 ? 8.0 : 4.0;
     const double n = double(mesh_->n);
-    const double per[3] = {2.0, 6.0, 3.0};
+    // (the mixed inner CG keeps no iterate: its update reads r, q, writes r)
+    const double per[3] = {2.0, prm_.precision == SP_FP64 ? 6.0 : 3.0, 3.0};
     double b = n * col_iters * per[which] * s;
     b += work_iters * (which == 0 ? n * double(mesh_->W) * (4.0 + s) : n * s);
     *bytes_per_launch = prof_launches_[which] ? b / double(prof_launches_[which]) : 0.0;

@@ -136,6 +136,9 @@ class Solver {
 
   DevBuf<double> u_, r64_, p64_, q64_;
   DevBuf<float> d32_, r32_, p32_, q32_;
+  DevBuf<float> pbuf_[kPRing];        // direction ring slots 1.. (slot 0 is p32_)
+  float* pring_[kPRing] = {};
+  DevBuf<double> ah_;                 // [kPRing][rp] alpha of each ring slot
   // heat increments of the last prm_.extrapolate steps (extrapolated start):
   // dh_[0] the latest, dh_[q-1] the oldest; a solve overwrites the oldest
   // with its start guess g and accumulates its own increment on top of it,

@@ -65,6 +65,15 @@ struct StepArgs {
                        // [3] active columns summed over CG iterations
 };
 
+// Direction ring of the float32 inner CG (see kernels.hip).
+constexpr int kPRing = 8;
+struct RingArgs {
+  const float* p[kPRing] = {};
+  int row[kPRing] = {};  // coefficient row (ring slot) of each direction
+  int n = 0;
+  int accumulate = 0;    // 0: d = sum, 1: d += sum
+};
+
 // Linear combination of up to kMaxExtrap float32 vectors (start guess).
 constexpr int kMaxExtrap = 8;
 struct ExtrapArgs {
@@ -121,6 +130,15 @@ void red_init_fp64(const StepArgs& a, hipStream_t s);
 template <typename T>
 void cg_iter(const StepArgs& a, int it, T* x, T* r, T* p, T* q, const T* K, const T* dinv,
              hipStream_t s, const hipEvent_t* ev);
+// one iteration of the float32 inner CG in direction-ring form: directions
+// in pring[kPRing] (iteration it uses slot it % kPRing and writes the next),
+// alpha rows in ah[kPRing][rp]; when the ring fills, d (+)= sum alpha p and
+// *flushed is set (later folds accumulate)
+void cg_iter_ring(const StepArgs& a, int it, float* r, float* const* pring, float* q,
+                  double* ah, float* d, int* flushed, hipStream_t s, const hipEvent_t* ev);
+// d (+)= sum over count ring slots from first (cyclic) of alpha_slot p_slot
+void materialize(const StepArgs& a, float* const* pring, const double* ah, int first, int count,
+                 int accumulate, float* d, hipStream_t s);
 // the CG matrix product alone (q = K p over the active columns; needs
 // ring[0] != 0), used to time tilings
 template <typename T>

@@ -41,12 +41,13 @@ bool Server::compatible(const sp_params& a, const sp_params& b) {
 
 int64_t Server::batch_bytes(const Mesh* m, const sp_params& p, int cap, int rcap) {
   // state u and outer residual (float64) + CG vectors (float64 pair or
-  // float32 quad) and, for the extrapolated start, up to three float32
-  // increments and a float64 iterate per element, the float64/float32 K copies of this tau, the mesh matrices,
+  // float32 quad, plus the rest of the float32 direction ring) and, for the
+  // extrapolated start, the float32 increments and a float64 iterate per
+  // element, the float64/float32 K copies of this tau, the mesh matrices,
   // partial sums and tables
   const double n = double(m->n);
   const double per_col =
-      16.0 + 16.0 +
+      16.0 + 16.0 + (p.precision != SP_FP64 ? 4.0 * (kPRing - 1) : 0.0) +
       (p.precision != SP_FP64 && p.extrapolate ? 8.0 + 4.0 * p.extrapolate : 0.0);
   const double mats = double(m->W) * n * (4 + 8 + 8 + 8 + 4) + n * 28.0 + double(m->nt) * 20.0;
   const double part = 3.0 * 8.0 * cap * (n / 64.0 + 1.0);
