@@ -252,8 +252,8 @@ Solver::~Solver() {
 std::vector<Tile> Solver::tile_candidates() const {
   std::vector<Tile> out;
   const int n = int(mesh_->n);
-  for (int tg : {16, 32, 64})
-    for (int passes : {1, 2, 4})
+  for (int tg : {8, 16, 32, 64})
+    for (int passes : {1, 2, 4, 8})
       for (int nper : {64, 128, 256}) {
         Tile c = make_tile(n, rp_, tg, passes, nper);
         bool dup = false;
@@ -581,7 +581,7 @@ void Solver::heat_mixed() {
     }
     if (fast) {
       // A u and ||M u||^2 from the last step's norm pass: no float64 gather
-      k::refine_start(args_, u_.p, xg_.p, acc, r64_.p, d32_.p, r32_.p, p32_.p, s_);
+      k::refine_start(args_, xg_.p, acc, r64_.p, r32_.p, p32_.p, s_);
     } else {
       k::init_outer(args_, u_.p, acc, xg_.p, r64_.p, s_);
       k::red_outer_init(args_, s_);
@@ -609,11 +609,17 @@ void Solver::heat_mixed() {
         if (poll(ring_.p + last % kRing) == 0) break;
     }
     if (last % kPRing) k::materialize(args_, pring_, ah_.p, 0, last % kPRing, flushed, d32_.p, s_);
-    k::outer_update(args_, o, x, r64_.p, d32_.p, acc, s_);
+    // with a poll after this sweep the new residual is stored only if
+    // another sweep follows (most steps need one)
+    const bool polled = prm_.check_every > 0 && o + 1 < prm_.max_outer;
+    k::outer_update(args_, o, x, (fast && o == 0) ? u_.p : nullptr, r64_.p, d32_.p, acc, !polled,
+                    s_);
     k::red_outer(args_, o, s_);
     olast = o + 1;
-    if (prm_.check_every > 0 && olast < prm_.max_outer)
+    if (polled) {
       if (poll(args_.oring + olast % kRing) == 0) break;
+      k::outer_residual(args_, olast, r64_.p, d32_.p, s_);
+    }
   }
   k::flag_nonconv(args_, args_.oring + olast % kRing, s_);
   if (extrap) {

@@ -151,15 +151,20 @@ void init_outer(const StepArgs& a, const double* u, const float* g, double* x0, 
 void red_outer_init(const StepArgs& a, hipStream_t s);
 void inner_init(const StepArgs& a, int o, const double* r64, float* d, float* r, float* p,
                 hipStream_t s);
-// refinement start and first inner start from the norm pass's A v (in w_x0,
-// overwritten by x0 = u + g) and ||M u||^2; replaces init_outer,
-// red_outer_init, inner_init and red_inner_init of sweep 0
-void refine_start(const StepArgs& a, const double* u, double* w_x0, const float* g, double* r64,
-                  float* d, float* r, float* p, hipStream_t s);
+// refinement start and first inner start from the norm pass's A v (w) and
+// ||M u||^2; replaces init_outer, red_outer_init, inner_init and
+// red_inner_init of sweep 0 (the iterate u + g is formed by the first
+// outer_update in ubase mode)
+void refine_start(const StepArgs& a, const double* w, const float* g, double* r64, float* r,
+                  float* p, hipStream_t s);
 void red_inner_init(const StepArgs& a, int o, hipStream_t s);
-// u += d, r64 -= K d on the columns still refining; dacc (nullable) += d
-void outer_update(const StepArgs& a, int o, double* u, double* r64, const float* d, float* dacc,
-                  hipStream_t s);
+// x += d (ubase given: x = ubase + dacc + d), r64 -= K d on the columns
+// still refining; dacc (nullable) += d; store_r false: r64 not stored (then
+// outer_residual before another sweep)
+void outer_update(const StepArgs& a, int o, double* x, const double* ubase, double* r64,
+                  const float* d, float* dacc, bool store_r, hipStream_t s);
+// r64 -= K d on the columns still refining after sweep o - 1
+void outer_residual(const StepArgs& a, int o, double* r64, const float* d, hipStream_t s);
 // y = sum_j e.c[j] e.x[j] on the live columns, 0 on the others; y may be
 // one of the sources
 void extrap(const StepArgs& a, const ExtrapArgs& e, float* y, hipStream_t s);

@@ -679,16 +679,14 @@ __global__ void k_red_outer_init(StepArgs a) {
 // Refinement start and first inner start in one pass, from the previous
 // step's norm pass: the state u = v / n is already scaled and w holds A v, so
 // A u = w / n needs no float64 gather.  With the start guess g:
-//   x0 = u + g (written over w), r64 = b - K x0 = -tau A u - K64 g,
-//   r32 = float(r64), p = D r32 (the correction d is formed by the inner
-//   solve itself),
-// partials ||r64||^2, r32.p, ||r32||^2.  Columns that are not live get x0 = u
-// and zeros.  Tiling tm (the float32 gather of g).
-__global__ __launch_bounds__(kBlock) void k_refine_start(StepArgs a, const double* __restrict__ u,
-                                                         double* w_x0,
+//   r64 = b - K (u + g) = -tau A u - K64 g, r32 = float(r64), p = D r32;
+// the iterate u + g is formed by the first refinement update (ubase mode),
+// and the correction d by the inner solve.  Partials ||r64||^2, r32.p,
+// ||r32||^2.  Columns that are not live get zeros.  Tiling tm (the float32
+// gather of g).
+__global__ __launch_bounds__(kBlock) void k_refine_start(StepArgs a, const double* __restrict__ w,
                                                          const float* __restrict__ gd,
                                                          double* __restrict__ r64,
-                                                         float* __restrict__ d,
                                                          float* __restrict__ r,
                                                          float* __restrict__ p) {
   const Tile& t = a.tm;
@@ -705,32 +703,23 @@ __global__ __launch_bounds__(kBlock) void k_refine_start(StepArgs a, const doubl
     }
     for_rows(t, [&](int row) {
       double kg[4] = {};
-      V4<float> go = {};
-      for_neighbors(a, row, c0, gd, [&](int k, const V4<float>& x, size_t o) {
+      for_neighbors(a, row, c0, gd, [&](int, const V4<float>& x, size_t o) {
         const double v = ldm(a.K64 + o);
-        if (k == 0) go = x;
         for (int j = 0; j < 4; ++j) kg[j] = fma(v, double(x.v[j]), kg[j]);
       });
       const size_t o = size_t(row) * t.rp + c0;
-      const V4<double> uv = ld4(u + o), wv = ld4(w_x0 + o);
+      const V4<double> wv = ld4(w + o);
       const float di = a.dinv32[row];
-      V4<double> xv, rv;
+      V4<double> rv;
       V4<float> r32, pv;
       for (int j = 0; j < 4; ++j) {
-        if (lv[j]) {
-          rv.v[j] = -a.tau * (wv.v[j] * inv[j]) - kg[j];
-          xv.v[j] = uv.v[j] + double(go.v[j]);
-        } else {
-          rv.v[j] = 0.0;
-          xv.v[j] = uv.v[j];
-        }
+        rv.v[j] = lv[j] ? -a.tau * (wv.v[j] * inv[j]) - kg[j] : 0.0;
         r32.v[j] = float(rv.v[j]);
         pv.v[j] = di * r32.v[j];
         s[0][j] += rv.v[j] * rv.v[j];
         s[1][j] += double(r32.v[j]) * double(pv.v[j]);
         s[2][j] += double(r32.v[j]) * double(r32.v[j]);
       }
-      st4(w_x0 + o, xv);
       st4(r64 + o, rv);
       st4(r + o, r32);
       st4(p + o, pv);
@@ -824,16 +813,22 @@ __global__ void k_red_inner_init(StepArgs a, int oslot, int onext) {
   count_active(act, a.ring + 0);
 }
 
-// x64 += d; r64 -= K64 d (float64 product of the float32 correction);
-// partial ||r64||^2, on the columns still refining.  dacc (if given)
-// accumulates the corrections on top of the start guess, so after the last
-// sweep it holds the step's heat increment x - u.
+// x += d; r64 -= K64 d (float64 product of the float32 correction), on the
+// columns still refining; partial ||r64||^2 of the new residual.  dacc (if
+// given) accumulates the corrections on top of the start guess, so after the
+// last sweep it holds the step's heat increment x - u.
+// ubase (nullable, first sweep of the fused start): the iterate is formed
+// here as x = ubase + dacc (+ d), for every column of a group with a live
+// column (dacc is 0 on columns that are not live), instead of being read.
+// store_r == 0 leaves r64 as it was (the partial still measures the new
+// residual); outer_residual stores it when another sweep follows.
 __global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot,
-                                                         double* __restrict__ u,
+                                                         double* __restrict__ x,
+                                                         const double* __restrict__ ubase,
                                                          double* __restrict__ r64,
                                                          const float* __restrict__ d,
-                                                         float* __restrict__ dacc) {
-  if (a.oring[oslot] == 0) return;
+                                                         float* __restrict__ dacc, int store_r) {
+  if (!ubase && a.oring[oslot] == 0) return;
   const Tile& t = a.tm;
   for (int ct = 0; ct < t.nct; ++ct) {
   const int g = ct * t.tg + threadIdx.x % t.tg;
@@ -841,42 +836,82 @@ __global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot,
   double s[1][4] = {};
   if (g < t.G) {
     const int c0 = 4 * g;
-    int act[4], any = 0;
+    int act[4], any = 0, anylive = 0;
     for (int j = 0; j < 4; ++j) {
       act[j] = mask[c0 + j];
       any |= act[j];
+      anylive |= a.ct.live[c0 + j];
     }
-    if (any) {
+    if (any || (ubase && anylive)) {
       for_rows(t, [&](int row) {
         double kd[4] = {};
         float dd[4] = {};
-        for_neighbors(a, row, c0, d, [&](int k, const V4<float>& x, size_t o) {
-          const double v = ldm(a.K64 + o);
-          if (k == 0)
-            for (int j = 0; j < 4; ++j) dd[j] = x.v[j];
-          for (int j = 0; j < 4; ++j) kd[j] = fma(v, double(x.v[j]), kd[j]);
-        });
+        if (any)
+          for_neighbors(a, row, c0, d, [&](int k, const V4<float>& xv, size_t o) {
+            const double v = ldm(a.K64 + o);
+            if (k == 0)
+              for (int j = 0; j < 4; ++j) dd[j] = xv.v[j];
+            for (int j = 0; j < 4; ++j) kd[j] = fma(v, double(xv.v[j]), kd[j]);
+          });
         const size_t o = size_t(row) * t.rp + c0;
-        V4<double> uv = ld4(u + o), rv = ld4(r64 + o);
+        V4<float> av = {};
+        if (dacc) av = ld4(dacc + o);
+        V4<double> xv;
+        if (ubase) {
+          const V4<double> ub = ld4(ubase + o);
+          for (int j = 0; j < 4; ++j) xv.v[j] = ub.v[j] + double(av.v[j]);
+        } else {
+          xv = ld4(x + o);
+        }
+        V4<double> rv = {};
+        if (any) rv = ld4(r64 + o);
         for (int j = 0; j < 4; ++j) {
           if (act[j]) {
-            uv.v[j] += double(dd[j]);
+            xv.v[j] += double(dd[j]);
             rv.v[j] -= kd[j];
             s[0][j] += rv.v[j] * rv.v[j];
+            av.v[j] += dd[j];
           }
         }
-        st4(u + o, uv);
-        st4(r64 + o, rv);
-        if (dacc) {
-          V4<float> av = ld4(dacc + o);
-          for (int j = 0; j < 4; ++j)
-            if (act[j]) av.v[j] += dd[j];
-          st4(dacc + o, av);
-        }
+        st4(x + o, xv);
+        if (any && store_r) st4(r64 + o, rv);
+        if (dacc && any) st4(dacc + o, av);
       });
     }
   }
   block_store<1>(t, s, a.part, blockIdx.x, ct);
+  }
+}
+
+// r64 -= K64 d on the columns still refining, after a sweep whose update did
+// not store r64 (it is needed only when another sweep follows).
+__global__ __launch_bounds__(kBlock) void k_outer_residual(StepArgs a, int oslot,
+                                                           double* __restrict__ r64,
+                                                           const float* __restrict__ d) {
+  if (a.oring[oslot] == 0) return;
+  const Tile& t = a.tm;
+  for (int ct = 0; ct < t.nct; ++ct) {
+    const int g = ct * t.tg + threadIdx.x % t.tg;
+    if (g >= t.G) continue;
+    const int c0 = 4 * g;
+    int act[4], any = 0;
+    for (int j = 0; j < 4; ++j) {
+      act[j] = a.cg.act_o[c0 + j];
+      any |= act[j];
+    }
+    if (!any) continue;
+    for_rows(t, [&](int row) {
+      double kd[4] = {};
+      for_neighbors(a, row, c0, d, [&](int, const V4<float>& xv, size_t o) {
+        const double v = ldm(a.K64 + o);
+        for (int j = 0; j < 4; ++j) kd[j] = fma(v, double(xv.v[j]), kd[j]);
+      });
+      const size_t o = size_t(row) * t.rp + c0;
+      V4<double> rv = ld4(r64 + o);
+      for (int j = 0; j < 4; ++j)
+        if (act[j]) rv.v[j] -= kd[j];
+      st4(r64 + o, rv);
+    });
   }
 }
 
@@ -1837,10 +1872,9 @@ void red_outer_init(const StepArgs& a, hipStream_t s) {
   SP_LAUNCH_CHECK();
 }
 
-void refine_start(const StepArgs& a, const double* u, double* w_x0, const float* g, double* r64,
-                  float* d, float* r, float* p, hipStream_t s) {
-  hipLaunchKernelGGL(k_refine_start, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, u, w_x0, g, r64, d, r,
-                     p);
+void refine_start(const StepArgs& a, const double* w, const float* g, double* r64, float* r,
+                  float* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_refine_start, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, w, g, r64, r, p);
   hipLaunchKernelGGL(k_red_refine_start, dim3(colblocks(a.t)), dim3(kBlock), 0, s, a);
   SP_LAUNCH_CHECK();
 }
@@ -1857,10 +1891,15 @@ void red_inner_init(const StepArgs& a, int o, hipStream_t s) {
   SP_LAUNCH_CHECK();
 }
 
-void outer_update(const StepArgs& a, int o, double* u, double* r64, const float* d, float* dacc,
-                  hipStream_t s) {
-  hipLaunchKernelGGL(k_outer_update, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, o % kRing, u,
-                     r64, d, dacc);
+void outer_update(const StepArgs& a, int o, double* x, const double* ubase, double* r64,
+                  const float* d, float* dacc, bool store_r, hipStream_t s) {
+  hipLaunchKernelGGL(k_outer_update, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, o % kRing, x, ubase,
+                     r64, d, dacc, int(store_r));
+  SP_LAUNCH_CHECK();
+}
+
+void outer_residual(const StepArgs& a, int o, double* r64, const float* d, hipStream_t s) {
+  hipLaunchKernelGGL(k_outer_residual, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, o % kRing, r64, d);
   SP_LAUNCH_CHECK();
 }
 
