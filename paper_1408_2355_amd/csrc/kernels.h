@@ -56,6 +56,7 @@ struct StepArgs {
   double tau;
   double rtol2;        // cg_rtol^2
   double inner_rtol2;  // inner_rtol^2
+  double inner_floor2 = 0.81;  // an inner solve stops at sqrt(this) x the outer target
   ColTab ct;
   CgCols cg;
   double* part;        // [3][nchunk][rp] partial sums

@@ -746,7 +746,7 @@ __global__ void k_red_refine_start(StepArgs a) {
     act_o = (a.ct.live[c] && rr > a.rtol2 * bb) ? 1 : 0;
     a.cg.act_o[c] = act_o;
     a.cg.rz[c] = rz;
-    a.cg.tol2[c] = fmax(a.inner_rtol2 * r2, 0.0625 * a.rtol2 * bb);
+    a.cg.tol2[c] = fmax(a.inner_rtol2 * r2, a.inner_floor2 * a.rtol2 * bb);
     act = (act_o && r2 > 0.0) ? 1 : 0;
     a.cg.act[c] = act;
     a.cg.alpha[c] = 0.0;
@@ -802,9 +802,9 @@ __global__ void k_red_inner_init(StepArgs a, int oslot, int onext) {
   int act = 0;
   if (red_lead() && c < t.rp) {
     a.cg.rz[c] = rz;
-    // stop the inner solve once its residual drops by inner_rtol, or below a
-    // quarter of the outer target (no point solving further than needed)
-    a.cg.tol2[c] = fmax(a.inner_rtol2 * rr, 0.0625 * a.rtol2 * a.cg.bb[c]);
+    // stop the inner solve once its residual drops by inner_rtol, or below
+    // sqrt(inner_floor2) x the outer target (no point solving further)
+    a.cg.tol2[c] = fmax(a.inner_rtol2 * rr, a.inner_floor2 * a.rtol2 * a.cg.bb[c]);
     act = (a.cg.act_o[c] && rr > 0.0) ? 1 : 0;
     a.cg.act[c] = act;
     a.cg.alpha[c] = 0.0;
