@@ -6,7 +6,7 @@
 // JSON file as well (read at first use, rewritten after each new entry).
 // SEGPART_AUTOTUNE=0/1 switches the search off/on (default: on for batches of
 // at least 2^22 vertex-column values), SEGPART_TUNE_VERBOSE prints the
-// timings, SEGPART_SEPS_KERNEL=staged|direct forces the S_eps element kernel,
+// timings, SEGPART_SEPS_KERNEL=staged|direct|lanes forces the S_eps element kernel,
 // SEGPART_INNER_FLOOR=f (0 < f < 1, default 0.9) sets where a float32 inner
 // solve stops relative to the outer target (f x cg_rtol ||b||), and
 // SEGPART_SMALL=0 keeps small batches on the multi-kernel path.

@@ -236,6 +236,7 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     if (const char* e = std::getenv("SEGPART_SEPS_KERNEL")) {
       if (std::strcmp(e, "direct") == 0) sp_.direct = 1;
       if (std::strcmp(e, "staged") == 0) sp_.direct = 0;
+      if (std::strcmp(e, "lanes") == 0) sp_.direct = 2;
     }
   } catch (...) {
     if (h_poll_) (void)hipHostFree(h_poll_);
@@ -350,14 +351,15 @@ void Solver::autotune() {
     args_.t64 = make_tile(int(mesh_->n), rp_, b64.tg_cap, b64.passes, b64.nper_cap);
   }
 
-  // S_eps element kernel: LDS-staged or direct corner reads, whichever is
-  // faster for this batch's restart tiles
+  // S_eps element kernel: LDS-staged, direct corner reads or lane-split,
+  // whichever is fastest for this batch's restart tiles
   if (sp_.ntile > 0) {
     hipEvent_t e0, e1;
     SP_HIP(hipEventCreate(&e0));
     SP_HIP(hipEventCreate(&e1));
-    double t_mode[2] = {0, 0};
-    for (int mode = 0; mode < 2; ++mode) {
+    const int nmode = sp_.lanes_ok ? 3 : 2;
+    double t_mode[3] = {0, 0, 0};
+    for (int mode = 0; mode < nmode; ++mode) {
       sp_.direct = mode;
       k::energy_seps(args_, sp_, mesh_->tri.p, mesh_->tarea.p, u_.p, part_s_.p, s_);
       SP_HIP(hipEventRecord(e0, s_));
@@ -369,10 +371,13 @@ void Solver::autotune() {
       SP_HIP(hipEventElapsedTime(&ms, e0, e1));
       t_mode[mode] = ms;
       if (std::getenv("SEGPART_TUNE_VERBOSE"))
-        std::fprintf(stderr, "[segpart tune] S_eps %s: %.1f us\n", mode ? "direct" : "staged",
-                     500.0 * ms);
+        std::fprintf(stderr, "[segpart tune] S_eps %s: %.1f us\n",
+                     mode == 2 ? "lanes" : mode ? "direct" : "staged", 500.0 * ms);
     }
-    sp_.direct = t_mode[1] < t_mode[0] ? 1 : 0;
+    int best = 0;
+    for (int mode = 1; mode < nmode; ++mode)
+      if (t_mode[mode] < t_mode[best]) best = mode;
+    sp_.direct = best;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
   }
@@ -403,6 +408,14 @@ void Solver::push_tables() {
                         nres_p_ * sizeof(double), hipMemcpyHostToDevice, s_));
   std::vector<int4> tiles = k::seps_tiles(h_res_lo_, h_res_len_, nres);
   sp_.ntile = int(tiles.size());
+  // the lane-split S_eps kernel needs restarts on 4-column boundaries and
+  // tiles of at most 256 columns
+  sp_.lanes_ok = 1;
+  for (const int4& tl : tiles) {
+    if (tl.w - tl.z > 256) sp_.lanes_ok = 0;
+    for (int r = tl.x; r < tl.y; ++r)
+      if (h_res_len_[r] > 0 && (h_res_lo_[r] % 4 != 0 || h_res_len_[r] % 4 != 0)) sp_.lanes_ok = 0;
+  }
   sp_.tiles = seps_tiles_.p;
   if (!tiles.empty())
     SP_HIP(hipMemcpyAsync(seps_tiles_.p, tiles.data(), tiles.size() * sizeof(int4),

@@ -116,7 +116,9 @@ struct SepsPlan {
   int nper = 0;    // workgroups per XCD (8 * nper partial rows per restart)
   int nt = 0;      // triangles
   int nres_p = 0;  // row stride of the partial sums
-  int direct = 0;  // 1 = corners read from global memory, 0 = staged in LDS
+  int direct = 0;  // 0 = staged in LDS, 1 = corners read from global memory by one
+                   // lane per restart, 2 = lane-split restarts (needs lanes_ok)
+  int lanes_ok = 0;  // every restart of every tile starts and ends on a multiple of 4
 };
 namespace k {
 std::vector<int4> seps_tiles(const std::vector<int>& res_lo, const std::vector<int>& res_len,

@@ -1165,6 +1165,22 @@ __device__ __forceinline__ double quartic_pairs(const double* u0, const double* 
   int i = 0;
   if (((reinterpret_cast<size_t>(u0) | reinterpret_cast<size_t>(u1) |
         reinterpret_cast<size_t>(u2)) & 15) == 0) {
+    // 8 components at a time: all 12 loads are issued before the recursion
+    // uses them
+    for (; i + 7 < m; i += 8) {
+      double2 a0[4], a1[4], a2[4];
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        a0[h] = *reinterpret_cast<const double2*>(u0 + i + 2 * h);
+        a1[h] = *reinterpret_cast<const double2*>(u1 + i + 2 * h);
+        a2[h] = *reinterpret_cast<const double2*>(u2 + i + 2 * h);
+      }
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        qp.add(a0[h].x, a1[h].x, a2[h].x);
+        qp.add(a0[h].y, a1[h].y, a2[h].y);
+      }
+    }
     for (; i + 1 < m; i += 2) {
       const double2 a0 = *reinterpret_cast<const double2*>(u0 + i);
       const double2 a1 = *reinterpret_cast<const double2*>(u1 + i);
@@ -1311,6 +1327,105 @@ __global__ __launch_bounds__(kBlock) void k_energy_seps_direct(StepArgs a, SepsP
     }
     __syncthreads();
     if (tb == 0 && rr < nr) part_s[size_t(blockIdx.x) * sp.nres_p + r0 + rr] = red[tid];
+    __syncthreads();
+  });
+}
+
+// Lane-split variant for tiles whose restarts start and end on 4-column
+// boundaries.  One wavefront takes one triangle and one restart tile (at most
+// 256 columns = 64 lanes x 4): lane l owns columns c0 + 4l .. +3, so the
+// wavefront reads each corner row of the tile as one contiguous run.  A lane
+// runs the prefix recursion over its 4 components from zero (local sum and
+// H_l = sum a a^T), the lanes of each restart take an exclusive prefix of H
+// (shuffles), and since B is bilinear the lane's share is
+//   local + B(G_before, H_l),  G_before = sum of H over the restart's lower lanes.
+__device__ __forceinline__ double quartic_b(const double (&G)[6], const double (&H)[6]) {
+  // symmetric 3x3 as (00, 11, 22, 01, 02, 12)
+  const double trG = G[0] + G[1] + G[2], trH = H[0] + H[1] + H[2];
+  const double SG = trG + 2.0 * (G[3] + G[4] + G[5]), SH = trH + 2.0 * (H[3] + H[4] + H[5]);
+  const double gi[3] = {G[0] + G[3] + G[4], G[3] + G[1] + G[5], G[4] + G[5] + G[2]};
+  const double hi[3] = {H[0] + H[3] + H[4], H[3] + H[1] + H[5], H[4] + H[5] + H[2]};
+  const double GH = G[0] * H[0] + G[1] * H[1] + G[2] * H[2] +
+                    2.0 * (G[3] * H[3] + G[4] * H[4] + G[5] * H[5]);
+  double gh = 0, dgh = 0, gdh = 0, dgdh = 0;
+  for (int q = 0; q < 3; ++q) {
+    gh += gi[q] * hi[q];
+    dgh += G[q] * hi[q];
+    gdh += gi[q] * H[q];
+    dgdh += G[q] * H[q];
+  }
+  return (SG + trG) * (SH + trH) + 2.0 * GH + 4.0 * (gh + dgh + gdh) + 6.0 * dgdh;
+}
+
+__global__ __launch_bounds__(kBlock) void k_energy_seps_lanes(StepArgs a, SepsPlan sp,
+                                                              const int* __restrict__ tri,
+                                                              const double* __restrict__ tarea,
+                                                              const double* __restrict__ u,
+                                                              double* __restrict__ part_s) {
+  __shared__ double red[kBlock];
+  const int rp = a.t.rp;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int kW = kBlock / 64;
+  for_seps_chunks(sp, [&](int tile, int cb, int ce, int stride) {
+    const int4 tl = sp.tiles[tile];
+    const int r0 = tl.x, c0 = tl.z, ncol = tl.w - tl.z;
+    const int c = c0 + 4 * lane;
+    const bool on = 4 * lane < ncol;
+    // the lane's restart and its position among the restart's lanes; lanes
+    // per restart at most kmax (the prefix needs log2(kmax) shuffle steps)
+    int k = 0;
+    if (on) k = (c - a.ct.seg_lo[c]) >> 2;
+    int kmax = 1;
+    for (int q = tl.x; q < tl.y; ++q) kmax = max(kmax, a.ct.res_len[q] >> 2);
+    double acc = 0.0;
+    for (int chunk = cb; chunk < ce; chunk += stride) {
+      const int t_beg = chunk * sp.tchunk, t_end = min(t_beg + sp.tchunk, sp.nt);
+      for (int t = t_beg + wave; t < t_end; t += kW) {
+        double H[6] = {0, 0, 0, 0, 0, 0}, loc = 0.0;
+        if (on) {
+          const double* p0 = u + size_t(tri[3 * t + 0]) * rp + c;
+          const double* p1 = u + size_t(tri[3 * t + 1]) * rp + c;
+          const double* p2 = u + size_t(tri[3 * t + 2]) * rp + c;
+          const V4<double> x0 = ld4(p0), x1 = ld4(p1), x2 = ld4(p2);
+          QuarticPairs qp;
+          for (int j = 0; j < 4; ++j) qp.add(x0.v[j], x1.v[j], x2.v[j]);
+          loc = qp.acc;
+          H[0] = qp.g00;
+          H[1] = qp.g11;
+          H[2] = qp.g22;
+          H[3] = qp.g01;
+          H[4] = qp.g02;
+          H[5] = qp.g12;
+        }
+        // inclusive prefix of H over the restart's lanes (k = position)
+        double P[6];
+        for (int q = 0; q < 6; ++q) P[q] = H[q];
+        for (int d = 1; d < kmax; d <<= 1) {
+          double up[6];
+          for (int q = 0; q < 6; ++q) up[q] = __shfl_up(P[q], d);
+          if (k >= d)
+            for (int q = 0; q < 6; ++q) P[q] += up[q];
+        }
+        double G[6];
+        for (int q = 0; q < 6; ++q) G[q] = P[q] - H[q];  // exclusive
+        if (on && k > 0) loc += quartic_b(G, H);
+        if (on) acc += loc * tarea[t] * (1.0 / 180.0);
+      }
+    }
+    // per restart: its lanes, then the workgroup's wavefronts, in order
+    red[tid] = acc;
+    __syncthreads();
+    const int nr = tl.y - tl.x;
+    if (tid < nr) {
+      const int lo = a.ct.res_lo[r0 + tid], m = a.ct.res_len[r0 + tid];
+      double sum = 0.0;
+      if (m > 0) {
+        const int l0 = (lo - c0) >> 2, l1 = (lo - c0 + m) >> 2;
+        for (int w = 0; w < kW; ++w)
+          for (int l = l0; l < l1; ++l) sum += red[w * 64 + l];
+      }
+      part_s[size_t(blockIdx.x) * sp.nres_p + r0 + tid] = sum;
+    }
     __syncthreads();
   });
 }
@@ -1942,7 +2057,10 @@ void energy_rq(const StepArgs& a, const double* u, hipStream_t s) {
 void energy_seps(const StepArgs& a, const SepsPlan& sp, const int32_t* tri, const double* tarea,
                  const double* u, double* part_s, hipStream_t s) {
   if (sp.ntile == 0) return;
-  if (sp.direct)
+  if (sp.direct == 2 && sp.lanes_ok)
+    hipLaunchKernelGGL(k_energy_seps_lanes, dim3(8 * sp.nper), dim3(kBlock), 0, s, a, sp, tri,
+                       tarea, u, part_s);
+  else if (sp.direct)
     hipLaunchKernelGGL(k_energy_seps_direct, dim3(8 * sp.nper), dim3(kBlock), 0, s, a, sp, tri,
                        tarea, u, part_s);
   else

@@ -6,9 +6,9 @@ Unit sphere, icosahedral level 7 (163842 vertices), m in {4, 8, 12, 16} with
 float32 CG in float64 refinement (outer rtol 1e-10, inner 1e-6, poll every 8
 iterations), start extrapolated from five increments, energy every step.
 Six steps (the sixth uses the five-increment start), once with each S_eps
-element kernel.
+element kernel (LDS-staged, direct, lane-split).
 
-Checks: the two runs give the same state (the S_eps kernel does not touch
+Checks: the three runs give the same state (the S_eps kernel does not touch
 the flow) and the same S_eps to 1e-12; restart 0 of every m group matches the
 oracle run of that restart alone (u, every lambda_i, S_eps, E) within 1e-5,
 the mixed-precision bar; every restart's E equals its sum lambda + S_eps.
@@ -55,7 +55,7 @@ def runs():
     out = {}
     old = os.environ.get("SEGPART_SEPS_KERNEL")
     try:
-        for kern in ("staged", "direct"):
+        for kern in ("staged", "direct", "lanes"):
             os.environ["SEGPART_SEPS_KERNEL"] = kern
             print(f"level 7 batch, {STEPS} steps, S_eps kernel {kern}", flush=True)
             prm = sp.params(TAU, precision="mixed", n_steps=1, energy_every=1, cg_rtol=1e-10,
@@ -83,12 +83,14 @@ def runs():
 
 def test_seps_kernels_agree_and_flow_is_unchanged(runs):
     v, f, u0, ms, first, col0, out = runs
-    a, b = out["staged"], out["direct"]
-    assert rel(b["u_sample"], a["u_sample"]) < 1e-14
-    assert rel(b["u_sum"], a["u_sum"]) < 1e-14
-    assert rel(b["lam"], a["lam"]) < 1e-13
-    assert rel(b["s_eps"], a["s_eps"]) < 1e-12
-    for kern in ("staged", "direct"):
+    b = out["direct"]
+    for other in ("staged", "lanes"):
+        a = out[other]
+        assert rel(b["u_sample"], a["u_sample"]) < 1e-14
+        assert rel(b["u_sum"], a["u_sum"]) < 1e-14
+        assert rel(b["lam"], a["lam"]) < 1e-13
+        assert rel(b["s_eps"], a["s_eps"]) < 1e-12
+    for kern in ("staged", "direct", "lanes"):
         r = out[kern]
         lo = 0
         for i, m in enumerate(ms):
