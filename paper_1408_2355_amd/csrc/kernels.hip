@@ -45,6 +45,39 @@ __device__ __forceinline__ void st4(double* p, const V4<double>& x) {
 __device__ __forceinline__ void st4(float* p, const V4<float>& x) {
   *reinterpret_cast<float4*>(p) = make_float4(x.v[0], x.v[1], x.v[2], x.v[3]);
 }
+// Nontemporal (nt) forms, for data touched once per launch: every operand
+// of the streaming kernels, the output of the gathering kernels and their
+// row's own operands.  They do not displace the gathered operand's rows
+// from L2, where the reuse between neighbouring rows happens (the matrix
+// product runs about 15% faster with them, the time step about 8%).
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void st4_nt(float* p, const V4<float>& x) {
+  f4v v = {x.v[0], x.v[1], x.v[2], x.v[3]};
+  __builtin_nontemporal_store(v, reinterpret_cast<f4v*>(p));
+}
+__device__ __forceinline__ void st4_nt(double* p, const V4<double>& x) {
+  d2v a = {x.v[0], x.v[1]}, b = {x.v[2], x.v[3]};
+  __builtin_nontemporal_store(a, reinterpret_cast<d2v*>(p));
+  __builtin_nontemporal_store(b, reinterpret_cast<d2v*>(p) + 1);
+}
+__device__ __forceinline__ V4<float> ld4_nt(const float* p) {
+  f4v v = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p));
+  return {{v.x, v.y, v.z, v.w}};
+}
+__device__ __forceinline__ V4<double> ld4_nt(const double* p) {
+  d2v a = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
+  d2v b = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p) + 1);
+  return {{a.x, a.y, b.x, b.y}};
+}
+template <typename T>
+__device__ __forceinline__ V4<T> ld4g(const T* p) { return ld4_nt(p); }  // own row, gathering kernel
+template <typename T>
+__device__ __forceinline__ void st4g(T* p, const V4<T>& x) { st4_nt(p, x); }  // gathering kernel
+template <typename T>
+__device__ __forceinline__ V4<T> ld4s(const T* p) { return ld4_nt(p); }  // streaming kernel
+template <typename T>
+__device__ __forceinline__ void st4s(T* p, const V4<T>& x) { st4_nt(p, x); }  // streaming kernel
 
 // Row traversal of the row-parallel kernels.  Workgroups are handed to the
 // 8 XCDs round-robin by id, so workgroup b runs on XCD b % 8.  The rows are
@@ -153,7 +186,12 @@ __device__ __forceinline__ void count_active(int flag, int* counter) {
 // pads it; padding slots point at the row itself with value 0), so slots are
 // walked in groups of kSlots with straight-line code: all indices of a group
 // are loaded, then all neighbour vectors are requested, then used, so a
-// thread keeps kSlots gathers in flight.  f(k, x_k, o) gets the slot, the
+// thread keeps kSlots gathers in flight.  The last slot of a group, when it
+// is padding (index = row), requests nothing and hands f zeros: on a
+// triangle mesh of valence 6 every row has 7 entries, so one gather in 8 is
+// saved, and the gathers are what bounds the product.  (Only the last slot
+// is tested, after all indices of the group are loaded, so the other loads
+// of the group stay in flight together.)  f(k, x_k, o) gets the slot, the
 // neighbour's 4 column values and the matrix offset o = k*n + row.
 constexpr int kSlots = 8;
 
@@ -175,7 +213,9 @@ __device__ __forceinline__ void for_neighbors(const StepArgs& a, int row, int c0
     for (int k = 0; k < kSlots; ++k) idx[k] = ldm(a.cols + size_t(kb + k) * n + row);
     V4<T> xv[kSlots];
 #pragma unroll
-    for (int k = 0; k < kSlots; ++k) xv[k] = ld4(x + size_t(idx[k]) * rp + c0);
+    for (int k = 0; k < kSlots - 1; ++k) xv[k] = ld4(x + size_t(idx[k]) * rp + c0);
+    constexpr int kl = kSlots - 1;
+    xv[kl] = idx[kl] != row ? ld4(x + size_t(idx[kl]) * rp + c0) : V4<T>{};
 #pragma unroll
     for (int k = 0; k < kSlots; ++k) f(kb + k, xv[k], size_t(kb + k) * n + row);
   }
@@ -292,8 +332,8 @@ __global__ __launch_bounds__(kBlock) void k_init_fp64(StepArgs a, const double* 
         s[1][j] += rv.v[j] * pv.v[j];
         s[2][j] += rv.v[j] * rv.v[j];
       }
-      st4(r + size_t(row) * t.rp + c0, rv);
-      st4(p + size_t(row) * t.rp + c0, pv);
+      st4g(r + size_t(row) * t.rp + c0, rv);
+      st4g(p + size_t(row) * t.rp + c0, pv);
     });
   }
   block_store<3>(t, s, a.part, blockIdx.x, ct);
@@ -339,7 +379,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmm(StepArgs a, int slot, const 
           if (k == 0) pd = x;
           for (int j = 0; j < 4; ++j) acc.v[j] = fma(v, x.v[j], acc.v[j]);
         });
-        st4(q + size_t(row) * t.rp + c0, acc);
+        st4g(q + size_t(row) * t.rp + c0, acc);
         for (int j = 0; j < 4; ++j) s[0][j] += double(pd.v[j]) * double(acc.v[j]);
       });
     }
@@ -394,8 +434,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(StepArgs a, int slot, T* _
     if (any) {
       for_rows(t, [&](int row) {
         const size_t o = size_t(row) * t.rp + c0;
-        V4<T> xv = ld4(x + o), rv = ld4(r + o);
-        const V4<T> pv = ld4(p + o), qv = ld4(q + o);
+        V4<T> xv = ld4s(x + o), rv = ld4s(r + o);
+        const V4<T> pv = ld4s(p + o), qv = ld4s(q + o);
         const T di = dinv[row];
         for (int j = 0; j < 4; ++j) {
           if (act[j]) {
@@ -406,8 +446,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(StepArgs a, int slot, T* _
             s[1][j] += rd * rd;
           }
         }
-        st4(x + o, xv);
-        st4(r + o, rv);
+        st4s(x + o, xv);
+        st4s(r + o, rv);
       });
     }
   }
@@ -468,8 +508,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_r(StepArgs a, int slot,
     if (any) {
       for_rows(t, [&](int row) {
         const size_t o = size_t(row) * t.rp + c0;
-        V4<float> rv = ld4(r + o);
-        const V4<float> qv = ld4(q + o);
+        V4<float> rv = ld4s(r + o);
+        const V4<float> qv = ld4s(q + o);
         const float di = dinv[row];
         for (int j = 0; j < 4; ++j) {
           if (act[j]) {
@@ -479,7 +519,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_r(StepArgs a, int slot,
             s[1][j] += rd * rd;
           }
         }
-        st4(r + o, rv);
+        st4s(r + o, rv);
       });
     }
   }
@@ -511,11 +551,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir_ring(StepArgs a, int next,
   if (!any) continue;
   for_rows(t, [&](int row) {
     const size_t o = size_t(row) * t.rp + c0;
-    const V4<float> pv = ld4(p + o), rv = ld4(r + o);
+    const V4<float> pv = ld4s(p + o), rv = ld4s(r + o);
     const float di = dinv[row];
     V4<float> nv;
     for (int j = 0; j < 4; ++j) nv.v[j] = act[j] ? fmaf(be[j], pv.v[j], di * rv.v[j]) : 0.0f;
-    st4(pn + o, nv);
+    st4s(pn + o, nv);
   });
   }
 }
@@ -539,15 +579,15 @@ __global__ __launch_bounds__(kBlock) void k_materialize(StepArgs a, RingArgs ra,
     for_rows(t, [&](int row) {
       const size_t o = size_t(row) * t.rp + c0;
       V4<float> acc = {};
-      if (ra.accumulate) acc = ld4(d + o);
+      if (ra.accumulate) acc = ld4s(d + o);
       for (int q = 0; q < ra.n; ++q) {
         // a direction whose 4 coefficients are zero (columns that had
         // converged) adds nothing: skip its load
         if (cf[q][0] == 0.0f && cf[q][1] == 0.0f && cf[q][2] == 0.0f && cf[q][3] == 0.0f) continue;
-        const V4<float> pv = ld4(ra.p[q] + o);
+        const V4<float> pv = ld4s(ra.p[q] + o);
         for (int j = 0; j < 4; ++j) acc.v[j] = fmaf(cf[q][j], pv.v[j], acc.v[j]);
       }
-      st4(d + o, acc);
+      st4s(d + o, acc);
     });
   }
 }
@@ -566,12 +606,12 @@ __global__ __launch_bounds__(kBlock) void k_extrap(StepArgs a, ExtrapArgs e, flo
       const size_t o = size_t(row) * t.rp + cb;
       float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
       for (int q = 0; q < e.n; ++q) {
-        const V4<float> v = ld4(e.x[q] + o);
+        const V4<float> v = ld4s(e.x[q] + o);
         for (int j = 0; j < 4; ++j) acc[j] = fmaf(e.c[q], v.v[j], acc[j]);
       }
       V4<float> yv;
       for (int j = 0; j < 4; ++j) yv.v[j] = lv[j] ? acc[j] : 0.0f;
-      st4(y + o, yv);
+      st4s(y + o, yv);
     });
   }
 }
@@ -598,12 +638,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_p(StepArgs a, int next, T*
   if (!any) continue;
   for_rows(t, [&](int row) {
     const size_t o = size_t(row) * t.rp + c0;
-    V4<T> pv = ld4(p + o);
-    const V4<T> rv = ld4(r + o);
+    V4<T> pv = ld4s(p + o);
+    const V4<T> rv = ld4s(r + o);
     const T di = dinv[row];
     for (int j = 0; j < 4; ++j)
       if (act[j]) pv.v[j] = fma(be[j], pv.v[j], di * rv.v[j]);
-    st4(p + o, pv);
+    st4s(p + o, pv);
   });
   }
 }
@@ -652,8 +692,8 @@ __global__ __launch_bounds__(kBlock) void k_init_outer(StepArgs a, const double*
         s[1][j] += rv.v[j] * rv.v[j];
       }
       const size_t o = size_t(row) * t.rp + c0;
-      st4(r64 + o, rv);
-      if (gd) st4(x0 + o, xv);
+      st4g(r64 + o, rv);
+      if (gd) st4g(x0 + o, xv);
     });
   }
   block_store<2>(t, s, a.part, blockIdx.x, ct);
@@ -708,7 +748,7 @@ __global__ __launch_bounds__(kBlock) void k_refine_start(StepArgs a, const doubl
         for (int j = 0; j < 4; ++j) kg[j] = fma(v, double(x.v[j]), kg[j]);
       });
       const size_t o = size_t(row) * t.rp + c0;
-      const V4<double> wv = ld4(w + o);
+      const V4<double> wv = ld4g(w + o);
       const float di = a.dinv32[row];
       V4<double> rv;
       V4<float> r32, pv;
@@ -720,9 +760,9 @@ __global__ __launch_bounds__(kBlock) void k_refine_start(StepArgs a, const doubl
         s[1][j] += double(r32.v[j]) * double(pv.v[j]);
         s[2][j] += double(r32.v[j]) * double(r32.v[j]);
       }
-      st4(r64 + o, rv);
-      st4(r + o, r32);
-      st4(p + o, pv);
+      st4g(r64 + o, rv);
+      st4g(r + o, r32);
+      st4g(p + o, pv);
     });
   }
   block_store<3>(t, s, a.part, blockIdx.x, ct);
@@ -775,7 +815,7 @@ __global__ __launch_bounds__(kBlock) void k_inner_init(StepArgs a, int oslot,
     for (int j = 0; j < 4; ++j) act[j] = a.cg.act_o[c0 + j];
     for_rows(t, [&](int row) {
       const size_t o = size_t(row) * t.rp + c0;
-      const V4<double> rd = ld4(r64 + o);
+      const V4<double> rd = ld4s(r64 + o);
       const float di = a.dinv32[row];
       V4<float> rv, pv;
       for (int j = 0; j < 4; ++j) {
@@ -784,8 +824,8 @@ __global__ __launch_bounds__(kBlock) void k_inner_init(StepArgs a, int oslot,
         s[0][j] += double(rv.v[j]) * double(pv.v[j]);
         s[1][j] += double(rv.v[j]) * double(rv.v[j]);
       }
-      st4(r + o, rv);
-      st4(p + o, pv);
+      st4s(r + o, rv);
+      st4s(p + o, pv);
     });
   }
   block_store<2>(t, s, a.part, blockIdx.x, ct);
@@ -855,16 +895,16 @@ __global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot,
           });
         const size_t o = size_t(row) * t.rp + c0;
         V4<float> av = {};
-        if (dacc) av = ld4(dacc + o);
+        if (dacc) av = ld4g(dacc + o);
         V4<double> xv;
         if (ubase) {
-          const V4<double> ub = ld4(ubase + o);
+          const V4<double> ub = ld4g(ubase + o);
           for (int j = 0; j < 4; ++j) xv.v[j] = ub.v[j] + double(av.v[j]);
         } else {
-          xv = ld4(x + o);
+          xv = ld4g(x + o);
         }
         V4<double> rv = {};
-        if (any) rv = ld4(r64 + o);
+        if (any) rv = ld4g(r64 + o);
         for (int j = 0; j < 4; ++j) {
           if (act[j]) {
             xv.v[j] += double(dd[j]);
@@ -873,9 +913,9 @@ __global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot,
             av.v[j] += dd[j];
           }
         }
-        st4(x + o, xv);
-        if (any && store_r) st4(r64 + o, rv);
-        if (dacc && any) st4(dacc + o, av);
+        st4g(x + o, xv);
+        if (any && store_r) st4g(r64 + o, rv);
+        if (dacc && any) st4g(dacc + o, av);
       });
     }
   }
@@ -907,10 +947,10 @@ __global__ __launch_bounds__(kBlock) void k_outer_residual(StepArgs a, int oslot
         for (int j = 0; j < 4; ++j) kd[j] = fma(v, double(xv.v[j]), kd[j]);
       });
       const size_t o = size_t(row) * t.rp + c0;
-      V4<double> rv = ld4(r64 + o);
+      V4<double> rv = ld4g(r64 + o);
       for (int j = 0; j < 4; ++j)
         if (act[j]) rv.v[j] -= kd[j];
-      st4(r64 + o, rv);
+      st4g(r64 + o, rv);
     });
   }
 }
@@ -954,7 +994,7 @@ __global__ __launch_bounds__(kBlock) void k_nodal(StepArgs a, const double* __re
   if (!(lv[0] | lv[1] | lv[2] | lv[3])) continue;
   for_rows(t, [&](int row) {
     const double* ur = u + size_t(row) * t.rp;
-    V4<double> uv = ld4(ur + c0), ov = uv;
+    V4<double> uv = ld4s(ur + c0), ov = uv;
     double S = 0.0;
     int cur = -1;
     for (int j = 0; j < 4; ++j) {
@@ -970,7 +1010,7 @@ __global__ __launch_bounds__(kBlock) void k_nodal(StepArgs a, const double* __re
       const double x = uv.v[j];
       ov.v[j] = x * exp(-cf[j] * (S - x * x));
     }
-    st4(out + size_t(row) * t.rp + c0, ov);
+    st4s(out + size_t(row) * t.rp + c0, ov);
   });
   }
 }
@@ -1009,7 +1049,7 @@ __global__ __launch_bounds__(kBlock) void k_norm_dot(StepArgs a, const double* _
             s[1][j] += vd.v[j] * av.v[j];
             s[2][j] += mv[j] * mv[j];
           }
-        if (w) st4(w + size_t(row) * t.rp + c0, av);
+        if (w) st4g(w + size_t(row) * t.rp + c0, av);
       });
     }
   }
@@ -1052,12 +1092,12 @@ __global__ __launch_bounds__(kBlock) void k_scale(StepArgs a, const double* __re
   const bool all = lv[0] && lv[1] && lv[2] && lv[3];
   for_rows(t, [&](int row) {
     const size_t o = size_t(row) * t.rp + c0;
-    const V4<double> vv = ld4(v + o);
+    const V4<double> vv = ld4s(v + o);
     // columns that are not live keep their value (read only where needed)
-    V4<double> uv = all ? vv : ld4(u + o);
+    V4<double> uv = all ? vv : ld4s(u + o);
     for (int j = 0; j < 4; ++j)
       if (lv[j]) uv.v[j] = vv.v[j] * inv[j];
-    st4(u + o, uv);
+    st4s(u + o, uv);
   });
   }
 }
