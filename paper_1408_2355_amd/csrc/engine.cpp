@@ -23,7 +23,7 @@
 namespace sp {
 
 namespace {
-enum { CF_BB, CF_RZ, CF_TOL2, CF_ALPHA, CF_BETA, CF_RRO, CF_NRM, CF_BBN, CF_COEF, CF_N };
+enum { CF_BB, CF_RZ, CF_TOL2, CF_ALPHA, CF_BETA, CF_RRO, CF_NRM, CF_BBN, CF_ISC, CF_COEF, CF_N };
 enum { CI_ACT, CI_ACTO, CI_ITERS, CI_SWEEPS, CI_SEGLO, CI_SEGLEN, CI_LIVE, CI_N };
 }  // namespace
 
@@ -184,6 +184,7 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     a.cg.rr_o = cf + CF_RRO * rp_;
     a.cg.nrm = cf + CF_NRM * rp_;
     a.cg.bb_next = cf + CF_BBN * rp_;
+    a.cg.isc = cf + CF_ISC * rp_;
     a.ct.coef = cf + CF_COEF * rp_;
     a.ct.res_ieps2 = cf + CF_N * rp_;
     a.cg.act = ci + CI_ACT * rp_;
@@ -384,6 +385,7 @@ void Solver::autotune() {
 }
 
 void Solver::push_tables() {
+  flush_scale();  // the pending factors belong to the current live masks
   lam_fresh_ = false;
   all_live_ = true;
   for (int c = 0; c < rp_; ++c)
@@ -411,8 +413,9 @@ void Solver::push_tables() {
   // the lane-split S_eps kernel needs restarts on 4-column boundaries and
   // tiles of at most 256 columns
   sp_.lanes_ok = 1;
+  sp_.wide = 0;
   for (const int4& tl : tiles) {
-    if (tl.w - tl.z > 256) sp_.lanes_ok = 0;
+    if (tl.w - tl.z > 256) sp_.lanes_ok = 0, sp_.wide = 1;
     for (int r = tl.x; r < tl.y; ++r)
       if (h_res_len_[r] > 0 && (h_res_lo_[r] % 4 != 0 || h_res_len_[r] % 4 != 0)) sp_.lanes_ok = 0;
   }
@@ -467,6 +470,7 @@ int Solver::poll(const int* dev_counter) {
 void Solver::sync() { SP_HIP(hipStreamSynchronize(s_)); }
 
 void Solver::upload_host(const double* u0, bool normalise) {
+  flush_scale();
   aw_fresh_ = false;
   SP_REQUIRE(u0 != nullptr, SP_EINVAL, "NULL u0");
   n_prev_ = 0;
@@ -484,6 +488,7 @@ void Solver::upload_host(const double* u0, bool normalise) {
 }
 
 void Solver::upload_device(const double* d_u0, bool normalise, bool check_norms) {
+  flush_scale();
   aw_fresh_ = false;
   SP_REQUIRE(d_u0 != nullptr, SP_EINVAL, "NULL u0");
   n_prev_ = 0;
@@ -502,6 +507,7 @@ void Solver::upload_device(const double* d_u0, bool normalise, bool check_norms)
 }
 
 void Solver::normalise_columns() {
+  flush_scale();
   k::norm_dot(args_, u_.p, nullptr, s_);
   k::red_norm(args_, lam_.p, s_);
   std::vector<double> nrm(rp_);
@@ -517,6 +523,7 @@ void Solver::normalise_columns() {
 }
 
 void Solver::pack_range(int c_lo, int Rq, const double* d_src) {
+  flush_scale();
   aw_fresh_ = false;
   SP_REQUIRE(c_lo >= 0 && Rq >= 0 && c_lo + Rq <= rp_, SP_EINVAL, "column range");
   n_prev_ = 0;  // the new columns have no previous increment
@@ -525,6 +532,7 @@ void Solver::pack_range(int c_lo, int Rq, const double* d_src) {
 }
 
 void Solver::unpack_range(int c_lo, int Rq, double* d_dst) {
+  flush_scale();
   SP_REQUIRE(c_lo >= 0 && Rq >= 0 && c_lo + Rq <= rp_, SP_EINVAL, "column range");
   k::unpack(args_.t, c_lo, Rq, u_.p, mesh_->perm_d.p, d_dst, s_);
 }
@@ -546,6 +554,7 @@ void Solver::normalise_range(int c_lo, int Rq) {
 }
 
 void Solver::download_host(double* u) {
+  flush_scale();
   const size_t cnt = size_t(R_) * mesh_->n;
   DevBuf<double> tmp(cnt);
   k::unpack(args_.t, 0, R_, u_.p, mesh_->perm_d.p, tmp.p, s_);
@@ -554,10 +563,12 @@ void Solver::download_host(double* u) {
 }
 
 void Solver::download_device(double* d_u) {
+  flush_scale();
   k::unpack(args_.t, 0, R_, u_.p, mesh_->perm_d.p, d_u, s_);
 }
 
 void Solver::heat_fp64() {
+  flush_scale();
   k::fill_i32(ring_.p, 0, ring_.n, s_);
   k::init_fp64(args_, u_.p, r64_.p, p64_.p, s_);
   k::red_init_fp64(args_, s_);
@@ -582,6 +593,7 @@ void Solver::heat_mixed() {
   // the norm pass that scaled u left A u (times ||v||_M) in xg_
   const bool fast = aw_fresh_ && extrap && n_prev_ >= 1;
   aw_fresh_ = false;
+  if (!fast) flush_scale();  // the other starts read u_ as it is
   if (extrap && n_prev_ >= 1) {
     // start from x0 = u + g, g the polynomial extrapolation of the last heat
     // increments d_k, d_{k-1}, ... (as many as kept and available):
@@ -632,8 +644,10 @@ void Solver::heat_mixed() {
     // with a poll after this sweep the new residual is stored only if
     // another sweep follows (most steps need one)
     const bool polled = prm_.check_every > 0 && o + 1 < prm_.max_outer;
-    k::outer_update(args_, o, x, (fast && o == 0) ? u_.p : nullptr, r64_.p, d32_.p, acc, !polled,
-                    s_);
+    const bool ubase = fast && o == 0;
+    args_.usc = ubase && u_pending_ ? args_.cg.isc : nullptr;
+    k::outer_update(args_, o, x, ubase ? u_.p : nullptr, r64_.p, d32_.p, acc, !polled, s_);
+    args_.usc = nullptr;
     k::red_outer(args_, o, s_);
     olast = o + 1;
     if (polled) {
@@ -659,6 +673,7 @@ void Solver::heat() {
 }
 
 void Solver::stage_heat() {
+  flush_scale();
   aw_fresh_ = false;
   heat();
   if (heat_x_ != u_.p)
@@ -668,22 +683,42 @@ void Solver::stage_heat() {
 
 // node step of the heat solution (the iterate the last solve left, u or xg_)
 void Solver::node_to_r() {
-  k::nodal(args_, heat_x_, r64_.p, s_);
+  if (heat_x_ == xg_.p && xg_.p) {
+    // the solve left x in xg_ (mixed precision, extrapolated start): the
+    // node step writes v into u_, whose pending state the solve has used
+    u_pending_ = false;
+    k::nodal(args_, heat_x_, u_.p, true, s_);
+    node_out_ = u_.p;
+  } else {
+    flush_scale();
+    k::nodal(args_, heat_x_, r64_.p, false, s_);
+    node_out_ = r64_.p;
+  }
   heat_x_ = u_.p;
 }
 
-void Solver::norm_dot_scale(const double* v) {
+void Solver::norm_dot_scale(const double* v, bool defer) {
   // in a step the norm pass also leaves A v in xg_ (free after the node
   // step) for the next step's refinement start
-  double* w = (xg_.p && v == r64_.p) ? xg_.p : nullptr;
+  double* w = (xg_.p && (v == r64_.p || defer)) ? xg_.p : nullptr;
   k::norm_dot(args_, v, w, s_);
   k::red_norm(args_, lam_.p, s_);
-  k::scale(args_, v, u_.p, s_);
+  if (defer)
+    u_pending_ = true;  // v is in u_; the state is v * isc
+  else
+    k::scale(args_, v, u_.p, s_);
   lam_fresh_ = all_live_;
   aw_fresh_ = w != nullptr;
 }
 
+void Solver::flush_scale() {
+  if (!u_pending_) return;
+  u_pending_ = false;
+  k::scale(args_, u_.p, u_.p, s_);
+}
+
 void Solver::stage_node() {
+  flush_scale();
   aw_fresh_ = false;
   lam_fresh_ = false;
   node_to_r();
@@ -692,8 +727,9 @@ void Solver::stage_node() {
 }
 
 void Solver::stage_norm() {
+  flush_scale();
   aw_fresh_ = false;
-  norm_dot_scale(u_.p);
+  norm_dot_scale(u_.p, false);
 }
 
 void Solver::energy() {
@@ -701,8 +737,11 @@ void Solver::energy() {
   // right after a normalisation of every column the Rayleigh quotients are
   // already in lam (see red_norm); otherwise evaluate them now
   const bool need_rq = !lam_fresh_;
-  if (need_rq) k::energy_rq(args_, u_.p, s_);
+  if (need_rq) k::energy_rq(args_, u_.p, s_);  // quotients: the pending factor cancels
+  if (sp_.wide) flush_scale();
+  args_.usc = u_pending_ ? args_.cg.isc : nullptr;
   k::energy_seps(args_, sp_, mesh_->tri.p, mesh_->tarea.p, u_.p, part_s_.p, s_);
+  args_.usc = nullptr;
   k::red_energy(args_, sp_, part_s_.p, need_rq, lam_.p, seps_.p, energy_.p, s_);
 }
 
@@ -719,6 +758,7 @@ void Solver::energy_to_host(double* lam, double* seps, double* E) {
 // (the float64 form whatever the precision setting: at this size it costs
 // nothing more); energies at the cadence come back from the device history.
 void Solver::step_small(int64_t k) {
+  flush_scale();
   const int nres = int(spec_.m.size());
   while (k > 0) {
     const int chunk = int(std::min<int64_t>(k, kSmallChunk));
@@ -773,7 +813,7 @@ void Solver::step(int64_t k) {
   for (int64_t i = 0; i < k; ++i) {
     heat();
     node_to_r();
-    norm_dot_scale(r64_.p);
+    norm_dot_scale(node_out_, node_out_ == u_.p);
     ++steps_done_;
     if (prm_.energy_every > 0 && steps_done_ % prm_.energy_every == 0) {
       if (record_history) {
@@ -819,11 +859,13 @@ void Solver::run_to_stop() {
 }
 
 void Solver::labels_device(int32_t* d_lab, int32_t* d_lab_am) {
+  flush_scale();
   if (args_.ct.nres == 0) return;
   k::labels(args_, u_.p, mesh_->perm_d.p, d_lab, d_lab_am, s_);
 }
 
 void Solver::labels_host(int32_t* lab, int32_t* lab_am) {
+  flush_scale();
   const size_t cnt = size_t(spec_.m.size()) * mesh_->n;
   DevBuf<int32_t> a(lab ? cnt : 0), b(lab_am ? cnt : 0);
   k::labels(args_, u_.p, mesh_->perm_d.p, a.p, b.p, s_);

@@ -78,7 +78,10 @@ class Solver {
   const double* d_lam() const { return lam_.p; }
   const double* d_seps() const { return seps_.p; }
   const double* d_energy() const { return energy_.p; }
-  double* d_u() { return u_.p; }
+  double* d_u() {
+    flush_scale();
+    return u_.p;
+  }
   const Tile& tile() const { return args_.t; }
   const Tile& gather_tile() const { return args_.tm; }
   double tuned_us() const { return tuned_.us; }
@@ -116,7 +119,8 @@ class Solver {
   void heat_fp64();
   void heat_mixed();
   void node_to_r();
-  void norm_dot_scale(const double* v);
+  void norm_dot_scale(const double* v, bool defer);
+  void flush_scale();
   int poll(const int* dev_counter);
   void push_tables();
   std::vector<Tile> tile_candidates() const;
@@ -154,6 +158,13 @@ class Solver {
   bool aw_fresh_ = false;      // xg_ holds A v of the norm pass that produced u (and
                                // cg.bb_next its ||M u||^2): the next solve can start
                                // without gathering u
+  // Deferred normalisation: in a mixed-precision step the node step writes
+  // v straight into u_ and the norm pass leaves 1/||v||_M in cg.isc instead
+  // of scaling; the next solve's first update and the S_eps kernels apply the
+  // factor as they read u_.  Anything else that reads u_ or changes the live
+  // masks calls flush_scale() first.
+  bool u_pending_ = false;
+  double* node_out_ = nullptr;  // where the last node step wrote (u_ or r64_)
   bool lam_fresh_ = false;  // lam holds the Rayleigh quotients of the current state
   bool all_live_ = true;    // every real column is live
   DevBuf<double> part_, part_s_;

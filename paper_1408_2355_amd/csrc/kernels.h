@@ -33,6 +33,7 @@ struct CgCols {
   double* rr_o;   // outer residual norm^2 (mixed)
   double* nrm;    // M-norms (normalisation)
   double* bb_next;  // ||M u||^2 of the state the last norm pass scaled
+  double* isc;      // 1 / nrm (1 on columns that were not live)
   int* act;       // column active in the current (inner) CG
   int* act_o;     // column active in the outer refinement (mixed)
   int* iters;     // CG iterations taken (cumulative)
@@ -57,6 +58,10 @@ struct StepArgs {
   double rtol2;        // cg_rtol^2
   double inner_rtol2;  // inner_rtol^2
   double inner_floor2 = 0.81;  // an inner solve stops at sqrt(this) x the outer target
+  // Deferred normalisation: non-null while the state vector holds v and the
+  // state is v * usc[c] per column (usc = cg.isc); the refinement update's
+  // ubase and the S_eps kernels apply it as they read.
+  const double* usc = nullptr;
   ColTab ct;
   CgCols cg;
   double* part;        // [3][nchunk][rp] partial sums
@@ -118,6 +123,8 @@ struct SepsPlan {
   int nres_p = 0;  // row stride of the partial sums
   int direct = 0;  // 0 = staged in LDS, 1 = corners read from global memory by one
                    // lane per restart, 2 = lane-split restarts (needs lanes_ok)
+  int wide = 0;      // some tile spans more than 256 columns (the direct kernel
+                     // then cannot stage its column factors)
   int lanes_ok = 0;  // every restart of every tile starts and ends on a multiple of 4
 };
 namespace k {
@@ -173,12 +180,14 @@ void outer_residual(const StepArgs& a, int o, double* r64, const float* d, hipSt
 void extrap(const StepArgs& a, const ExtrapArgs& e, float* y, hipStream_t s);
 void red_outer(const StepArgs& a, int o, hipStream_t s);
 // node step and normalisation
-void nodal(const StepArgs& a, const double* u, double* out, hipStream_t s);
+// keep: columns that are not live keep out's value (out is the state)
+void nodal(const StepArgs& a, const double* u, double* out, bool keep, hipStream_t s);
 // v.Mv, v.Av, ||Mv||^2 partials; w (nullable) receives A v
 void norm_dot(const StepArgs& a, const double* v, double* w, hipStream_t s);
 // M-norms of the live columns of the vector norm_dot saw; lam (nullable)
 // receives their Rayleigh quotients
 void red_norm(const StepArgs& a, double* lam, hipStream_t s);
+// u = v / nrm on the live columns (u may be v)
 void scale(const StepArgs& a, const double* v, double* u, hipStream_t s);
 // energies
 void energy_rq(const StepArgs& a, const double* u, hipStream_t s);

@@ -877,10 +877,12 @@ __global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot,
   if (g < t.G) {
     const int c0 = 4 * g;
     int act[4], any = 0, anylive = 0;
+    double usc[4] = {1.0, 1.0, 1.0, 1.0};
     for (int j = 0; j < 4; ++j) {
       act[j] = mask[c0 + j];
       any |= act[j];
       anylive |= a.ct.live[c0 + j];
+      if (a.usc) usc[j] = a.usc[c0 + j];
     }
     if (any || (ubase && anylive)) {
       for_rows(t, [&](int row) {
@@ -899,7 +901,7 @@ __global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot,
         V4<double> xv;
         if (ubase) {
           const V4<double> ub = ld4g(ubase + o);
-          for (int j = 0; j < 4; ++j) xv.v[j] = ub.v[j] + double(av.v[j]);
+          for (int j = 0; j < 4; ++j) xv.v[j] = ub.v[j] * usc[j] + double(av.v[j]);
         } else {
           xv = ld4g(x + o);
         }
@@ -977,7 +979,7 @@ __global__ void k_red_outer(StepArgs a, int oslot, int onext) {
 // Step 2 of Algorithm 2.2 in its practical form: S = sum_j u~_j^2 over the
 // restart's components, u^_i = u~_i exp(-(2 tau/eps^2)(S - u~_i^2)).
 __global__ __launch_bounds__(kBlock) void k_nodal(StepArgs a, const double* __restrict__ u,
-                                                  double* __restrict__ out) {
+                                                  double* __restrict__ out, int keep) {
   const Tile& t = a.t;
   for (int ct = 0; ct < t.nct; ++ct) {
   const int g = ct * t.tg + threadIdx.x % t.tg;
@@ -992,9 +994,12 @@ __global__ __launch_bounds__(kBlock) void k_nodal(StepArgs a, const double* __re
     cf[j] = a.ct.coef[c0 + j];
   }
   if (!(lv[0] | lv[1] | lv[2] | lv[3])) continue;
+  const bool mixed = keep && !(lv[0] & lv[1] & lv[2] & lv[3]);
   for_rows(t, [&](int row) {
     const double* ur = u + size_t(row) * t.rp;
     V4<double> uv = ld4s(ur + c0), ov = uv;
+    // columns that are not live keep the state's value
+    if (mixed) ov = ld4s(out + size_t(row) * t.rp + c0);
     double S = 0.0;
     int cur = -1;
     for (int j = 0; j < 4; ++j) {
@@ -1069,13 +1074,13 @@ __global__ void k_red_norm(StepArgs a, double* __restrict__ lam) {
   const double sm = red_sum(a.part + part_off(t, 2), lv ? t.nchunk : 0, t.rp, c);
   if (!red_lead() || c >= t.rp) return;
   a.cg.nrm[c] = lv ? sqrt(s) : 1.0;
+  a.cg.isc[c] = lv ? 1.0 / sqrt(s) : 1.0;
   if (lv && lam) lam[c] = sa / s;
   // ||M u||^2 of the scaled state u = v / ||v||_M (the next solve's ||b||^2)
   if (lv) a.cg.bb_next[c] = sm / s;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scale(StepArgs a, const double* __restrict__ v,
-                                                  double* __restrict__ u) {
+__global__ __launch_bounds__(kBlock) void k_scale(StepArgs a, const double* v, double* u) {
   const Tile& t = a.t;
   for (int ct = 0; ct < t.nct; ++ct) {
   const int g = ct * t.tg + threadIdx.x % t.tg;
@@ -1199,8 +1204,12 @@ struct QuarticPairs {
 // u1, u2 (rows of global memory).  With 16-byte aligned starts the values
 // are read two at a time (half the load instructions; each lane's loads walk
 // one cache line).
+// Sum over the triangle's component pairs for one restart of m components
+// (corner rows u0, u1, u2); w (Scaled) holds per-component factors the
+// values are multiplied by as they are read (deferred normalisation).
+template <bool Scaled, typename WP = const double*>
 __device__ __forceinline__ double quartic_pairs(const double* u0, const double* u1,
-                                                const double* u2, int m) {
+                                                const double* u2, WP w, int m) {
   QuarticPairs qp;
   int i = 0;
   if (((reinterpret_cast<size_t>(u0) | reinterpret_cast<size_t>(u1) |
@@ -1217,19 +1226,36 @@ __device__ __forceinline__ double quartic_pairs(const double* u0, const double* 
       }
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
-        qp.add(a0[h].x, a1[h].x, a2[h].x);
-        qp.add(a0[h].y, a1[h].y, a2[h].y);
+        if constexpr (Scaled) {
+          const double wx = w[i + 2 * h], wy = w[i + 2 * h + 1];
+          qp.add(a0[h].x * wx, a1[h].x * wx, a2[h].x * wx);
+          qp.add(a0[h].y * wy, a1[h].y * wy, a2[h].y * wy);
+        } else {
+          qp.add(a0[h].x, a1[h].x, a2[h].x);
+          qp.add(a0[h].y, a1[h].y, a2[h].y);
+        }
       }
     }
     for (; i + 1 < m; i += 2) {
       const double2 a0 = *reinterpret_cast<const double2*>(u0 + i);
       const double2 a1 = *reinterpret_cast<const double2*>(u1 + i);
       const double2 a2 = *reinterpret_cast<const double2*>(u2 + i);
-      qp.add(a0.x, a1.x, a2.x);
-      qp.add(a0.y, a1.y, a2.y);
+      if constexpr (Scaled) {
+        const double wx = w[i], wy = w[i + 1];
+        qp.add(a0.x * wx, a1.x * wx, a2.x * wx);
+        qp.add(a0.y * wy, a1.y * wy, a2.y * wy);
+      } else {
+        qp.add(a0.x, a1.x, a2.x);
+        qp.add(a0.y, a1.y, a2.y);
+      }
     }
   }
-  for (; i < m; ++i) qp.add(u0[i], u1[i], u2[i]);
+  for (; i < m; ++i) {
+    if constexpr (Scaled)
+      qp.add(u0[i] * w[i], u1[i] * w[i], u2[i] * w[i]);
+    else
+      qp.add(u0[i], u1[i], u2[i]);
+  }
   return qp.acc;
 }
 
@@ -1295,8 +1321,9 @@ __global__ __launch_bounds__(kBlock) void k_energy_seps(StepArgs a, SepsPlan sp,
             const int i = i0 + 2 * h, len = s_len[row3];
             double vx = 0.0, vy = 0.0;
             if (off >= 0) {
-              if (i < len) vx = u[off + i];
-              if (i + 1 < len) vy = u[off + i + 1];
+              const int cl = s_lo[row3 % nr] + i;
+              if (i < len) vx = u[off + i] * (a.usc ? a.usc[cl] : 1.0);
+              if (i + 1 < len) vy = u[off + i + 1] * (a.usc ? a.usc[cl + 1] : 1.0);
             }
             double* dst = sh + row3 * kSepsPad + 2 * h;
             dst[0] = vx;
@@ -1330,16 +1357,23 @@ __global__ __launch_bounds__(kBlock) void k_energy_seps(StepArgs a, SepsPlan sp,
 // restart lanes (nrp = restarts of the tile rounded up to a power of two);
 // each lane reads its restart's m corner values straight from global memory
 // (lanes of one triangle read adjacent segments of the same rows).
+template <bool Scaled>
 __global__ __launch_bounds__(kBlock) void k_energy_seps_direct(StepArgs a, SepsPlan sp,
                                                                const int* __restrict__ tri,
                                                                const double* __restrict__ tarea,
                                                                const double* __restrict__ u,
                                                                double* __restrict__ part_s) {
   __shared__ double red[kBlock];
+  __shared__ double s_w[kSepsCols];  // the tile's column factors (Scaled)
   const int rp = a.t.rp;
   const int tid = threadIdx.x;
   for_seps_chunks(sp, [&](int tile, int cb, int ce, int stride) {
     const int4 tl = sp.tiles[tile];
+    if (Scaled) {
+      // the host flushes the factors instead when a tile is wider
+      for (int c = tid; c < tl.w - tl.z; c += kBlock) s_w[c] = a.usc[tl.z + c];
+      __syncthreads();
+    }
     const int r0 = tl.x, nr = tl.y - tl.x;
     int nrp = 1;
     while (nrp < nr) nrp <<= 1;
@@ -1351,15 +1385,18 @@ __global__ __launch_bounds__(kBlock) void k_energy_seps_direct(StepArgs a, SepsP
       m = a.ct.res_len[r0 + rr];
     }
     double acc = 0.0;
-    if (m > 0)
+    if (m > 0) {
+      typedef const __attribute__((address_space(3))) double* LdsPtr;
+      const LdsPtr w = (LdsPtr)(s_w + (Scaled ? lo - tl.z : 0));
       for (int chunk = cb; chunk < ce; chunk += stride) {
         const int t_beg = chunk * sp.tchunk, t_end = min(t_beg + sp.tchunk, sp.nt);
         for (int t = t_beg + tb; t < t_end; t += TB)
-          acc += quartic_pairs(u + size_t(tri[3 * t + 0]) * rp + lo,
-                               u + size_t(tri[3 * t + 1]) * rp + lo,
-                               u + size_t(tri[3 * t + 2]) * rp + lo, m) *
+          acc += quartic_pairs<Scaled>(u + size_t(tri[3 * t + 0]) * rp + lo,
+                                       u + size_t(tri[3 * t + 1]) * rp + lo,
+                                       u + size_t(tri[3 * t + 2]) * rp + lo, w, m) *
                  tarea[t] * (1.0 / 180.0);
       }
+    }
     red[tid] = acc;
     for (int st = TB >> 1; st >= 1; st >>= 1) {
       __syncthreads();
@@ -1426,7 +1463,15 @@ __global__ __launch_bounds__(kBlock) void k_energy_seps_lanes(StepArgs a, SepsPl
           const double* p0 = u + size_t(tri[3 * t + 0]) * rp + c;
           const double* p1 = u + size_t(tri[3 * t + 1]) * rp + c;
           const double* p2 = u + size_t(tri[3 * t + 2]) * rp + c;
-          const V4<double> x0 = ld4(p0), x1 = ld4(p1), x2 = ld4(p2);
+          V4<double> x0 = ld4(p0), x1 = ld4(p1), x2 = ld4(p2);
+          if (a.usc) {
+            const V4<double> w = ld4(a.usc + c);
+            for (int j = 0; j < 4; ++j) {
+              x0.v[j] *= w.v[j];
+              x1.v[j] *= w.v[j];
+              x2.v[j] *= w.v[j];
+            }
+          }
           QuarticPairs qp;
           for (int j = 0; j < 4; ++j) qp.add(x0.v[j], x1.v[j], x2.v[j]);
           loc = qp.acc;
@@ -1797,9 +1842,9 @@ __global__ __launch_bounds__(kSmallBlock) void k_small_steps(StepArgs a, SmallAr
         const int lo = a.ct.res_lo[rr], m = a.ct.res_len[rr];
         if (m > 0)
           for (int t = tl; t < sa.nt; t += TL)
-            acc[0] += quartic_pairs(u + size_t(sa.tri[3 * t + 0]) * rp + lo,
-                                    u + size_t(sa.tri[3 * t + 1]) * rp + lo,
-                                    u + size_t(sa.tri[3 * t + 2]) * rp + lo, m) *
+            acc[0] += quartic_pairs<false>(u + size_t(sa.tri[3 * t + 0]) * rp + lo,
+                                           u + size_t(sa.tri[3 * t + 1]) * rp + lo,
+                                           u + size_t(sa.tri[3 * t + 2]) * rp + lo, nullptr, m) *
                       sa.tarea[t] * (1.0 / 180.0);
       }
       // per-restart sums: small_sum with np2 as the group width (slot 0)
@@ -2069,8 +2114,8 @@ void red_outer(const StepArgs& a, int o, hipStream_t s) {
   SP_LAUNCH_CHECK();
 }
 
-void nodal(const StepArgs& a, const double* u, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_nodal, dim3(a.t.nblk), dim3(kBlock), 0, s, a, u, out);
+void nodal(const StepArgs& a, const double* u, double* out, bool keep, hipStream_t s) {
+  hipLaunchKernelGGL(k_nodal, dim3(a.t.nblk), dim3(kBlock), 0, s, a, u, out, int(keep));
   SP_LAUNCH_CHECK();
 }
 
@@ -2100,9 +2145,12 @@ void energy_seps(const StepArgs& a, const SepsPlan& sp, const int32_t* tri, cons
   if (sp.direct == 2 && sp.lanes_ok)
     hipLaunchKernelGGL(k_energy_seps_lanes, dim3(8 * sp.nper), dim3(kBlock), 0, s, a, sp, tri,
                        tarea, u, part_s);
+  else if (sp.direct && a.usc)
+    hipLaunchKernelGGL(k_energy_seps_direct<true>, dim3(8 * sp.nper), dim3(kBlock), 0, s, a, sp,
+                       tri, tarea, u, part_s);
   else if (sp.direct)
-    hipLaunchKernelGGL(k_energy_seps_direct, dim3(8 * sp.nper), dim3(kBlock), 0, s, a, sp, tri,
-                       tarea, u, part_s);
+    hipLaunchKernelGGL(k_energy_seps_direct<false>, dim3(8 * sp.nper), dim3(kBlock), 0, s, a, sp,
+                       tri, tarea, u, part_s);
   else
     hipLaunchKernelGGL(k_energy_seps, dim3(8 * sp.nper), dim3(kBlock), 0, s, a, sp, tri, tarea, u,
                        part_s);
