@@ -5,5 +5,6 @@ holds none of the partition method's arithmetic, so it can feed both sides of
 a parity comparison without coupling them.
 """
 from .meshes import (icosahedron, icosphere, torus, ellipsoid, surface_mesh,  # noqa: F401
-                     MESH_KINDS)
-from .states import uniform_u0, one_hot_u0, batch_u0, poisson_trace  # noqa: F401
+                     MESH_KINDS, project_sphere, project_ellipsoid)
+from .states import (uniform_u0, one_hot_u0, batch_u0, poisson_trace,  # noqa: F401
+                     eps_study_levels)

@@ -21,7 +21,7 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = ["icosahedron", "icosphere", "torus", "ellipsoid", "surface_mesh",
-           "MESH_KINDS"]
+           "MESH_KINDS", "project_sphere", "project_ellipsoid"]
 
 
 def icosahedron():
@@ -120,3 +120,19 @@ def surface_mesh(kind: str):
     if kind.startswith("ellipsoid"):
         return ellipsoid(int(kind[9:]))
     raise ValueError(f"unknown mesh kind {kind!r}")
+
+
+def project_sphere(x):
+    """Points x [k, 3] moved radially onto the unit sphere (how the icosphere
+    places its edge midpoints; the surface map for refining sphere meshes)."""
+    x = np.asarray(x, dtype=np.float64)
+    return x / np.linalg.norm(x, axis=1, keepdims=True)
+
+
+def project_ellipsoid(x, axes=(1.0, 0.8, 0.6)):
+    """Points x [k, 3] moved along the ray from the centre onto the ellipsoid
+    with semi-axes ``axes`` (the lift the ellipsoid meshes are built with)."""
+    x = np.asarray(x, dtype=np.float64)
+    a = np.asarray(axes, dtype=np.float64)[None, :]
+    return x / np.sqrt(((x / a) ** 2).sum(axis=1, keepdims=True))
+

@@ -11,7 +11,7 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["uniform_u0", "one_hot_u0", "batch_u0", "poisson_trace"]
+__all__ = ["uniform_u0", "one_hot_u0", "batch_u0", "poisson_trace", "eps_study_levels"]
 
 
 def _rng(seed: int):
@@ -69,3 +69,20 @@ def poisson_trace(seed: int, n_requests: int, rate: float, kinds, m_range,
             seed=int(g.integers(0, 2**31 - 1)),
         ))
     return out
+
+
+def eps_study_levels(n_levels: int, eps0: float = 0.5, tau0: float = 8e-4):
+    """Level schedule of the convergence study in eps (Section 3.1, table
+    tab:u-eps): eps halves from level to level (the table's rows), tau shrinks
+    by 1/sqrt(2) per level, and the mesh is refined (4-fold midpoint split =
+    two of the paper's bisections) before every second level (levels 2, 4,
+    ...), so h shrinks by 1/sqrt(2) per level on average as with one bisection
+    per level.  Returns [(eps, tau, refine)] for levels 0 .. n_levels - 1."""
+    out = []
+    eps, tau = float(eps0), float(tau0)
+    for lvl in range(n_levels):
+        out.append((eps, tau, lvl >= 2 and lvl % 2 == 0))
+        eps *= 0.5
+        tau /= 2.0 ** 0.5
+    return out
+
