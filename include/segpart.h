@@ -276,6 +276,75 @@ int sp_server_stats(sp_server* srv, double* p50_s, double* p99_s, double* cdof_p
 /* Stops the scheduler (abandoning unfinished requests) and frees everything. */
 void sp_server_destroy(sp_server* srv);
 
+/* ------------------------------------------------------------ continuation --
+ * The convergence study in eps of Section 3.1 (table tab:u-eps): a minimiser
+ * is computed on a coarse mesh at a large eps; then, level after level, the
+ * mesh is refined, tau and eps shrink, and the previous minimiser is the new
+ * initial condition, each level running until the stopping rule of Section
+ * 2.2 holds. */
+
+/* Moves the n points xyz [n][3] (host, in place) onto the surface. */
+typedef void (*sp_project_fn)(double* xyz, int64_t n, void* ctx);
+
+/* Refinement of Section 3.1: every triangle split into four at its edge
+ * midpoints (two of the paper's bisections, which halve h).  The fine mesh
+ * keeps the coarse vertices 0..n-1 (caller numbering) and appends one vertex
+ * per edge: vertex n + j is the midpoint of the j-th edge (a, b), a < b, in
+ * lexicographic order of (a, b), moved onto the surface by project (NULL:
+ * left at the midpoint; project is called once, on all new vertices, before
+ * this returns).  Coarse triangle t = (a, b, c) with midpoints ab, bc, ca
+ * becomes fine triangles 4t..4t+3 = (a, ab, ca), (b, bc, ab), (c, ca, bc),
+ * (ab, bc, ca).  *fine is a new mesh (sp_mesh_destroy) that remembers its
+ * parents.  Errors as sp_mesh_create (the projected points are validated). */
+int sp_mesh_refine(const sp_mesh* coarse, sp_project_fn project, void* ctx, sp_mesh** fine);
+/* Parents of a refined mesh's new vertices: parents [n_fine - n_coarse][2]
+ * (host), the edge (a, b) of each new vertex; *n_coarse (nullable) receives
+ * the coarse vertex count.  SP_EINVAL if the mesh was not made by
+ * sp_mesh_refine. */
+int sp_mesh_parents(const sp_mesh* fine, int32_t* parents, int64_t* n_coarse);
+/* The coarse state carried to a refined mesh as the P1 function it is: a
+ * coarse vertex keeps its value, new vertex n + j takes the mean of its two
+ * parents' values (the coarse function at the edge midpoint).  u_coarse
+ * [n_cols][n_coarse] -> u_fine [n_cols][n_fine], host arrays; the work runs on
+ * the GPU. */
+int sp_prolong(const sp_mesh* fine, int32_t n_cols, const double* u_coarse, double* u_fine);
+
+typedef struct {
+  double eps;       /* this level's eps                                         */
+  double tau;       /* this level's time step; the energy is checked every
+                       M_tau = round(0.1 / tau) steps (Section 2.2)             */
+  int32_t refine;   /* 1: refine the mesh (sp_mesh_refine) before this level and
+                       carry the state over (sp_prolong); must be 0 on level 0 */
+  int32_t reserved;
+} sp_level;
+
+typedef struct {
+  int64_t n_vert;   /* vertices of the level's mesh                             */
+  int64_t steps;    /* time steps the level took                                */
+  double energy;    /* E = sum lambda + S_eps at the level's final state        */
+  double s_eps;     /* S_eps of equation (Seps-u) there                         */
+  double seconds;   /* wall time of the level (refinement included)             */
+  int32_t converged;  /* 1 if every linear solve of the level met its tolerance */
+  int32_t reserved;
+} sp_level_result;
+
+/* Level loop for one restart of m components.  prm supplies the precision,
+ * the CG settings, stop_tol and max_steps; its tau and energy_every are
+ * replaced per level (tau = levels[l].tau, energy_every = M_tau); with
+ * prm->n_steps > 0 every level runs exactly that many steps instead of the
+ * stopping rule.  u0 [m][n_vert of mesh0] (host, normalised on upload like
+ * sp_solve's).  Outputs (host): results [n_levels]; lambda [n_levels][m]
+ * (nullable); *final_mesh (nullable) receives the last level's mesh as a new
+ * handle when any level refined, else NULL; u_final [m][n_vert of the last
+ * level] (nullable; the caller sizes it, e.g. n_vert grows to
+ * n + (3/2) n_tri per refinement of a closed surface).  project as in
+ * sp_mesh_refine.  Returns SP_ENOCONV (after writing outputs) if some linear
+ * solve hit its cap. */
+int sp_continue(const sp_mesh* mesh0, const sp_params* prm, int32_t m, const double* u0,
+                int32_t n_levels, const sp_level* levels, sp_project_fn project, void* ctx,
+                sp_level_result* results, double* lambda, sp_mesh** final_mesh,
+                double* u_final);
+
 #ifdef __cplusplus
 }
 #endif

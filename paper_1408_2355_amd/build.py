@@ -22,7 +22,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsegpart.so")
 
 ARCH = "gfx950"
-SOURCES = ["kernels.hip", "mesh.cpp", "engine.cpp", "autotune.cpp", "server.cpp", "capi.cpp"]
+SOURCES = ["kernels.hip", "prolong.hip", "mesh.cpp", "engine.cpp", "autotune.cpp", "server.cpp",
+           "continuation.cpp", "capi.cpp"]
 
 
 def hipcc():

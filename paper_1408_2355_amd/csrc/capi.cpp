@@ -8,6 +8,7 @@
 #include <new>
 #include <string>
 
+#include "continuation.h"
 #include "engine.h"
 #include "server.h"
 
@@ -413,3 +414,60 @@ int sp_server_stats(sp_server* srv, double* p50_s, double* p99_s, double* cdof_p
 void sp_server_destroy(sp_server* srv) { delete srv; }
 
 }  // extern "C"
+
+int sp_mesh_refine(const sp_mesh* coarse, sp_project_fn project, void* ctx, sp_mesh** fine) {
+  return guard([&] {
+    SP_REQUIRE(fine != nullptr, SP_EINVAL, "NULL fine");
+    *fine = nullptr;
+    SP_REQUIRE(coarse && coarse->m, SP_EINVAL, "NULL mesh");
+    std::unique_ptr<sp_mesh> h(new sp_mesh());
+    h->m.reset(sp::mesh_refine(*coarse->m, project, ctx));
+    *fine = h.release();
+    return SP_OK;
+  });
+}
+
+int sp_mesh_parents(const sp_mesh* fine, int32_t* parents, int64_t* n_coarse) {
+  return guard([&] {
+    SP_REQUIRE(fine && fine->m, SP_EINVAL, "NULL mesh");
+    SP_REQUIRE(fine->m->n_coarse > 0, SP_EINVAL, "mesh was not made by sp_mesh_refine");
+    if (parents) std::memcpy(parents, fine->m->parents.data(), fine->m->parents.size() * sizeof(int32_t));
+    if (n_coarse) *n_coarse = fine->m->n_coarse;
+    return SP_OK;
+  });
+}
+
+int sp_prolong(const sp_mesh* fine, int32_t n_cols, const double* u_coarse, double* u_fine) {
+  return guard([&] {
+    SP_REQUIRE(fine && fine->m, SP_EINVAL, "NULL mesh");
+    SP_REQUIRE(fine->m->n_coarse > 0, SP_EINVAL, "mesh was not made by sp_mesh_refine");
+    SP_REQUIRE(n_cols >= 0, SP_EINVAL, "n_cols must be >= 0");
+    SP_REQUIRE(n_cols == 0 || (u_coarse && u_fine), SP_EINVAL, "NULL state");
+    const sp::Mesh& F = *fine->m;
+    if (n_cols == 0) return SP_OK;
+    sp::DevBuf<double> c(size_t(n_cols) * F.n_coarse), f(size_t(n_cols) * F.n);
+    SP_HIP(hipMemcpy(c.p, u_coarse, c.bytes(), hipMemcpyHostToDevice));
+    sp::k::prolong(F, n_cols, c.p, f.p, nullptr);
+    SP_HIP(hipMemcpy(u_fine, f.p, f.bytes(), hipMemcpyDeviceToHost));
+    return SP_OK;
+  });
+}
+
+int sp_continue(const sp_mesh* mesh0, const sp_params* prm, int32_t m, const double* u0,
+                int32_t n_levels, const sp_level* levels, sp_project_fn project, void* ctx,
+                sp_level_result* results, double* lambda, sp_mesh** final_mesh,
+                double* u_final) {
+  return guard([&] {
+    if (final_mesh) *final_mesh = nullptr;
+    SP_REQUIRE(mesh0 && mesh0->m && prm, SP_EINVAL, "NULL mesh or params");
+    sp::ContinuationOut o = sp::run_continuation(mesh0->m.get(), *prm, m, u0, n_levels, levels,
+                                                 project, ctx, results, lambda, u_final);
+    if (final_mesh && o.mesh) {
+      std::unique_ptr<sp_mesh> h(new sp_mesh());
+      h->m = std::move(o.mesh);
+      *final_mesh = h.release();
+    }
+    return o.converged ? SP_OK : SP_ENOCONV;
+  });
+}
+

@@ -111,6 +111,13 @@ struct Mesh {
   DevBuf<int32_t> tri;         // [nt][3] (new numbering, sorted for locality)
   DevBuf<double> tarea;        // [nt]
   DevBuf<int32_t> perm_d, iperm_d;
+  std::vector<double> h_xyz;   // [n][3] caller numbering (refinement)
+  std::vector<int32_t> h_tri;  // [nt][3] caller numbering
+  // made by refinement: new vertex n_coarse + j is the midpoint of edge
+  // (parents[2j], parents[2j+1]) of the coarse mesh (caller numbering)
+  int64_t n_coarse = 0;
+  std::vector<int32_t> parents;
+  DevBuf<int32_t> parents_d;
   int device = 0;
   std::mutex mu;
   std::vector<std::unique_ptr<TauMats>> kcache;
@@ -118,6 +125,10 @@ struct Mesh {
 };
 
 Mesh* mesh_create(int64_t n, const double* xyz, int64_t nt, const int32_t* tri);
+// 4-fold midpoint refinement (continuation.cpp); project (nullable) moves the
+// new vertices onto the surface.
+typedef void (*ProjectFn)(double* xyz, int64_t n, void* ctx);
+Mesh* mesh_refine(const Mesh& coarse, ProjectFn project, void* ctx);
 
 // Kernel launchers (kernels.hip).
 struct ColTables;  // forward
@@ -128,6 +139,8 @@ void tau_mats(const Mesh& m, TauMats& t, hipStream_t s);
 void fill_i32(int32_t* p, int32_t v, size_t n, hipStream_t s);
 void fill_f64(double* p, double v, size_t n, hipStream_t s);
 void fill_f32(float* p, float v, size_t n, hipStream_t s);
+// u_fine [cols][fine.n] from u_coarse [cols][fine.n_coarse] (prolong.hip)
+void prolong(const Mesh& fine, int cols, const double* u_coarse, double* u_fine, hipStream_t s);
 }  // namespace k
 
 }  // namespace sp

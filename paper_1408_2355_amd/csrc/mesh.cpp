@@ -146,6 +146,8 @@ Mesh* mesh_create(int64_t n, const double* xyz, int64_t nt, const int32_t* tri) 
   M->n = n;
   M->nt = nt;
   M->area = area;
+  M->h_xyz.assign(xyz, xyz + 3 * n);
+  M->h_tri.assign(tri, tri + 3 * nt);
   M->perm = rcm_order(n, ptr, adj);
   M->iperm.assign(n, 0);
   for (int64_t i = 0; i < n; ++i) M->iperm[M->perm[i]] = int32_t(i);

@@ -52,6 +52,23 @@ class sp_stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class sp_level(C.Structure):
+    _fields_ = [("eps", C.c_double), ("tau", C.c_double), ("refine", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class sp_level_result(C.Structure):
+    _fields_ = [("n_vert", C.c_int64), ("steps", C.c_int64), ("energy", C.c_double),
+                ("s_eps", C.c_double), ("seconds", C.c_double), ("converged", C.c_int32),
+                ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+# void (*)(double* xyz, int64_t n, void* ctx)
+PROJECT_FN = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.c_int64, C.c_void_p)
+
 _lib = None
 
 P = C.c_void_p
@@ -92,6 +109,12 @@ _SIGS = {
     "sp_server_fetch": (C.c_int, [P, C.c_int64, D, I32, D, D, D, D]),
     "sp_server_stats": (C.c_int, [P, D, D, D, I64]),
     "sp_server_destroy": (None, [P]),
+    "sp_mesh_refine": (C.c_int, [P, PROJECT_FN, P, PP]),
+    "sp_mesh_parents": (C.c_int, [P, I32, I64]),
+    "sp_prolong": (C.c_int, [P, C.c_int32, D, D]),
+    "sp_continue": (C.c_int, [P, C.POINTER(sp_params), C.c_int32, D, C.c_int32,
+                              C.POINTER(sp_level), PROJECT_FN, P, C.POINTER(sp_level_result),
+                              D, PP, D]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -227,12 +250,85 @@ def sp_solve_async(mesh_h, prm, m, eps, d_u0, d_u_out=None, d_labels=None,
                                 C.c_void_p(stream.cuda_stream)))
 
 
+def _project_cb(project):
+    """C callback around project(points [k, 3]) -> projected points [k, 3]."""
+    if project is None:
+        return PROJECT_FN()
+
+    def cb(ptr, n, _ctx):
+        a = np.ctypeslib.as_array(ptr, shape=(int(n) * 3,)).reshape(int(n), 3)
+        a[:] = project(a.copy())
+
+    return PROJECT_FN(cb)
+
+
+def sp_mesh_refine(h, project=None):
+    cb = _project_cb(project)
+    out = C.c_void_p()
+    _check(lib().sp_mesh_refine(h, cb, None, C.byref(out)))
+    return out
+
+
+def sp_mesh_parents(h):
+    n, _, _, _ = sp_mesh_info(h)
+    nc = C.c_int64()
+    _check(lib().sp_mesh_parents(h, None, C.byref(nc)))
+    par = np.empty((n - nc.value, 2), np.int32)
+    _check(lib().sp_mesh_parents(h, _ip(par), None))
+    return par, nc.value
+
+
+def sp_prolong(fine_h, u_coarse):
+    u = _f64(np.atleast_2d(u_coarse))
+    n, _, _, _ = sp_mesh_info(fine_h)
+    out = np.empty((u.shape[0], n))
+    _check(lib().sp_prolong(fine_h, u.shape[0], _dp(u), _dp(out)))
+    return out
+
+
+def sp_continue(mesh_h, prm, m, u0, levels, project=None, want_u=True):
+    """levels: sequence of (eps, tau, refine).  Returns (status, results
+    [list of dicts], lambda [n_levels, m], final mesh handle or None, u_final)."""
+    n0, t0, _, _ = sp_mesh_info(mesh_h)
+    u0 = _f64(u0)
+    if u0.shape != (m, n0):
+        raise ValueError(f"u0 must have shape ({m}, {n0}), got {u0.shape}")
+    lv = (sp_level * len(levels))()
+    n, t = n0, t0
+    for i, (eps, tau, ref) in enumerate(levels):
+        lv[i].eps, lv[i].tau, lv[i].refine = float(eps), float(tau), int(bool(ref))
+        if ref:  # closed surface: one new vertex per edge, 3 t / 2 edges
+            n, t = n + 3 * t // 2, 4 * t
+    res = (sp_level_result * len(levels))()
+    lam = np.empty((len(levels), m))
+    u = np.empty((m, n)) if want_u else None
+    fin = C.c_void_p()
+    cb = _project_cb(project)
+    rc = _check(lib().sp_continue(mesh_h, C.byref(prm), m, _dp(u0), len(levels), lv, cb, None,
+                                  res, _dp(lam), C.byref(fin), _dp(u)),
+                allow=(SP_ENOCONV,))
+    return rc, [r.as_dict() for r in res], lam, (fin if fin.value else None), u
+
+
 class Mesh:
     """Owner of an sp_mesh handle."""
 
-    def __init__(self, xyz, tri):
-        self.h = sp_mesh_create(xyz, tri)
+    def __init__(self, xyz=None, tri=None, handle=None):
+        self.h = sp_mesh_create(xyz, tri) if handle is None else handle
         self.n_vert, self.n_tri, self.nnz, self.area = sp_mesh_info(self.h)
+
+    def refine(self, project=None):
+        """4-fold midpoint refinement; project(points [k, 3]) moves the new
+        vertices onto the surface."""
+        return Mesh(handle=sp_mesh_refine(self.h, project))
+
+    def parents(self):
+        """(parents [n_new, 2], n_coarse) of a refined mesh."""
+        return sp_mesh_parents(self.h)
+
+    def prolong(self, u_coarse):
+        """u_coarse [cols, n_coarse] -> [cols, n_vert] on this refined mesh."""
+        return sp_prolong(self.h, u_coarse)
 
     def export(self, which):
         """(row_ptr, col, val) CSR of M (SP_MAT_M) or A (SP_MAT_A)."""
@@ -248,6 +344,12 @@ class Mesh:
 
 def solve(mesh, prm, m, eps, u0, **kw):
     return sp_solve(mesh.h, prm, m, eps, u0, **kw)
+
+
+def continue_levels(mesh, prm, m, u0, levels, project=None, want_u=True):
+    """sp_continue on a Mesh; the final mesh comes back as a Mesh (or None)."""
+    rc, res, lam, fin, u = sp_continue(mesh.h, prm, m, u0, levels, project, want_u)
+    return rc, res, lam, (Mesh(handle=fin) if fin is not None else None), u
 
 
 class State:
