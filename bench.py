@@ -177,6 +177,59 @@ def serve(args, sp):
     print(json.dumps(result), flush=True)
 
 
+def eps_study(args, sp):
+    """The convergence study in eps (Section 3.1): sp_continue over the
+    schedule of workloads.eps_study_levels, m = 3, random U[0,1) start (seed
+    7), mixed precision, stopping rule |dE| < 1e-6 every M_tau steps."""
+    from workloads import eps_study_levels, icosphere, project_sphere, uniform_u0
+    levels = eps_study_levels(args.eps_study)
+    v, f = icosphere(args.eps_study_mesh)
+    m = 3
+    u0 = uniform_u0(7, 1, m, v.shape[0])
+    mesh = sp.Mesh(v, f)
+    prm = sp.params(levels[0][1], n_steps=0, stop_tol=1e-6, max_steps=200000,
+                    precision="mixed", cg_rtol=1e-10, inner_rtol=args.inner_rtol,
+                    check_every=args.check_every, extrapolate=args.extrapolate)
+    log(f"[bench] eps study: {len(levels)} levels from icosphere level {args.eps_study_mesh} "
+        f"({v.shape[0]} vertices)")
+    t0 = time.perf_counter()
+    rc, res, lam, fin, _ = sp.continue_levels(mesh, prm, m, u0, levels, project_sphere,
+                                              want_u=False)
+    wall = time.perf_counter() - t0
+    table = np.loadtxt(os.path.join(ROOT, "tests", "golden", "tab_u_eps.txt"), ndmin=2)
+    rows, cdof = [], 0.0
+    for i, ((eps, tau, ref), r) in enumerate(zip(levels, res)):
+        cdof += float(r["steps"]) * r["n_vert"] * m
+        row = dict(eps=eps, tau=tau, n_vert=r["n_vert"], steps=r["steps"],
+                   energy=r["energy"], s_eps=r["s_eps"], seconds=round(r["seconds"], 3),
+                   lam=[float(x) for x in lam[i]])
+        if i < table.shape[0] and abs(table[i, 0] - eps) < 1e-5 * eps:  # table rounds eps
+            row["paper_energy"], row["paper_s_eps"] = float(table[i, 1]), float(table[i, 4])
+        rows.append(row)
+        log(f"[bench]   eps {eps:.5g} tau {tau:.4g} n {r['n_vert']}: {r['steps']} steps, "
+            f"E {r['energy']:.4f} S {r['s_eps']:.4f} ({r['seconds']:.1f} s)"
+            + (f"  paper E {row['paper_energy']:.4f} S {row['paper_s_eps']:.4f}"
+               if "paper_energy" in row else ""))
+    for i in range(1, len(rows)):  # eoc of the energy error against 45/4 and of S_eps
+        e0, e1 = 11.25 - rows[i - 1]["energy"], 11.25 - rows[i]["energy"]
+        if e0 > 0 and e1 > 0:
+            rows[i]["eoc_energy"] = float(np.log(e1 / e0) / np.log(0.5))
+        rows[i]["eoc_s_eps"] = float(np.log(rows[i]["s_eps"] / rows[i - 1]["s_eps"]) / np.log(0.5))
+    if fin is not None:
+        fin.close()
+    mesh.close()
+    print(json.dumps({
+        "metric": "eps study (continuation to the stopping rule): component-DOF updates/s",
+        "value": cdof / wall, "unit": "cdof/s", "n_gpus": 1, "steps": int(sum(r["steps"] for r in res)),
+        "warmup": 0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"eps study: unit sphere from icosahedral level {args.eps_study_mesh}, "
+                               f"m 3, {len(levels)} levels (eps 0.5 halving, tau 8e-4 / sqrt(2) per "
+                               "level, 4-fold refinement before levels 2, 4, ...), stop |dE| < 1e-6 "
+                               "every M_tau = 0.1 / tau steps, mixed precision"},
+        "wall_s": wall, "status": int(rc), "levels": rows}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,6 +254,12 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-rate", type=float, default=50.0, help="arrivals per second")
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--eps-study", type=int, default=0, metavar="LEVELS",
+                    help="continuation benchmark instead: the convergence study in eps of "
+                         "Section 3.1 (table tab:u-eps) for LEVELS levels from icosphere level "
+                         "--eps-study-mesh, m = 3, each level to the stopping rule; prints the "
+                         "per-level energies beside the paper's and the whole study's throughput")
+    ap.add_argument("--eps-study-mesh", type=int, default=5)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -227,6 +286,8 @@ def main():
     torch.cuda.set_device(0)
     if args.serve:
         return serve(args, sp)
+    if args.eps_study:
+        return eps_study(args, sp)
     kind, groups, eps, tau = WORKLOADS[args.workload]
     v, f = surface_mesh(kind)
     n = v.shape[0]
