@@ -45,10 +45,13 @@ WORKLOADS = {
                          0.01, 5e-5),
     "ellipsoid7-batched": ("ellipsoid7", [(4108, 16, 8), (4116, 16, 16), (4132, 16, 32)],
                            0.01, 5e-5),
+    "surfaceD7-batched": ("surfaceD7", [(4208, 16, 8), (4216, 16, 16), (4232, 16, 32)],
+                          0.01, 5e-5),
     "sphere3": ("sphere3", [(1003, 1, 3)], 0.1, 1e-3),
 }
 MESH_TEXT = {"sphere": "unit sphere, icosahedral level {}", "torus": "ring torus {0}x{0} (R 1, r 0.4)",
-             "ellipsoid": "ellipsoid (1, 0.8, 0.6), icosahedral level {}"}
+             "ellipsoid": "ellipsoid (1, 0.8, 0.6), icosahedral level {}",
+             "surfaceD": "surface (D) (x1 - x3^2)^2 + x2^2 + x3^2 = 1, from icosahedral level {}"}
 
 # request stream of the serving benchmark: every mesh kind, m in 3..32,
 # eps in {0.02, 0.01, 0.005}, tau = eps / 200, 1..32 restarts, 200 steps

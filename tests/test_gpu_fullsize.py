@@ -13,9 +13,10 @@ the flow) and the same S_eps to 1e-12; restart 0 of every m group matches the
 oracle run of that restart alone (u, every lambda_i, S_eps, E) within 1e-5,
 the mixed-precision bar; every restart's E equals its sum lambda + S_eps.
 
-The torus (512 x 512, R = 1, r = 0.4) and ellipsoid (level 7, axes 1, 0.8,
-0.6) batches, m in {8, 16, 32} with 16 restarts each (896 columns, seeds
-4000 + m and 4100 + m), run the same configuration with the S_eps kernel the
+The torus (512 x 512, R = 1, r = 0.4), ellipsoid (level 7, axes 1, 0.8,
+0.6) and surface (D) (from icosphere level 7) batches, m in {8, 16, 32} with
+16 restarts each (896 columns, seeds 4000 + m, 4100 + m and 4200 + m), run
+the same configuration with the S_eps kernel the
 timing picks; restart 0 of the m = 8 group (the oracle's cost grows with m
 and the mesh: a sparse LU of the 262144-vertex torus alone takes ~40 s) is
 checked against the oracle, E = sum lambda + S_eps for every restart.
@@ -121,6 +122,7 @@ def test_sampled_restarts_match_oracle(runs):
 OTHER = {
     "torus512": [(4008, 16, 8), (4016, 16, 16), (4032, 16, 32)],
     "ellipsoid7": [(4108, 16, 8), (4116, 16, 16), (4132, 16, 32)],
+    "surfaceD7": [(4208, 16, 8), (4216, 16, 16), (4232, 16, 32)],
 }
 
 

@@ -3,7 +3,8 @@ import numpy as np
 import pytest
 
 from workloads import (icosphere, torus, ellipsoid, surface_mesh, uniform_u0,
-                       one_hot_u0, batch_u0, poisson_trace)
+                       one_hot_u0, batch_u0, poisson_trace, surface_d, surface_d_phi,
+                       project_surface_d, project_ellipsoid, project_sphere)
 
 
 def _edge_counts(tri):
@@ -86,3 +87,32 @@ def test_poisson_trace():
     assert all(3 <= r["m"] <= 32 and 1 <= r["restarts"] <= 32 for r in tr)
     assert tr == poisson_trace(5000, 50, 50.0, ["sphere3", "torus512"], (3, 32),
                                (0.02, 0.01), (1, 32))
+
+
+@pytest.mark.parametrize("level", [1, 3])
+def test_surface_d_on_surface_closed_outward(level):
+    v, f = surface_d(level)
+    assert np.abs(surface_d_phi(v)).max() < 1e-14
+    counts = _edge_counts(f)
+    assert (counts == 2).all() and v.shape[0] - counts.size + f.shape[0] == 2
+    # outward: the face normal agrees with grad Phi at the face centroid
+    n = np.cross(v[f[:, 1]] - v[f[:, 0]], v[f[:, 2]] - v[f[:, 0]])
+    c = v[f].mean(1)
+    g = np.stack([2 * (c[:, 0] - c[:, 2] ** 2), 2 * c[:, 1],
+                  -4 * c[:, 2] * (c[:, 0] - c[:, 2] ** 2) + 2 * c[:, 2]], 1)
+    assert (np.einsum("ij,ij->i", n, g) > 0).all()
+    assert np.array_equal(surface_mesh(f"surfaceD{level}")[0], v)
+
+
+def test_projections_land_on_their_surfaces():
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((200, 3)) * 0.7 + 0.1
+    assert np.abs(np.linalg.norm(project_sphere(x), axis=1) - 1).max() < 1e-15
+    a = np.array([1.0, 0.8, 0.6])
+    y = project_ellipsoid(x, a)
+    assert np.abs(((y / a) ** 2).sum(1) - 1).max() < 1e-14
+    assert np.abs(surface_d_phi(project_surface_d(x))).max() < 1e-13
+    # points already on a surface stay (to rounding)
+    v, _ = surface_d(2)
+    assert np.abs(project_surface_d(v) - v).max() < 1e-15
+

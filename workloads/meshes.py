@@ -15,13 +15,19 @@ Surfaces:
     quad split on a fixed diagonal; n_vert = nu*nv, n_tri = 2*nu*nv.
   * ``ellipsoid(level, axes)``  icosphere vertices scaled by the axes, so they
     lie exactly on the ellipsoid.
+  * ``surface_d(level)``  surface (D) of Section 3.3, the zero set of
+    (x1 - x3^2)^2 + x2^2 + x3^2 - 1: the image of the unit sphere under
+    (y1, y2, y3) -> (y1 + y3^2, y2, y3), so icosphere vertices mapped this
+    way lie exactly on it (same genus as the sphere, strongly varying
+    curvature).
 """
 from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["icosahedron", "icosphere", "torus", "ellipsoid", "surface_mesh",
-           "MESH_KINDS", "project_sphere", "project_ellipsoid"]
+__all__ = ["icosahedron", "icosphere", "torus", "ellipsoid", "surface_d", "surface_mesh",
+           "MESH_KINDS", "project_sphere", "project_ellipsoid", "project_surface_d",
+           "surface_d_phi"]
 
 
 def icosahedron():
@@ -105,13 +111,30 @@ def ellipsoid(level: int, axes=(1.0, 0.8, 0.6)):
     return np.ascontiguousarray(v * np.asarray(axes, dtype=np.float64)[None, :]), f
 
 
+def surface_d(level: int):
+    """Surface (D) from the level-``level`` icosphere: x = (y1 + y3^2, y2, y3).
+    The map has Jacobian determinant 1, so the outward orientation is kept."""
+    v, f = icosphere(level)
+    x = v.copy()
+    x[:, 0] += v[:, 2] * v[:, 2]
+    return np.ascontiguousarray(x), f
+
+
+def surface_d_phi(x):
+    """Level-set function of surface (D): (x1 - x3^2)^2 + x2^2 + x3^2 - 1."""
+    x = np.asarray(x, dtype=np.float64)
+    return (x[:, 0] - x[:, 2] ** 2) ** 2 + x[:, 1] ** 2 + x[:, 2] ** 2 - 1.0
+
+
 MESH_KINDS = ("sphere3", "sphere4", "sphere5", "sphere6", "sphere7", "sphere8",
               "torus512", "ellipsoid7")
 
 
 def surface_mesh(kind: str):
     """Named workload meshes: ``sphereL`` (icosphere level L), ``torusN`` (N x N
-    ring torus, R=1, r=0.4), ``ellipsoidL`` (axes 1, 0.8, 0.6)."""
+    ring torus, R=1, r=0.4), ``ellipsoidL`` (axes 1, 0.8, 0.6), ``surfaceDL``
+    (surface (D) from icosphere level L).  MESH_KINDS lists the kinds of the
+    serving request stream."""
     if kind.startswith("sphere"):
         return icosphere(int(kind[6:]))
     if kind.startswith("torus"):
@@ -119,6 +142,8 @@ def surface_mesh(kind: str):
         return torus(n, n, 1.0, 0.4)
     if kind.startswith("ellipsoid"):
         return ellipsoid(int(kind[9:]))
+    if kind.startswith("surfaceD"):
+        return surface_d(int(kind[8:]))
     raise ValueError(f"unknown mesh kind {kind!r}")
 
 
@@ -135,4 +160,16 @@ def project_ellipsoid(x, axes=(1.0, 0.8, 0.6)):
     x = np.asarray(x, dtype=np.float64)
     a = np.asarray(axes, dtype=np.float64)[None, :]
     return x / np.sqrt(((x / a) ** 2).sum(axis=1, keepdims=True))
+
+
+def project_surface_d(x):
+    """Points x [k, 3] moved onto surface (D) through the sphere it is the image
+    of: y = (x1 - x3^2, x2, x3) scaled to unit length, then mapped back."""
+    x = np.asarray(x, dtype=np.float64)
+    y = x.copy()
+    y[:, 0] -= x[:, 2] * x[:, 2]
+    y /= np.linalg.norm(y, axis=1, keepdims=True)
+    out = y.copy()
+    out[:, 0] += y[:, 2] * y[:, 2]
+    return out
 
