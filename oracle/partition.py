@@ -7,9 +7,15 @@ Two readings of a partition {Gamma_i} given as vertex labels:
   does not depend on eps.  Discretely, region i gets the P1 functions that
   vanish at every vertex not labelled i, and lambda_1 is the smallest
   eigenvalue of the pencil (A_II, M_II) restricted to the vertices I labelled
-  i.  On the sphere the three lunes of the Y-partition give 15/4 each
-  (Section 3.1); the reduced problem on the unit disk gives 20.19 for a
-  sector of angle 2 pi / 3 and 26.37 for a quadrant (Section 3.2).
+  i.  Such functions live on every triangle that touches the region, half an
+  element beyond it, so on a partition that covers the surface the value
+  lies below the region's own (O(h)); with ``interior`` the region's
+  boundary vertices (those with a neighbour labelled otherwise) are left out
+  too, which keeps the functions inside it, and the value lies above.  The
+  two bracket the eigenvalue of the region the labels describe.  On the
+  sphere the three lunes of the Y-partition give 15/4 each (Section 3.1);
+  the reduced problem on the unit disk gives 20.19 for a sector of angle
+  2 pi / 3 and 26.37 for a quadrant (Section 3.2).
 * ``region_graph``  which regions touch (share a mesh edge), the number of
   sides of each region (its number of neighbours, one arc per neighbour) and
   the counts n_k of regions with k sides.  For a partition whose junctions
@@ -25,14 +31,31 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse.linalg as spla
 
-__all__ = ["region_eigen", "region_graph", "gauss_bonnet_sides"]
+__all__ = ["region_eigen", "interior_labels", "region_graph", "gauss_bonnet_sides"]
 
 
-def region_eigen(M, A, labels, m):
+def interior_labels(M, labels):
+    """labels with every vertex that has a neighbour (a mesh edge: an
+    off-diagonal entry of the mass matrix, all of which are positive) of
+    another label set to -1."""
+    labels = np.asarray(labels)
+    C = M.tocoo()
+    off = C.row != C.col
+    bad = np.zeros(labels.shape[0], dtype=bool)
+    diff = labels[C.row[off]] != labels[C.col[off]]
+    bad[C.row[off][diff]] = True
+    out = labels.copy()
+    out[bad] = -1
+    return out
+
+
+def region_eigen(M, A, labels, m, interior=False):
     """lambda_1 of regions 0..m-1 (labels [N] int); NaN for an empty region."""
     labels = np.asarray(labels)
     M = M.tocsr()
     A = A.tocsr()
+    if interior:
+        labels = interior_labels(M, labels)
     out = np.full(m, np.nan)
     for i in range(m):
         idx = np.flatnonzero(labels == i)

@@ -7,6 +7,10 @@
   (Section 3.1); the whole sphere has 0.  Meshes whose boundaries follow the
   regions (structured sector meshes, a longitude-latitude sphere) make the
   discrete values converge at second order, checked by halving h;
+* the two readings of a label partition bracket the region's eigenvalue: for
+  the Y-partition labelled by longitude on icosphere meshes (boundaries that
+  cut through triangles) the plain value lies below 15/4 and the interior
+  one above, both within O(h), the bracket shrinking as h halves;
 * region_graph and the Gauss-Bonnet identity on partitions whose cell
   structure is known: the Y-partition (three 2-gons), the tetrahedral (four
   triangles), cubic (six quadrilaterals) and dodecahedral (twelve pentagons)
@@ -18,7 +22,7 @@ from scipy.optimize import brentq
 from scipy.special import jv
 
 from oracle import fem
-from oracle.partition import gauss_bonnet_sides, region_eigen, region_graph
+from oracle.partition import gauss_bonnet_sides, interior_labels, region_eigen, region_graph
 from workloads import icosahedron, icosphere
 
 
@@ -155,3 +159,20 @@ def test_y_partition_side_counts():
     lab2 = lab.copy()
     lab2[::7] = -1
     assert np.array_equal(region_graph(f, lab2, 3)[0], adj)
+
+
+def test_label_partition_brackets_the_lune():
+    widths = []
+    for level in (4, 5):
+        v, f = icosphere(level)
+        M, A = fem.assemble(v, f)
+        ph = np.mod(np.arctan2(v[:, 1], v[:, 0]), 2 * np.pi)
+        lab = np.minimum((ph / (2 * np.pi / 3)).astype(int), 2)
+        lo = region_eigen(M, A, lab, 3)
+        hi = region_eigen(M, A, lab, 3, interior=True)
+        assert np.all(lo < 15.0 / 4.0) and np.all(hi > 15.0 / 4.0)
+        widths.append(float(np.max(hi - lo)))
+    assert widths[1] < 0.6 * widths[0]
+    inner = interior_labels(M, lab)
+    assert np.all(inner[lab == -1] == -1) and (inner == -1).sum() > 0
+
