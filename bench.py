@@ -196,9 +196,23 @@ def eps_study(args, sp):
     log(f"[bench] eps study: {len(levels)} levels from icosphere level {args.eps_study_mesh} "
         f"({v.shape[0]} vertices)")
     t0 = time.perf_counter()
-    rc, res, lam, fin, _ = sp.continue_levels(mesh, prm, m, u0, levels, project_sphere,
-                                              want_u=False)
+    rc, res, lam, fin, u_fin = sp.continue_levels(mesh, prm, m, u0, levels, project_sphere)
     wall = time.perf_counter() - t0
+    # the final partition, read sharply: the first Dirichlet eigenvalue of each
+    # region of its argmax labels (Problem 1.1's energy, no eps in it)
+    last = fin if fin is not None else mesh
+    st = sp.State(last, sp.params(levels[-1][1], precision="fp64"), [m], [levels[-1][0]], u_fin)
+    _, lab_am = st.labels()
+    st.close()
+    t1 = time.perf_counter()
+    rc_e, lam_reg, _, its = sp.sp_region_eigen(last.h, [m], lab_am, u0=u_fin, shift=1.0, tol=1e-10,
+                                               max_iter=200)
+    rc_i, lam_in, _, its_in = sp.sp_region_eigen(last.h, [m], lab_am, u0=u_fin, shift=1.0,
+                                                 tol=1e-10, max_iter=200, interior=True)
+    t_eig = time.perf_counter() - t1
+    log(f"[bench]   regions of the final partition: lambda_1 in [{np.round(lam_reg, 5)}, "
+        f"{np.round(lam_in, 5)}], sum in [{lam_reg.sum():.5f}, {lam_in.sum():.5f}] (45/4 = 11.25), "
+        f"{its} + {its_in} inverse iterations, {t_eig:.1f} s")
     table = np.loadtxt(os.path.join(ROOT, "tests", "golden", "tab_u_eps.txt"), ndmin=2)
     rows, cdof = [], 0.0
     for i, ((eps, tau, ref), r) in enumerate(zip(levels, res)):
@@ -230,7 +244,13 @@ def eps_study(args, sp):
                                f"m 3, {len(levels)} levels (eps 0.5 halving, tau 8e-4 / sqrt(2) per "
                                "level, 4-fold refinement before levels 2, 4, ...), stop |dE| < 1e-6 "
                                "every M_tau = 0.1 / tau steps, mixed precision"},
-        "wall_s": wall, "status": int(rc), "levels": rows}))
+        "wall_s": wall, "status": int(rc), "levels": rows,
+        "final_partition": {"region_lambda_1_plain": [float(x) for x in lam_reg],
+                            "region_lambda_1_interior": [float(x) for x in lam_in],
+                            "sum_plain": float(lam_reg.sum()), "sum_interior": float(lam_in.sum()),
+                            "y_partition_value": 11.25,
+                            "inverse_iterations": [int(its), int(its_in)], "seconds": t_eig,
+                            "status": [int(rc_e), int(rc_i)]}}))
 
 
 def main():

@@ -345,6 +345,48 @@ int sp_continue(const sp_mesh* mesh0, const sp_params* prm, int32_t m, const dou
                 sp_level_result* results, double* lambda, sp_mesh** final_mesh,
                 double* u_final);
 
+/* ------------------------------------------------------------ partitions --
+ * Post-processing of a computed partition given as vertex labels (e.g. the
+ * argmax labels of sp_solve): region i of restart r is the set of vertices
+ * labelled i; other values (-1, the void of equation (vi)) belong to no
+ * region.  labels [n_restarts][n_vert] int32, caller numbering. */
+
+/* First Dirichlet eigenvalue of every region: the smallest eigenvalue of
+ * A x = lambda M x over the P1 functions that vanish at every vertex outside
+ * the region (the partition problem's energy, Problem 1.1, is their sum; on
+ * the sphere the lunes of the Y-partition give 15/4 each).  Computed by
+ * inverse iteration u <- (M + shift A)^{-1} M u restricted to the region
+ * (float64 Jacobi-CG to relative residual 1e-12 each), normalised, until the
+ * Rayleigh quotient of every region changes by at most tol (relative)
+ * between iterations; each iteration contracts the error by about
+ * (1 + shift lambda_1) / (1 + shift lambda_2).  m [n_restarts]; u0 [sum m]
+ * [n_vert] start vectors (nullable: 1 on the region; the partition's own
+ * components are good starts), restricted to the regions before use.
+ * Outputs (host): lambda [sum m] (NaN for an empty region); u_out [sum m]
+ * [n_vert] (nullable) the eigenvectors, unit L2 norm, zero outside;
+ * iterations (nullable).  shift > 0, tol > 0, max_iter >= 1.
+ * interior = 0: the functions vanish at the vertices outside the region, so
+ * they reach half an element beyond it and, on labels that cover the surface,
+ * the value lies below the region's own (O(h)); interior = 1: the region's
+ * boundary vertices (those with a mesh neighbour labelled otherwise) are
+ * left out too and the value lies above.  The two bracket the eigenvalue of
+ * the region the labels describe.  Returns SP_ENOCONV (after writing the
+ * outputs) if max_iter iterations did not meet tol. */
+int sp_region_eigen(const sp_mesh* mesh, int32_t n_restarts, const int32_t* m,
+                    const int32_t* labels, int32_t interior, const double* u0, double shift,
+                    double tol, int32_t max_iter, double* lambda, double* u_out,
+                    int32_t* iterations);
+
+/* Which regions touch: adjacency [sum_r m_r^2] (host) holds, per restart in
+ * order, an m_r x m_r block with 1 where a vertex of region i and a vertex of
+ * region j (i != j) share a mesh edge; sides [sum m] (nullable) counts each
+ * region's neighbours (its sides, one arc per neighbour).  With triple
+ * junctions only, the counts n_k of k-sided regions satisfy the identity
+ * derived from Euler's formula (equation gauss-bonnet),
+ * 4 n_2 + 3 n_3 + 2 n_4 + n_5 = 6 chi + sum_{k>=7} (k - 6) n_k.  m_r <= 4096. */
+int sp_region_graph(const sp_mesh* mesh, int32_t n_restarts, const int32_t* m,
+                    const int32_t* labels, uint8_t* adjacency, int32_t* sides);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,8 +7,10 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "continuation.h"
+#include "partition.h"
 #include "engine.h"
 #include "server.h"
 
@@ -468,6 +470,49 @@ int sp_continue(const sp_mesh* mesh0, const sp_params* prm, int32_t m, const dou
       *final_mesh = h.release();
     }
     return o.converged ? SP_OK : SP_ENOCONV;
+  });
+}
+
+int sp_region_eigen(const sp_mesh* mesh, int32_t n_restarts, const int32_t* m,
+                    const int32_t* labels, int32_t interior, const double* u0, double shift,
+                    double tol, int32_t max_iter, double* lambda, double* u_out,
+                    int32_t* iterations) {
+  return guard([&] {
+    SP_REQUIRE(mesh && mesh->m && labels && lambda, SP_EINVAL, "NULL argument");
+    SP_REQUIRE(std::isfinite(shift) && shift > 0, SP_EINVAL, "shift must be > 0");
+    SP_REQUIRE(n_restarts >= 1 && m, SP_EINVAL, "need n_restarts >= 1");
+    std::vector<double> eps(n_restarts, 1.0);  // unused by the restricted solve
+    sp::BatchSpec spec = make_spec(n_restarts, m, eps.data());
+    sp_params p;
+    sp_params_default(&p, shift);
+    p.precision = SP_FP64;
+    p.cg_rtol = 1e-12;
+    p.cg_max_iter = 100000;
+    p.n_steps = 1;
+    p.energy_every = 0;
+    sp::Solver S(mesh->m.get(), p, spec, nullptr);
+    const int R = S.R();
+    const int64_t n = mesh->m->n;
+    std::vector<double> ones;
+    if (!u0) {
+      ones.assign(size_t(R) * n, 1.0);
+      u0 = ones.data();
+    }
+    S.upload_host(u0, false);
+    S.set_region_mask(labels, interior != 0);
+    const int it = S.region_eigen(tol, max_iter, lambda);
+    if (iterations) *iterations = it < 0 ? -it : it;
+    if (u_out) S.download_host(u_out);
+    return it > 0 ? SP_OK : SP_ENOCONV;
+  });
+}
+
+int sp_region_graph(const sp_mesh* mesh, int32_t n_restarts, const int32_t* m,
+                    const int32_t* labels, uint8_t* adjacency, int32_t* sides) {
+  return guard([&] {
+    SP_REQUIRE(mesh && mesh->m, SP_EINVAL, "NULL mesh");
+    sp::region_graph(*mesh->m, n_restarts, m, labels, adjacency, sides);
+    return SP_OK;
   });
 }
 

@@ -54,6 +54,16 @@ class Solver {
   void energy_to_host(double* lam, double* seps, double* E);
   void labels_device(int32_t* d_lab, int32_t* d_lab_am);
   void labels_host(int32_t* lab, int32_t* lab_am);
+  // Partition post-processing (partition.cpp).  Restrict every column to its
+  // region: labels [nres][n] (caller order), column lo_r + i of restart r
+  // keeps the vertices labelled i (interior: and not on the region's
+  // boundary, i.e. without a mesh neighbour labelled otherwise); the state
+  // is masked, columns with an empty region stop being live.  Float64 only.
+  void set_region_mask(const int32_t* labels, bool interior);
+  // Inverse iteration u <- (M + tau A)^{-1} M u on the regions, normalised,
+  // until every live column's Rayleigh quotient changes by <= tol relative;
+  // lam [R] host (NaN where not live).  Returns the iterations taken.
+  int region_eigen(double tol, int max_iter, double* lam);
 
   // column/restart activity (continuous batching, stop rule)
   void set_restart_live(int r, bool live);
@@ -164,6 +174,7 @@ class Solver {
   // factor as they read u_.  Anything else that reads u_ or changes the live
   // masks calls flush_scale() first.
   bool u_pending_ = false;
+  DevBuf<uint8_t> mask_;  // [n][rp] region mask (set_region_mask)
   double* node_out_ = nullptr;  // where the last node step wrote (u_ or r64_)
   bool lam_fresh_ = false;  // lam holds the Rayleigh quotients of the current state
   bool all_live_ = true;    // every real column is live

@@ -62,6 +62,10 @@ struct StepArgs {
   // state is v * usc[c] per column (usc = cg.isc); the refinement update's
   // ubase and the S_eps kernels apply it as they read.
   const double* usc = nullptr;
+  // Region mask [n][rp] (0/1 per vertex and column), float64 solves only: the
+  // heat solve is restricted to the vertices of each column's region (the
+  // Dirichlet eigenproblems of a partition); null = no restriction.
+  const uint8_t* mask = nullptr;
   ColTab ct;
   CgCols cg;
   double* part;        // [3][nchunk][rp] partial sums
@@ -187,6 +191,13 @@ void norm_dot(const StepArgs& a, const double* v, double* w, hipStream_t s);
 // M-norms of the live columns of the vector norm_dot saw; lam (nullable)
 // receives their Rayleigh quotients
 void red_norm(const StepArgs& a, double* lam, hipStream_t s);
+// u *= mask (region restriction of the state)
+void apply_mask(const StepArgs& a, double* u, hipStream_t s);
+// adjacency of regions across mesh edges: adj[off[r] + i * m_r + j] = 1 when
+// a vertex of region i of restart r neighbours one of region j (labels
+// [nres][n] in the renumbered order; values outside 0..m_r-1 are ignored)
+void region_graph(const StepArgs& a, const int32_t* labels, const int* off, const int* mres,
+                  int nres, uint8_t* adj, hipStream_t s);
 // u = v / nrm on the live columns (u may be v)
 void scale(const StepArgs& a, const double* v, double* u, hipStream_t s);
 // energies

@@ -312,8 +312,8 @@ __global__ __launch_bounds__(kBlock) void k_init_fp64(StepArgs a, const double* 
   double s[3][4] = {};
   if (g < t.G) {
     const int c0 = 4 * g;
-    double lv[4];
-    for (int j = 0; j < 4; ++j) lv[j] = a.ct.live[c0 + j] ? 1.0 : 0.0;
+    double lv0[4];
+    for (int j = 0; j < 4; ++j) lv0[j] = a.ct.live[c0 + j] ? 1.0 : 0.0;
     for_rows(t, [&](int row) {
       double au[4] = {}, mu[4] = {};
       for_neighbors(a, row, c0, u, [&](int, const V4<double>& x, size_t o) {
@@ -324,6 +324,9 @@ __global__ __launch_bounds__(kBlock) void k_init_fp64(StepArgs a, const double* 
         }
       });
       const double di = a.dinv64[row];
+      double lv[4] = {lv0[0], lv0[1], lv0[2], lv0[3]};
+      if (a.mask)  // restricted solve: b and r0 live on the column's region
+        for (int j = 0; j < 4; ++j) lv[j] *= double(a.mask[size_t(row) * t.rp + c0 + j]);
       V4<double> rv, pv;
       for (int j = 0; j < 4; ++j) {
         rv.v[j] = -a.tau * au[j] * lv[j];
@@ -379,6 +382,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmm(StepArgs a, int slot, const 
           if (k == 0) pd = x;
           for (int j = 0; j < 4; ++j) acc.v[j] = fma(v, x.v[j], acc.v[j]);
         });
+        if constexpr (sizeof(T) == 8) {
+          if (a.mask)  // restricted solve: the product keeps the region's rows
+            for (int j = 0; j < 4; ++j)
+              if (!a.mask[size_t(row) * t.rp + c0 + j]) acc.v[j] = 0.0;
+        }
         st4g(q + size_t(row) * t.rp + c0, acc);
         for (int j = 0; j < 4; ++j) s[0][j] += double(pd.v[j]) * double(acc.v[j]);
       });
@@ -1078,6 +1086,37 @@ __global__ void k_red_norm(StepArgs a, double* __restrict__ lam) {
   if (lv && lam) lam[c] = sa / s;
   // ||M u||^2 of the scaled state u = v / ||v||_M (the next solve's ||b||^2)
   if (lv) a.cg.bb_next[c] = sm / s;
+}
+
+// u *= mask, every column (region restriction of a state).
+__global__ __launch_bounds__(kBlock) void k_apply_mask(StepArgs a, double* __restrict__ u) {
+  const size_t total = size_t(a.t.n) * a.t.rp;
+  for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < total;
+       i += size_t(gridDim.x) * kBlock)
+    if (!a.mask[i]) u[i] = 0.0;
+}
+
+// Region adjacency: one thread per (row, restart); every neighbour of the row
+// with another valid label marks the pair (all writers store 1).
+__global__ __launch_bounds__(kBlock) void k_region_graph(StepArgs a, const int32_t* __restrict__ lab,
+                                                         const int* __restrict__ off,
+                                                         const int* __restrict__ mres, int nres,
+                                                         uint8_t* __restrict__ adj) {
+  const int n = a.t.n;
+  const size_t total = size_t(n) * nres;
+  for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < total;
+       i += size_t(gridDim.x) * kBlock) {
+    const int r = int(i / n), row = int(i - size_t(r) * n);
+    const int m = mres[r];
+    const int32_t* lr = lab + size_t(r) * n;
+    const int li = lr[row];
+    if (li < 0 || li >= m) continue;
+    for (int k = 1; k < a.W; ++k) {
+      const int w = a.cols[size_t(k) * n + row];
+      const int lw = lr[w];
+      if (lw >= 0 && lw < m && lw != li) adj[off[r] + li * m + lw] = 1;
+    }
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_scale(StepArgs a, const double* v, double* u) {
@@ -2126,6 +2165,21 @@ void norm_dot(const StepArgs& a, const double* v, double* w, hipStream_t s) {
 
 void red_norm(const StepArgs& a, double* lam, hipStream_t s) {
   hipLaunchKernelGGL(k_red_norm, dim3(colblocks(a.t)), dim3(kBlock), 0, s, a, lam);
+  SP_LAUNCH_CHECK();
+}
+
+void apply_mask(const StepArgs& a, double* u, hipStream_t s) {
+  const size_t total = size_t(a.t.n) * a.t.rp;
+  hipLaunchKernelGGL(k_apply_mask, dim3(std::min<size_t>(nblocks(total), 65536)), dim3(kBlock), 0,
+                     s, a, u);
+  SP_LAUNCH_CHECK();
+}
+
+void region_graph(const StepArgs& a, const int32_t* labels, const int* off, const int* mres,
+                  int nres, uint8_t* adj, hipStream_t s) {
+  const size_t total = size_t(a.t.n) * nres;
+  hipLaunchKernelGGL(k_region_graph, dim3(std::min<size_t>(nblocks(total), 65536)), dim3(kBlock), 0,
+                     s, a, labels, off, mres, nres, adj);
   SP_LAUNCH_CHECK();
 }
 

@@ -115,6 +115,9 @@ _SIGS = {
     "sp_continue": (C.c_int, [P, C.POINTER(sp_params), C.c_int32, D, C.c_int32,
                               C.POINTER(sp_level), PROJECT_FN, P, C.POINTER(sp_level_result),
                               D, PP, D]),
+    "sp_region_eigen": (C.c_int, [P, C.c_int32, I32, I32, C.c_int32, D, C.c_double, C.c_double,
+                                  C.c_int32, D, D, I32]),
+    "sp_region_graph": (C.c_int, [P, C.c_int32, I32, I32, C.POINTER(C.c_uint8), I32]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -308,6 +311,47 @@ def sp_continue(mesh_h, prm, m, u0, levels, project=None, want_u=True):
                                   res, _dp(lam), C.byref(fin), _dp(u)),
                 allow=(SP_ENOCONV,))
     return rc, [r.as_dict() for r in res], lam, (fin if fin.value else None), u
+
+
+def sp_region_eigen(mesh_h, m, labels, u0=None, shift=1e3, tol=1e-12, max_iter=500,
+                    want_u=False, interior=False):
+    """Returns (status, lambda [sum m], u [sum m, n] or None, iterations)."""
+    n = sp_mesh_info(mesh_h)[0]
+    m = _i32(np.atleast_1d(m))
+    lab = _i32(np.atleast_2d(labels))
+    if lab.shape != (m.size, n):
+        raise ValueError(f"labels must have shape ({m.size}, {n}), got {lab.shape}")
+    R = int(m.sum())
+    if u0 is not None:
+        u0 = _f64(u0)
+        if u0.shape != (R, n):
+            raise ValueError(f"u0 must have shape ({R}, {n}), got {u0.shape}")
+    lam = np.empty(R)
+    u = np.empty((R, n)) if want_u else None
+    it = C.c_int32()
+    rc = _check(lib().sp_region_eigen(mesh_h, m.size, _ip(m), _ip(lab), int(bool(interior)),
+                                      _dp(u0), float(shift),
+                                      float(tol), int(max_iter), _dp(lam), _dp(u), C.byref(it)),
+                allow=(SP_ENOCONV,))
+    return rc, lam, u, it.value
+
+
+def sp_region_graph(mesh_h, m, labels):
+    """Returns (list of adjacency matrices [m_r, m_r] bool, sides [sum m])."""
+    n = sp_mesh_info(mesh_h)[0]
+    m = _i32(np.atleast_1d(m))
+    lab = _i32(np.atleast_2d(labels))
+    if lab.shape != (m.size, n):
+        raise ValueError(f"labels must have shape ({m.size}, {n}), got {lab.shape}")
+    adj = np.zeros(int((m.astype(np.int64) ** 2).sum()), np.uint8)
+    sides = np.empty(int(m.sum()), np.int32)
+    _check(lib().sp_region_graph(mesh_h, m.size, _ip(m), _ip(lab),
+                                 adj.ctypes.data_as(C.POINTER(C.c_uint8)), _ip(sides)))
+    out, o = [], 0
+    for k in m:
+        out.append(adj[o:o + k * k].reshape(k, k).astype(bool))
+        o += k * k
+    return out, sides
 
 
 class Mesh:
