@@ -23,7 +23,7 @@ import numpy as np
 
 from .fem import simplex_monomial, triangle_geometry
 
-__all__ = ["quartic_table", "rayleigh", "pair_integrals", "s_eps", "energy"]
+__all__ = ["quartic_table", "rayleigh", "pair_integrals", "s_eps", "energy", "multipliers"]
 
 
 def quartic_table():
@@ -73,3 +73,16 @@ def energy(xyz, tri, M, A, u, eps):
     lam = rayleigh(M, A, u)
     s = s_eps(xyz, tri, u, eps)
     return lam, s, float(lam.sum() + s)
+
+
+def multipliers(xyz, tri, M, A, u, eps):
+    """The Lagrange multipliers of the gradient flow (Section 2.2, after
+    Caffarelli & Lin): lambda_i^eps = int |grad u_i|^2 + (2/eps^2) int
+    (sum_{j != i} u_j^2) u_i^2 for each row u_i of a unit-norm state u [m, N].
+    The Dirichlet term is u_i^T A u_i / u_i^T M u_i (equal to u_i^T A u_i at
+    unit norm); the coupling is the off-diagonal row sum of the pair
+    integrals."""
+    lam = rayleigh(M, A, u)
+    P = pair_integrals(xyz, tri, u)
+    return lam + (2.0 / (eps * eps)) * (P.sum(axis=1) - np.diag(P))
+

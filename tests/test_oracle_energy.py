@@ -151,3 +151,33 @@ def test_paper_eps_table_consistency(golden_dir):
     np.testing.assert_allclose(eoc_ref, eoc[1:], atol=2e-3)
     np.testing.assert_allclose(eps[1:] / eps[:-1], 0.5, rtol=1e-5)
     assert abs(S[0] - 6.0 / (0.25 * 4 * np.pi)) < 2e-4
+
+
+def test_multipliers_closed_forms():
+    v, f = icosphere(2)
+    n = v.shape[0]
+    M, A = fem.assemble(v, f)
+    area = fem.surface_area(v, f)
+    # unit-norm constants: lambda_i = 0, lambda_i^eps = (2/eps^2)(m-1)/|Gamma_h|
+    m, eps = 3, 0.3
+    u = np.full((m, n), 1.0 / np.sqrt(area))
+    lm = energy.multipliers(v, f, M, A, u, eps)
+    ref = 2.0 / eps**2 * (m - 1) / area
+    assert np.all(np.abs(lm - ref) < 1e-12 * ref)
+    # constants of different size c_i: (2/eps^2) c_i^2 (sum_{j != i} c_j^2) |Gamma_h|
+    c = np.array([0.3, 0.7, 1.1])
+    u = np.repeat(c[:, None], n, axis=1)
+    lm = energy.multipliers(v, f, M, A, u, eps)
+    ref = 2.0 / eps**2 * c**2 * ((c**2).sum() - c**2) * area
+    assert np.max(np.abs(lm - ref) / ref) < 1e-12
+    # supports without a common triangle: lambda^eps = lambda
+    u = np.zeros((2, n))
+    u[0, v[:, 2] > 0.5] = 1.0
+    u[1, v[:, 2] < -0.5] = 1.0
+    assert np.array_equal(energy.multipliers(v, f, M, A, u, 0.1), energy.rayleigh(M, A, u))
+    # the paper's identity: sum_i lambda_i^eps = sum_i lambda_i + 2 S_eps
+    rng = np.random.default_rng(5)
+    u = rng.random((4, n))
+    lm = energy.multipliers(v, f, M, A, u, 0.2)
+    lam, s, _ = energy.energy(v, f, M, A, u, 0.2)
+    assert abs(lm.sum() - (lam.sum() + 2 * s)) < 1e-12 * lm.sum()
