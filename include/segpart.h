@@ -207,6 +207,12 @@ int sp_state_stage(sp_state* st, int32_t stage);
 /* Evaluate lambda [sum m], s_eps and energy [n_restarts] of the current state
  * now (float64 on the GPU).  Nullable outputs. */
 int sp_state_energy(sp_state* st, double* lambda, double* s_eps, double* energy);
+/* Lagrange multipliers of the gradient flow at the current state (Section
+ * 2.2, after Caffarelli and Lin): lambda_eps [sum m] (host),
+ * lambda_i^eps = int |grad u_i|^2 + (2/eps^2) int (sum_{j != i} u_j^2) u_i^2,
+ * the coupling integrated exactly per triangle.  Their sum is
+ * sum_i lambda_i + 2 S_eps. */
+int sp_state_multipliers(sp_state* st, double* lambda_eps);
 /* Copy the current state out ([sum m][n_vert], host) and the step counter. */
 int sp_state_read(sp_state* st, double* u, int64_t* step);
 /* Overwrite the state (checkpoint restore / parity set-up) and step counter;

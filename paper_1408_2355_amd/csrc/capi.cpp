@@ -272,6 +272,14 @@ int sp_state_energy(sp_state* st, double* lambda, double* s_eps, double* energy)
   });
 }
 
+int sp_state_multipliers(sp_state* st, double* lambda_eps) {
+  return guard([&] {
+    SP_REQUIRE(st && st->solver, SP_EINVAL, "NULL state");
+    st->solver->multipliers_to_host(lambda_eps);
+    return SP_OK;
+  });
+}
+
 int sp_state_read(sp_state* st, double* u, int64_t* step) {
   return guard([&] {
     SP_REQUIRE(st && st->solver, SP_EINVAL, "NULL state");

@@ -745,6 +745,16 @@ void Solver::energy() {
   k::red_energy(args_, sp_, part_s_.p, need_rq, lam_.p, seps_.p, energy_.p, s_);
 }
 
+void Solver::multipliers_to_host(double* lam_eps) {
+  SP_REQUIRE(lam_eps != nullptr, SP_EINVAL, "NULL output");
+  flush_scale();
+  energy();  // Rayleigh quotients of the current state in lam_
+  DevBuf<double> part(size_t(8 * sp_.nper) * rp_), out(rp_);
+  k::multipliers(args_, sp_, mesh_->tri.p, mesh_->tarea.p, u_.p, part.p, lam_.p, out.p, s_);
+  SP_HIP(hipMemcpyAsync(lam_eps, out.p, R_ * sizeof(double), hipMemcpyDeviceToHost, s_));
+  SP_HIP(hipStreamSynchronize(s_));
+}
+
 void Solver::energy_to_host(double* lam, double* seps, double* E) {
   energy();
   if (lam) SP_HIP(hipMemcpyAsync(lam, lam_.p, R_ * sizeof(double), hipMemcpyDeviceToHost, s_));

@@ -52,6 +52,8 @@ class Solver {
   // Energies of the current state into device arrays (lam [rp], seps/E [nres]).
   void energy();
   void energy_to_host(double* lam, double* seps, double* E);
+  // Lagrange multipliers lambda^eps [R] of the current state (host)
+  void multipliers_to_host(double* lam_eps);
   void labels_device(int32_t* d_lab, int32_t* d_lab_am);
   void labels_host(int32_t* lab, int32_t* lab_am);
   // Partition post-processing (partition.cpp).  Restrict every column to its

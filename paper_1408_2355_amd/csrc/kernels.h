@@ -198,6 +198,10 @@ void apply_mask(const StepArgs& a, double* u, hipStream_t s);
 // [nres][n] in the renumbered order; values outside 0..m_r-1 are ignored)
 void region_graph(const StepArgs& a, const int32_t* labels, const int* off, const int* mres,
                   int nres, uint8_t* adj, hipStream_t s);
+// Lagrange multipliers lambda^eps [rp] of the state u (unit norm, lam its
+// Rayleigh quotients); part [8 sp.nper][rp] scratch
+void multipliers(const StepArgs& a, const SepsPlan& sp, const int32_t* tri, const double* tarea,
+                 const double* u, double* part, const double* lam, double* out, hipStream_t s);
 // u = v / nrm on the live columns (u may be v)
 void scale(const StepArgs& a, const double* v, double* u, hipStream_t s);
 // energies

@@ -1554,6 +1554,92 @@ __global__ __launch_bounds__(kBlock) void k_energy_seps_lanes(StepArgs a, SepsPl
   });
 }
 
+// Coupling term of the Lagrange multipliers: P_i = int u_i^2 sum_{j != i}
+// u_j^2 per column, = (|T|/360) B(G - a_i a_i^T, a_i a_i^T) per triangle with
+// G = sum_j a_j a_j^T over the restart's components (B as above).  Layout of
+// the direct S_eps kernel (one lane per restart and triangle); components in
+// blocks of 8 accumulated in registers, G recomputed per block; the block
+// loop runs to the tile's largest m so every thread reaches the barriers.
+// part [8 nper][rp]: one partial per workgroup and column (lane order fixed).
+__global__ __launch_bounds__(kBlock) void k_multipliers(StepArgs a, SepsPlan sp,
+                                                        const int* __restrict__ tri,
+                                                        const double* __restrict__ tarea,
+                                                        const double* __restrict__ u,
+                                                        double* __restrict__ part) {
+  __shared__ double red[kBlock];
+  const int rp = a.t.rp;
+  const int tid = threadIdx.x;
+  for_seps_chunks(sp, [&](int tile, int cb, int ce, int stride) {
+    const int4 tl = sp.tiles[tile];
+    const int r0 = tl.x, nr = tl.y - tl.x;
+    int nrp = 1;
+    while (nrp < nr) nrp <<= 1;
+    const int TB = kBlock / nrp;
+    const int tb = tid / nrp, rr = tid % nrp;
+    int lo = 0, m = 0, mmax = 0;
+    for (int q = 0; q < nr; ++q) mmax = max(mmax, a.ct.res_len[r0 + q]);
+    if (rr < nr) {
+      lo = a.ct.res_lo[r0 + rr];
+      m = a.ct.res_len[r0 + rr];
+    }
+    for (int kb = 0; kb < mmax; kb += 8) {
+      double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (kb < m)
+        for (int chunk = cb; chunk < ce; chunk += stride) {
+          const int t_beg = chunk * sp.tchunk, t_end = min(t_beg + sp.tchunk, sp.nt);
+          for (int t = t_beg + tb; t < t_end; t += TB) {
+            const double* c0 = u + size_t(tri[3 * t + 0]) * rp + lo;
+            const double* c1 = u + size_t(tri[3 * t + 1]) * rp + lo;
+            const double* c2 = u + size_t(tri[3 * t + 2]) * rp + lo;
+            double G[6] = {0, 0, 0, 0, 0, 0};
+            for (int i = 0; i < m; ++i) {
+              const double x0 = c0[i], x1 = c1[i], x2 = c2[i];
+              G[0] = fma(x0, x0, G[0]);
+              G[1] = fma(x1, x1, G[1]);
+              G[2] = fma(x2, x2, G[2]);
+              G[3] = fma(x0, x1, G[3]);
+              G[4] = fma(x0, x2, G[4]);
+              G[5] = fma(x1, x2, G[5]);
+            }
+            const double w = tarea[t] * (1.0 / 360.0);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              if (kb + j >= m) break;
+              const double x0 = c0[kb + j], x1 = c1[kb + j], x2 = c2[kb + j];
+              const double H[6] = {x0 * x0, x1 * x1, x2 * x2, x0 * x1, x0 * x2, x1 * x2};
+              double R[6];
+              for (int q = 0; q < 6; ++q) R[q] = G[q] - H[q];
+              acc[j] = fma(quartic_b(R, H), w, acc[j]);
+            }
+          }
+        }
+      for (int j = 0; j < 8; ++j) {
+        red[tid] = acc[j];
+        for (int st = TB >> 1; st >= 1; st >>= 1) {
+          __syncthreads();
+          if (tb < st) red[tid] += red[tid + st * nrp];
+        }
+        __syncthreads();
+        if (tb == 0 && rr < nr && kb + j < m) part[size_t(blockIdx.x) * rp + lo + kb + j] = red[tid];
+        __syncthreads();
+      }
+    }
+  });
+}
+
+// lambda^eps_c = lambda_c + (2 / eps^2) sum over workgroups of the partials
+// (fixed order); 2 / eps^2 = coef / tau.
+__global__ void k_red_multipliers(StepArgs a, SepsPlan sp, const double* __restrict__ part,
+                                  const double* __restrict__ lam, double* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.t.rp) return;
+  if (a.ct.seg_len[c] == 0) {
+    out[c] = 0.0;
+    return;
+  }
+  out[c] = lam[c] + (a.ct.coef[c] / a.tau) * sum_chunks(part, 8 * sp.nper, a.t.rp, c);
+}
+
 __global__ void k_red_lambda(StepArgs a, double* __restrict__ lam) {
   const int c = red_col();
   const Tile& t = a.t64;
@@ -2180,6 +2266,16 @@ void region_graph(const StepArgs& a, const int32_t* labels, const int* off, cons
   const size_t total = size_t(a.t.n) * nres;
   hipLaunchKernelGGL(k_region_graph, dim3(std::min<size_t>(nblocks(total), 65536)), dim3(kBlock), 0,
                      s, a, labels, off, mres, nres, adj);
+  SP_LAUNCH_CHECK();
+}
+
+void multipliers(const StepArgs& a, const SepsPlan& sp, const int32_t* tri, const double* tarea,
+                 const double* u, double* part, const double* lam, double* out, hipStream_t s) {
+  if (sp.ntile > 0)
+    hipLaunchKernelGGL(k_multipliers, dim3(8 * sp.nper), dim3(kBlock), 0, s, a, sp, tri, tarea, u,
+                       part);
+  hipLaunchKernelGGL(k_red_multipliers, dim3(nblocks(size_t(a.t.rp))), dim3(kBlock), 0, s, a, sp,
+                     part, lam, out);
   SP_LAUNCH_CHECK();
 }
 

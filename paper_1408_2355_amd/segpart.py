@@ -94,6 +94,7 @@ _SIGS = {
     "sp_state_stage": (C.c_int, [P, C.c_int32]),
     "sp_state_energy": (C.c_int, [P, D, D, D]),
     "sp_state_read": (C.c_int, [P, D, I64]),
+    "sp_state_multipliers": (C.c_int, [P, D]),
     "sp_state_write": (C.c_int, [P, D, C.c_int64, C.c_int32]),
     "sp_state_labels": (C.c_int, [P, I32, I32]),
     "sp_state_history": (C.c_int, [P, C.c_int32, C.c_int64, I64, D, I64]),
@@ -429,6 +430,12 @@ class State:
     def write(self, u, step=0, normalise=False):
         u = _f64(u)
         _check(lib().sp_state_write(self.h, _dp(u), int(step), int(bool(normalise))))
+
+    def multipliers(self):
+        """lambda_i^eps [sum m] of the current state."""
+        out = np.empty(self.R)
+        _check(lib().sp_state_multipliers(self.h, _dp(out)))
+        return out
 
     def labels(self):
         a = np.empty((self.m.size, self.mesh.n_vert), np.int32)

@@ -11,7 +11,10 @@
   argmax partition of a short m = 4 flow; the eigenvectors vanish outside
   their regions and have unit M-norm; an empty region gives NaN; the default
   start (1 on the region) reaches the same values; the interior reading
-  (boundary vertices left out) against the oracle's, above the plain one.
+  (boundary vertices left out) against the oracle's, above the plain one;
+* sp_state_multipliers: lambda_i^eps against the oracle on the state read
+  back (1e-11), float64 and mixed (a pending normalisation applied first),
+  and sum lambda^eps = sum lambda + 2 S_eps.
 """
 import numpy as np
 import pytest
@@ -157,3 +160,37 @@ def test_region_eigen_of_a_flow_partition(gpu):
     print("  interior reading", flush=True)
     lam_in, _ = check_eigen(v, f, lab, [m], u0=res["u"], interior=True)
     assert np.all(lam_in > lam_u)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_multipliers_match_oracle(gpu, precision):
+    """lambda^eps of a state stepped on the GPU (mixed: its last normalisation
+    still pending) against the oracle on the state read back; m = 3, 5, 11
+    (one, and more than one, block of 8 components)."""
+    from oracle import energy as oen
+    v, f = icosphere(4)
+    n = v.shape[0]
+    ms = [3, 5, 11]
+    eps = [0.05, 0.1, 0.08]
+    u0 = uniform_u0(33, 1, sum(ms), n)
+    mesh = sp.Mesh(v, f)
+    prm = sp.params(2e-3, precision=precision, n_steps=1, energy_every=1, cg_rtol=1e-12,
+                    extrapolate=3)
+    print(f"multipliers after 12 steps, {precision}", flush=True)
+    st = sp.State(mesh, prm, ms, eps, u0)
+    try:
+        st.step(12)
+        lm = st.multipliers()
+        lam, s_eps, _ = st.energy()
+        u, _ = st.read()
+    finally:
+        st.close()
+    M, A = fem.assemble(v, f)
+    lo = 0
+    for r, m in enumerate(ms):
+        ref = oen.multipliers(v, f, M, A, u[lo:lo + m], eps[r])
+        assert np.max(np.abs(lm[lo:lo + m] - ref) / np.abs(ref)) < 1e-11
+        assert abs(lm[lo:lo + m].sum() - (lam[lo:lo + m].sum() + 2 * s_eps[r])) <= \
+            1e-12 * lm[lo:lo + m].sum()
+        lo += m
+    mesh.close()
