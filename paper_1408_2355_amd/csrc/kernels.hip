@@ -1013,12 +1013,19 @@ __global__ __launch_bounds__(kBlock) void k_nodal(StepArgs a, const double* __re
     for (int j = 0; j < 4; ++j) {
       if (!lv[j]) continue;
       if (lo[j] != cur) {
+        // S over the restart's components, in component order (wide loads
+        // where the segment is aligned; the same fma sequence either way)
         cur = lo[j];
         S = 0.0;
-        for (int i = 0; i < len[j]; ++i) {
-          const double w = ur[lo[j] + i];
-          S = fma(w, w, S);
+        const double* seg = ur + lo[j];
+        int i = 0;
+        if (((lo[j] | len[j]) & 3) == 0) {
+          for (; i < len[j]; i += 4) {
+            const V4<double> w = ld4(seg + i);
+            for (int q = 0; q < 4; ++q) S = fma(w.v[q], w.v[q], S);
+          }
         }
+        for (; i < len[j]; ++i) S = fma(seg[i], seg[i], S);
       }
       const double x = uv.v[j];
       ov.v[j] = x * exp(-cf[j] * (S - x * x));
