@@ -991,20 +991,55 @@ __global__ __launch_bounds__(kBlock) void k_nodal(StepArgs a, const double* __re
   const Tile& t = a.t;
   for (int ct = 0; ct < t.nct; ++ct) {
   const int g = ct * t.tg + threadIdx.x % t.tg;
-  if (g >= t.G) continue;
+  if (t.tg != 64 && g >= t.G) continue;  // (tg == 64: the whole wavefront stays)
   const int c0 = 4 * g;
-  int lo[4], len[4], lv[4];
-  double cf[4];
-  for (int j = 0; j < 4; ++j) {
-    lo[j] = a.ct.seg_lo[c0 + j];
-    len[j] = a.ct.seg_len[c0 + j];
-    lv[j] = a.ct.live[c0 + j];
-    cf[j] = a.ct.coef[c0 + j];
-  }
-  if (!(lv[0] | lv[1] | lv[2] | lv[3])) continue;
+  int lo[4] = {0, 0, 0, 0}, len[4] = {0, 0, 0, 0}, lv[4] = {0, 0, 0, 0};
+  double cf[4] = {0, 0, 0, 0};
+  if (g < t.G)
+    for (int j = 0; j < 4; ++j) {
+      lo[j] = a.ct.seg_lo[c0 + j];
+      len[j] = a.ct.seg_len[c0 + j];
+      lv[j] = a.ct.live[c0 + j];
+      cf[j] = a.ct.coef[c0 + j];
+    }
   const bool mixed = keep && !(lv[0] & lv[1] & lv[2] & lv[3]);
+  // One row per wavefront and every lane's four columns inside one restart
+  // whose lanes all lie in this wavefront: S comes from a segmented sum of
+  // the lanes' partial sums across the wavefront instead of re-reading the
+  // restart's values.  The lane test is wave-uniform (ballot); a wavefront
+  // that fails it (a restart across a tile edge, m not a multiple of 4)
+  // takes the general path below.  Lanes past the last group take part in
+  // the shuffles with an empty segment.
+  const int lane = threadIdx.x & 63;
+  const int tile0 = 4 * (ct * t.tg);
+  const bool one_seg = g < t.G && lo[0] == lo[3] && len[0] > 0 && ((lo[0] | len[0]) & 3) == 0 &&
+                       lo[0] >= tile0 && lo[0] + len[0] <= tile0 + 256;
+  const bool lanes = t.tg == 64 && __all(g >= t.G || one_seg);
+  const int ls = one_seg ? (lo[0] - tile0) >> 2 : lane, le = one_seg ? ls + (len[0] >> 2) : lane + 1;
+  if (!lanes && !(lv[0] | lv[1] | lv[2] | lv[3])) continue;
+  if (lanes && !__any(lv[0] | lv[1] | lv[2] | lv[3])) continue;
   for_rows(t, [&](int row) {
     const double* ur = u + size_t(row) * t.rp;
+    if (lanes) {
+      V4<double> uv = {}, ov = {};
+      if (g < t.G) {
+        uv = ld4s(ur + c0);
+        ov = mixed ? ld4s(out + size_t(row) * t.rp + c0) : uv;
+      }
+      double v = 0.0;
+      for (int j = 0; j < 4; ++j) v = fma(uv.v[j], uv.v[j], v);
+      for (int d = 1; d < 64 && __any(lane + d < le); d <<= 1) {
+        const double w = __shfl_down(v, d);
+        if (lane + d < le) v += w;
+      }
+      const double S = __shfl(v, ls);
+      if (g < t.G) {
+        for (int j = 0; j < 4; ++j)
+          if (lv[j]) ov.v[j] = uv.v[j] * exp(-cf[j] * (S - uv.v[j] * uv.v[j]));
+        st4s(out + size_t(row) * t.rp + c0, ov);
+      }
+      return;
+    }
     V4<double> uv = ld4s(ur + c0), ov = uv;
     // columns that are not live keep the state's value
     if (mixed) ov = ld4s(out + size_t(row) * t.rp + c0);

@@ -102,3 +102,24 @@ def test_zero_steps_and_many_restarts(gpu):
         assert rel(u[2 * r:2 * r + 2], ref["u"]) < 1e-10
         assert abs(s_eps[r] - ref["s_eps"][0]) < 1e-10 * ref["s_eps"][0]
         assert abs(e[r] - ref["energy"][0]) < 1e-10 * ref["energy"][0]
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_wide_batch_node_step_paths(gpu, precision, bar):
+    """A batch wider than one 256-column tile (one row per wavefront): 64
+    restarts of m = 4 fill tile 0 (the node step's cross-lane sums), then m =
+    12 restarts straddle the next tile edges (the general path) and m = 3 ones
+    break the 4-column alignment; sampled restarts against the oracle."""
+    v, f = icosphere(3)
+    n = v.shape[0]
+    ms = [4] * 64 + [12] * 24 + [3] * 5
+    eps = [0.1] * len(ms)
+    u0 = uniform_u0(44, 1, sum(ms), n)
+    print(f"wide batch ({sum(ms)} columns), 15 steps, {precision}", flush=True)
+    out = run_gpu(v, f, ms, eps, u0, 1e-3, 15, precision)
+    prob = flow.Problem(v, f, 1e-3)
+    col0 = np.concatenate([[0], np.cumsum(ms)])
+    for r in (0, 63, 64, 70, 87, 88, 92):
+        ref = flow.run(prob, u0[col0[r]:col0[r + 1]], [ms[r]], [0.1], 15)
+        assert rel(out["u"][col0[r]:col0[r + 1]], ref["u"]) < bar
+        assert abs(out["energy"][r] - ref["energy"][0]) < bar * ref["energy"][0]
