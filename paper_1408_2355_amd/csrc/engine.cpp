@@ -154,6 +154,7 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
 
     StepArgs& a = args_;
     a.t = t;   // streaming kernels: widest tiling (most workgroups in flight)
+    a.ts = make_tile(n, rp_, 64, 1, 256);
     a.tm = t;   // gathering kernels: replaced by the autotuner's picks
     a.t64 = t;
     a.W = mesh_->W;

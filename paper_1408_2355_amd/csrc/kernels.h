@@ -42,6 +42,8 @@ struct CgCols {
 
 struct StepArgs {
   Tile t;   // tiling of the streaming row kernels (no neighbour gathers)
+  Tile ts;  // tiling of the streaming kernels without column sums (node step,
+            // ring fold, extrapolation, scaling): more workgroups in flight
   Tile tm;  // tiling of the CG matrix product and the refinement update (gathers
             // float32 in mixed precision); same n, rp
   Tile t64;  // tiling of the kernels that gather float64 values (solve set-up,

@@ -573,7 +573,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir_ring(StepArgs a, int next,
 __global__ __launch_bounds__(kBlock) void k_materialize(StepArgs a, RingArgs ra,
                                                         const double* __restrict__ ah,
                                                         float* __restrict__ d) {
-  const Tile& t = a.t;
+  const Tile& t = a.ts;
   for (int ct = 0; ct < t.nct; ++ct) {
     const int g = ct * t.tg + threadIdx.x % t.tg;
     if (g >= t.G) continue;
@@ -603,7 +603,7 @@ __global__ __launch_bounds__(kBlock) void k_materialize(StepArgs a, RingArgs ra,
 // y = sum_j e.c[j] e.x[j] on the live columns, 0 elsewhere.  y may be one of
 // the sources (each element is read before it is written, by the same thread).
 __global__ __launch_bounds__(kBlock) void k_extrap(StepArgs a, ExtrapArgs e, float* y) {
-  const Tile& t = a.t;
+  const Tile& t = a.ts;
   for (int ct = 0; ct < t.nct; ++ct) {
     const int g = ct * t.tg + threadIdx.x % t.tg;
     if (g >= t.G) continue;
@@ -988,7 +988,7 @@ __global__ void k_red_outer(StepArgs a, int oslot, int onext) {
 // restart's components, u^_i = u~_i exp(-(2 tau/eps^2)(S - u~_i^2)).
 __global__ __launch_bounds__(kBlock) void k_nodal(StepArgs a, const double* __restrict__ u,
                                                   double* __restrict__ out, int keep) {
-  const Tile& t = a.t;
+  const Tile& t = a.ts;
   for (int ct = 0; ct < t.nct; ++ct) {
   const int g = ct * t.tg + threadIdx.x % t.tg;
   if (t.tg != 64 && g >= t.G) continue;  // (tg == 64: the whole wavefront stays)
@@ -1162,7 +1162,7 @@ __global__ __launch_bounds__(kBlock) void k_region_graph(StepArgs a, const int32
 }
 
 __global__ __launch_bounds__(kBlock) void k_scale(StepArgs a, const double* v, double* u) {
-  const Tile& t = a.t;
+  const Tile& t = a.ts;
   for (int ct = 0; ct < t.nct; ++ct) {
   const int g = ct * t.tg + threadIdx.x % t.tg;
   if (g >= t.G) continue;
@@ -2219,7 +2219,7 @@ void materialize(const StepArgs& a, float* const* pring, const double* ah, int f
     ra.p[q] = pring[sl];
     ra.row[q] = sl;
   }
-  hipLaunchKernelGGL(k_materialize, dim3(a.t.nblk), dim3(kBlock), 0, s, a, ra, ah, d);
+  hipLaunchKernelGGL(k_materialize, dim3(a.ts.nblk), dim3(kBlock), 0, s, a, ra, ah, d);
   SP_LAUNCH_CHECK();
 }
 
@@ -2271,7 +2271,7 @@ void outer_residual(const StepArgs& a, int o, double* r64, const float* d, hipSt
 }
 
 void extrap(const StepArgs& a, const ExtrapArgs& e, float* y, hipStream_t s) {
-  hipLaunchKernelGGL(k_extrap, dim3(a.t.nblk), dim3(kBlock), 0, s, a, e, y);
+  hipLaunchKernelGGL(k_extrap, dim3(a.ts.nblk), dim3(kBlock), 0, s, a, e, y);
   SP_LAUNCH_CHECK();
 }
 
@@ -2282,7 +2282,7 @@ void red_outer(const StepArgs& a, int o, hipStream_t s) {
 }
 
 void nodal(const StepArgs& a, const double* u, double* out, bool keep, hipStream_t s) {
-  hipLaunchKernelGGL(k_nodal, dim3(a.t.nblk), dim3(kBlock), 0, s, a, u, out, int(keep));
+  hipLaunchKernelGGL(k_nodal, dim3(a.ts.nblk), dim3(kBlock), 0, s, a, u, out, int(keep));
   SP_LAUNCH_CHECK();
 }
 
@@ -2322,7 +2322,7 @@ void multipliers(const StepArgs& a, const SepsPlan& sp, const int32_t* tri, cons
 }
 
 void scale(const StepArgs& a, const double* v, double* u, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale, dim3(a.t.nblk), dim3(kBlock), 0, s, a, v, u);
+  hipLaunchKernelGGL(k_scale, dim3(a.ts.nblk), dim3(kBlock), 0, s, a, v, u);
   SP_LAUNCH_CHECK();
 }
 
