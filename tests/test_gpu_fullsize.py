@@ -20,6 +20,9 @@ the same configuration with the S_eps kernel the
 timing picks; restart 0 of the m = 8 group (the oracle's cost grows with m
 and the mesh: a sparse LU of the 262144-vertex torus alone takes ~40 s) is
 checked against the oracle, E = sum lambda + S_eps for every restart.
+
+The largest configuration (icosphere level 8, 1024 columns) runs two steps
+with restart 0 checked against the oracle.
 """
 import os
 
@@ -163,3 +166,41 @@ def test_other_batches_match_oracle_on_sampled_restarts(kind):
         assert rel(lam[col0[r]:col0[r + 1]], ref["lam"]) < 1e-5
         assert abs(s_eps[r] - ref["s_eps"][0]) < 1e-5 * ref["s_eps"][0]
         assert abs(e[r] - ref["energy"][0]) < 1e-5 * ref["energy"][0]
+
+
+def test_largest_config_level8_sphere():
+    """The largest serving configuration: icosphere level 8 (655362 vertices),
+    32 restarts of m = 32 (1024 columns, 5.4 GB per float64 vector), mixed
+    precision, two steps; restart 0 against the oracle (1e-5) and E = sum
+    lambda + S_eps for every restart."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    v, f = icosphere(8)
+    n = v.shape[0]
+    groups = [(5032, 32, 32)]
+    u0, ms = batch_u0(n, groups)
+    mesh = sp.Mesh(v, f)
+    print(f"level 8 sphere, {int(ms.sum())} columns, 2 steps", flush=True)
+    prm = sp.params(TAU, precision="mixed", n_steps=1, energy_every=1, cg_rtol=1e-10,
+                    inner_rtol=1e-6, max_outer=8, cg_max_iter=500, check_every=8, extrapolate=5)
+    st = sp.State(mesh, prm, ms, np.full(ms.size, EPS), u0)
+    try:
+        assert st.step(2) == sp.SP_OK
+        lam, s_eps, e = st.energy()
+        u, _ = st.read()
+        u_r0 = u[:32].copy()
+        del u
+    finally:
+        st.close()
+        mesh.close()
+    lo = 0
+    for i, m in enumerate(ms):
+        assert abs(e[i] - (lam[lo:lo + m].sum() + s_eps[i])) <= 1e-12 * abs(e[i])
+        lo += m
+    print("  oracle factorisation (level 8)", flush=True)
+    prob = flow.Problem(v, f, TAU)
+    ref = flow.run(prob, u0[:32], [32], [EPS], 2)
+    assert rel(u_r0, ref["u"]) < 1e-5
+    assert rel(lam[:32], ref["lam"]) < 1e-5
+    assert abs(s_eps[0] - ref["s_eps"][0]) < 1e-5 * ref["s_eps"][0]
+    assert abs(e[0] - ref["energy"][0]) < 1e-5 * ref["energy"][0]
