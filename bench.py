@@ -409,7 +409,7 @@ def main():
 
     if not args.no_cpu:
         log("[bench] cpu oracle sample")
-        out["cpu_baseline"] = cpu_baseline(v, f, groups, eps, tau)
+        out["cpu_baseline"] = cpu_baseline(v, f, groups, eps, tau, steps=3)
 
     st.close()
     mesh.close()
