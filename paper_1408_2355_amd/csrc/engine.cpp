@@ -96,6 +96,8 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     r64_.alloc(nv);
     // small batches run whole steps in one workgroup (float64 CG) unless
     // SEGPART_SMALL=0
+    const char* gr_env = std::getenv("SEGPART_GRAPH");
+    graph_on_ = !(gr_env && std::strcmp(gr_env, "0") == 0);
     const char* sm_env = std::getenv("SEGPART_SMALL");
     small_ = nv <= size_t(kSmallMaxValues) && rp_ <= kSmallMaxCols &&
              nres_p_ <= kSmallMaxRestarts && !(sm_env && std::strcmp(sm_env, "0") == 0);
@@ -253,6 +255,8 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
 
 Solver::~Solver() {
   if (!detached_ || own_stream_) (void)hipStreamSynchronize(s_);
+  for (auto& g : cg_graph_)
+    if (g) (void)hipGraphExecDestroy(g);
   for (auto& e : ev_)
     for (auto x : e) (void)hipEventDestroy(x);
   if (h_poll_) (void)hipHostFree(h_poll_);
@@ -634,10 +638,18 @@ void Solver::heat_mixed() {
     // inner CG in direction-ring form: d is formed from the stored
     // directions when the ring fills and after the last iteration
     int flushed = 0, last = 0;
-    for (int it = 0; it < prm_.cg_max_iter; ++it) {
-      k::cg_iter_ring(args_, it, r32_.p, pring_, q32_.p, ah_.p, d32_.p, &flushed, s_,
-                      prof_events());
-      last = it + 1;
+    const bool blocks = graph_on_ && !prof_ && s_ != nullptr && prm_.check_every == kPRing;
+    for (int it = 0; it < prm_.cg_max_iter;) {
+      if (blocks && it % kPRing == 0 && it + kPRing <= prm_.cg_max_iter) {
+        cg_block(flushed);
+        flushed = 1;
+        it += kPRing;
+      } else {
+        k::cg_iter_ring(args_, it, r32_.p, pring_, q32_.p, ah_.p, d32_.p, &flushed, s_,
+                        prof_events());
+        ++it;
+      }
+      last = it;
       if (prm_.check_every > 0 && last % prm_.check_every == 0 && last < prm_.cg_max_iter)
         if (poll(ring_.p + last % kRing) == 0) break;
     }
@@ -663,6 +675,39 @@ void Solver::heat_mixed() {
     n_prev_ = std::min(n_prev_ + 1, q);
   }
   heat_x_ = x;
+}
+
+void Solver::cg_block(int flushed) {
+  const int v = flushed ? 1 : 0;
+  if (cg_graph_[v] && std::memcmp(&cg_graph_args_[v], &args_, sizeof(StepArgs)) != 0) {
+    SP_HIP(hipGraphExecDestroy(cg_graph_[v]));
+    cg_graph_[v] = nullptr;
+  }
+  if (!cg_graph_[v]) {
+    // iterations 0..kPRing-1 use the same ring slots as any block that
+    // starts at a multiple of kPRing (kRing divides kPRing)
+    static_assert(kPRing % kRing == 0, "ring periods");
+    hipGraph_t g = nullptr;
+    SP_HIP(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
+    try {
+      int f = flushed;
+      for (int i = 0; i < kPRing; ++i)
+        k::cg_iter_ring(args_, i, r32_.p, pring_, q32_.p, ah_.p, d32_.p, &f, s_, nullptr);
+    } catch (...) {
+      (void)hipStreamEndCapture(s_, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    SP_HIP(hipStreamEndCapture(s_, &g));
+    hipError_t e = hipGraphInstantiate(&cg_graph_[v], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      cg_graph_[v] = nullptr;
+      throw Error(SP_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    std::memcpy(&cg_graph_args_[v], &args_, sizeof(StepArgs));
+  }
+  SP_HIP(hipGraphLaunch(cg_graph_[v], s_));
 }
 
 void Solver::heat() {

@@ -175,6 +175,17 @@ class Solver {
   // of scaling; the next solve's first update and the S_eps kernels apply the
   // factor as they read u_.  Anything else that reads u_ or changes the live
   // masks calls flush_scale() first.
+  // The float32 inner CG in blocks of kPRing iterations (the polling period)
+  // replayed from a captured HIP graph: one launch instead of 5 kPRing.
+  // Variant [f]: f = 1 once the direction ring has been folded before (the
+  // block's last iteration folds it again, accumulating).  Re-captured when
+  // args_ has changed since the capture (the kernels take it by value).
+  // SEGPART_GRAPH=0 turns this off; never used while profiling, on the
+  // legacy default stream, or with another polling period.
+  void cg_block(int flushed);
+  bool graph_on_ = true;
+  hipGraphExec_t cg_graph_[2] = {nullptr, nullptr};
+  StepArgs cg_graph_args_[2];
   bool u_pending_ = false;
   DevBuf<uint8_t> mask_;  // [n][rp] region mask (set_region_mask)
   double* node_out_ = nullptr;  // where the last node step wrote (u_ or r64_)
