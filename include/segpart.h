@@ -46,7 +46,7 @@ extern "C" {
 #endif
 
 #define SP_VERSION_MAJOR 1
-#define SP_VERSION_MINOR 0
+#define SP_VERSION_MINOR 1  /* 1.1: continuation, partition post-processing, multipliers */
 
 enum sp_status {
   SP_OK = 0,

@@ -30,7 +30,7 @@ def test_header_declares_and_library_exports_every_entry_point():
 
 
 def test_version_and_defaults():
-    assert sp.sp_version() == (1, 0)
+    assert sp.sp_version() == (1, 1)
     p = sp.params(5e-5)
     assert p.tau == 5e-5 and p.energy_every == 2000 and p.precision == sp.SP_MIXED
     assert p.cg_rtol == 1e-10 and p.check_every == 8
