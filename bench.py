@@ -187,8 +187,8 @@ def eps_study(args, sp):
     from workloads import eps_study_levels, icosphere, project_sphere, uniform_u0
     levels = eps_study_levels(args.eps_study)
     v, f = icosphere(args.eps_study_mesh)
-    m = 3
-    u0 = uniform_u0(7, 1, m, v.shape[0])
+    m, nres = 3, args.eps_study_restarts
+    u0 = uniform_u0(7, nres, m, v.shape[0])
     mesh = sp.Mesh(v, f)
     prm = sp.params(levels[0][1], n_steps=0, stop_tol=1e-6, max_steps=200000,
                     precision="mixed", cg_rtol=1e-10, inner_rtol=args.inner_rtol,
@@ -196,8 +196,22 @@ def eps_study(args, sp):
     log(f"[bench] eps study: {len(levels)} levels from icosphere level {args.eps_study_mesh} "
         f"({v.shape[0]} vertices)")
     t0 = time.perf_counter()
-    rc, res, lam, fin, u_fin = sp.continue_levels(mesh, prm, m, u0, levels, project_sphere)
+    def progress(level, rs):
+        e = [r["energy"] for r in rs]
+        log(f"[bench]   level {level} done: n {rs[0]['n_vert']}, {rs[0]['seconds']:.1f} s, "
+            f"steps {min(r['steps'] for r in rs)}..{max(r['steps'] for r in rs)}, "
+            f"E {min(e):.4f}..{max(e):.4f}")
+
+    rc, res_all, lam_all, fin, u_all = sp.continue_levels(mesh, prm, m, u0, levels, project_sphere,
+                                                          n_restarts=nres, on_level=progress)
     wall = time.perf_counter() - t0
+    # the restart with the lowest final energy is the study's answer
+    best = int(np.argmin([res_all[-1][r]["energy"] for r in range(nres)]))
+    res = [lvl[best] for lvl in res_all]
+    lam = lam_all[:, best * m:(best + 1) * m]
+    u_fin = u_all[best * m:(best + 1) * m]
+    total_steps = sum(x["steps"] for lvl in res_all for x in lvl)
+    cdof_all = sum(float(x["steps"]) * x["n_vert"] * m for lvl in res_all for x in lvl)
     # the final partition, read sharply: the first Dirichlet eigenvalue of each
     # region of its argmax labels (Problem 1.1's energy, no eps in it)
     last = fin if fin is not None else mesh
@@ -214,9 +228,8 @@ def eps_study(args, sp):
         f"{np.round(lam_in, 5)}], sum in [{lam_reg.sum():.5f}, {lam_in.sum():.5f}] (45/4 = 11.25), "
         f"{its} + {its_in} inverse iterations, {t_eig:.1f} s")
     table = np.loadtxt(os.path.join(ROOT, "tests", "golden", "tab_u_eps.txt"), ndmin=2)
-    rows, cdof = [], 0.0
+    rows = []
     for i, ((eps, tau, ref), r) in enumerate(zip(levels, res)):
-        cdof += float(r["steps"]) * r["n_vert"] * m
         row = dict(eps=eps, tau=tau, n_vert=r["n_vert"], steps=r["steps"],
                    energy=r["energy"], s_eps=r["s_eps"], seconds=round(r["seconds"], 3),
                    lam=[float(x) for x in lam[i]])
@@ -237,13 +250,17 @@ def eps_study(args, sp):
     mesh.close()
     print(json.dumps({
         "metric": "eps study (continuation to the stopping rule): component-DOF updates/s",
-        "value": cdof / wall, "unit": "cdof/s", "n_gpus": 1, "steps": int(sum(r["steps"] for r in res)),
+        "value": cdof_all / wall, "unit": "cdof/s", "n_gpus": 1, "steps": int(total_steps),
         "warmup": 0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": f"eps study: unit sphere from icosahedral level {args.eps_study_mesh}, "
-                               f"m 3, {len(levels)} levels (eps 0.5 halving, tau 8e-4 / sqrt(2) per "
-                               "level, 4-fold refinement before levels 2, 4, ...), stop |dE| < 1e-6 "
-                               "every M_tau = 0.1 / tau steps, mixed precision"},
+                               f"{nres} random restart(s) of m 3 in one batch, {len(levels)} levels "
+                               "(eps 0.5 halving, tau 8e-4 / sqrt(2) per level, 4-fold refinement "
+                               "before levels 2, 4, ...), stop |dE| < 1e-6 every M_tau = 0.1 / tau "
+                               "steps per restart, mixed precision; levels reported for the restart "
+                               "with the lowest final energy"},
+        "best_restart": best,
+        "final_energy_per_restart": [float(res_all[-1][r]["energy"]) for r in range(nres)],
         "wall_s": wall, "status": int(rc), "levels": rows,
         "final_partition": {"region_lambda_1_plain": [float(x) for x in lam_reg],
                             "region_lambda_1_interior": [float(x) for x in lam_in],
@@ -283,6 +300,8 @@ def main():
                          "--eps-study-mesh, m = 3, each level to the stopping rule; prints the "
                          "per-level energies beside the paper's and the whole study's throughput")
     ap.add_argument("--eps-study-mesh", type=int, default=5)
+    ap.add_argument("--eps-study-restarts", type=int, default=1,
+                    help="random restarts run together through the study (the best is reported)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")

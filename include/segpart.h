@@ -326,7 +326,7 @@ typedef struct {
 
 typedef struct {
   int64_t n_vert;   /* vertices of the level's mesh                             */
-  int64_t steps;    /* time steps the level took                                */
+  int64_t steps;    /* time steps the restart took on the level                 */
   double energy;    /* E = sum lambda + S_eps at the level's final state        */
   double s_eps;     /* S_eps of equation (Seps-u) there                         */
   double seconds;   /* wall time of the level (refinement included)             */
@@ -334,22 +334,32 @@ typedef struct {
   int32_t reserved;
 } sp_level_result;
 
-/* Level loop for one restart of m components.  prm supplies the precision,
- * the CG settings, stop_tol and max_steps; its tau and energy_every are
- * replaced per level (tau = levels[l].tau, energy_every = M_tau); with
- * prm->n_steps > 0 every level runs exactly that many steps instead of the
- * stopping rule.  u0 [m][n_vert of mesh0] (host, normalised on upload like
- * sp_solve's).  Outputs (host): results [n_levels]; lambda [n_levels][m]
- * (nullable); *final_mesh (nullable) receives the last level's mesh as a new
- * handle when any level refined, else NULL; u_final [m][n_vert of the last
+/* Level loop for n_restarts independent restarts of m components each, run
+ * as one batch (the paper starts from random states; several starts and the
+ * best final energy guard against local minima).  prm supplies the
+ * precision, the CG settings, stop_tol and max_steps; its tau and
+ * energy_every are replaced per level (tau = levels[l].tau, energy_every =
+ * M_tau), eps = levels[l].eps for every restart; each restart stops on its
+ * own when the stopping rule holds for it (the batch level ends when all have
+ * stopped); with prm->n_steps > 0 every level runs exactly that many steps.
+ * u0 [n_restarts * m][n_vert of mesh0] (host, restart-major, normalised on
+ * upload like sp_solve's).  Outputs (host): results [n_levels][n_restarts]
+ * (steps, energy and s_eps per restart; n_vert, seconds and converged per
+ * level, repeated); lambda [n_levels][n_restarts * m] (nullable);
+ * *final_mesh (nullable) receives the last level's mesh as a new handle when
+ * any level refined, else NULL; u_final [n_restarts * m][n_vert of the last
  * level] (nullable; the caller sizes it, e.g. n_vert grows to
  * n + (3/2) n_tri per refinement of a closed surface).  project as in
- * sp_mesh_refine.  Returns SP_ENOCONV (after writing outputs) if some linear
+ * sp_mesh_refine.  on_level (nullable) is called on the calling thread after
+ * each level with the level index and its n_restarts results (progress of a
+ * long study).  Returns SP_ENOCONV (after writing outputs) if some linear
  * solve hit its cap. */
-int sp_continue(const sp_mesh* mesh0, const sp_params* prm, int32_t m, const double* u0,
-                int32_t n_levels, const sp_level* levels, sp_project_fn project, void* ctx,
-                sp_level_result* results, double* lambda, sp_mesh** final_mesh,
-                double* u_final);
+typedef void (*sp_level_fn)(int32_t level, const sp_level_result* results, void* ctx);
+int sp_continue(const sp_mesh* mesh0, const sp_params* prm, int32_t n_restarts, int32_t m,
+                const double* u0, int32_t n_levels, const sp_level* levels,
+                sp_project_fn project, void* ctx, sp_level_result* results, double* lambda,
+                sp_mesh** final_mesh, double* u_final, sp_level_fn on_level,
+                void* level_ctx);
 
 /* ------------------------------------------------------------ partitions --
  * Post-processing of a computed partition given as vertex labels (e.g. the

@@ -463,15 +463,17 @@ int sp_prolong(const sp_mesh* fine, int32_t n_cols, const double* u_coarse, doub
   });
 }
 
-int sp_continue(const sp_mesh* mesh0, const sp_params* prm, int32_t m, const double* u0,
-                int32_t n_levels, const sp_level* levels, sp_project_fn project, void* ctx,
-                sp_level_result* results, double* lambda, sp_mesh** final_mesh,
-                double* u_final) {
+int sp_continue(const sp_mesh* mesh0, const sp_params* prm, int32_t n_restarts, int32_t m,
+                const double* u0, int32_t n_levels, const sp_level* levels,
+                sp_project_fn project, void* ctx, sp_level_result* results, double* lambda,
+                sp_mesh** final_mesh, double* u_final, sp_level_fn on_level,
+                void* level_ctx) {
   return guard([&] {
     if (final_mesh) *final_mesh = nullptr;
     SP_REQUIRE(mesh0 && mesh0->m && prm, SP_EINVAL, "NULL mesh or params");
-    sp::ContinuationOut o = sp::run_continuation(mesh0->m.get(), *prm, m, u0, n_levels, levels,
-                                                 project, ctx, results, lambda, u_final);
+    sp::ContinuationOut o =
+        sp::run_continuation(mesh0->m.get(), *prm, n_restarts, m, u0, n_levels, levels, project,
+                             ctx, results, lambda, u_final, on_level, level_ctx);
     if (final_mesh && o.mesh) {
       std::unique_ptr<sp_mesh> h(new sp_mesh());
       h->m = std::move(o.mesh);

@@ -70,11 +70,16 @@ double now_s() {
 }
 }  // namespace
 
-ContinuationOut run_continuation(Mesh* mesh0, const sp_params& prm, int m, const double* u0,
-                                 int nlev, const sp_level* levels, ProjectFn project, void* ctx,
-                                 sp_level_result* results, double* lambda, double* u_final) {
+ContinuationOut run_continuation(Mesh* mesh0, const sp_params& prm, int nres, int m,
+                                 const double* u0, int nlev, const sp_level* levels,
+                                 ProjectFn project, void* ctx, sp_level_result* results,
+                                 double* lambda, double* u_final, sp_level_fn on_level,
+                                 void* level_ctx) {
   SP_REQUIRE(mesh0 && u0 && levels && results, SP_EINVAL, "continue: NULL argument");
-  SP_REQUIRE(m >= 1 && nlev >= 1, SP_EINVAL, "continue: need m >= 1 and n_levels >= 1");
+  SP_REQUIRE(m >= 1 && nres >= 1 && nlev >= 1, SP_EINVAL,
+             "continue: need m >= 1, n_restarts >= 1 and n_levels >= 1");
+  SP_REQUIRE(int64_t(nres) * m <= (int64_t(1) << 24), SP_EINVAL, "continue: too many columns");
+  const int R = nres * m;
   SP_REQUIRE(levels[0].refine == 0, SP_EINVAL, "continue: level 0 cannot refine");
   for (int l = 0; l < nlev; ++l)
     SP_REQUIRE(std::isfinite(levels[l].eps) && levels[l].eps > 0 && std::isfinite(levels[l].tau) &&
@@ -91,14 +96,14 @@ ContinuationOut run_continuation(Mesh* mesh0, const sp_params& prm, int m, const
       (void)hipStreamDestroy(s);
     }
   } guard{s};
-  DevBuf<double> u(size_t(m) * mesh->n);
+  DevBuf<double> u(size_t(R) * mesh->n);
   SP_HIP(hipMemcpyAsync(u.p, u0, u.bytes(), hipMemcpyHostToDevice, s));
   for (int l = 0; l < nlev; ++l) {
     const double t0 = now_s();
     if (levels[l].refine) {
       std::unique_ptr<Mesh> fine(mesh_refine(*mesh, project, ctx));
-      DevBuf<double> uf(size_t(m) * fine->n);
-      k::prolong(*fine, m, u.p, uf.p, s);
+      DevBuf<double> uf(size_t(R) * fine->n);
+      k::prolong(*fine, R, u.p, uf.p, s);
       SP_HIP(hipStreamSynchronize(s));
       u = std::move(uf);
       out.mesh = std::move(fine);  // frees the previous refined mesh
@@ -108,8 +113,8 @@ ContinuationOut run_continuation(Mesh* mesh0, const sp_params& prm, int m, const
     p.tau = levels[l].tau;
     p.energy_every = std::max<int64_t>(1, std::llround(0.1 / p.tau));
     BatchSpec spec;
-    spec.m = {m};
-    spec.eps = {levels[l].eps};
+    spec.m.assign(nres, m);
+    spec.eps.assign(nres, levels[l].eps);
     Solver S(mesh, p, spec, &s);
     S.record_history = p.n_steps == 0;  // the stopping rule reads the energies
     S.upload_device(u.p, true, true);
@@ -117,22 +122,25 @@ ContinuationOut run_continuation(Mesh* mesh0, const sp_params& prm, int m, const
       S.step(p.n_steps);
     else
       S.run_to_stop();
-    double seps = 0, E = 0;
-    std::vector<double> lam(m);
-    S.energy_to_host(lam.data(), &seps, &E);
+    std::vector<double> lam(R), seps(nres), E(nres);
+    S.energy_to_host(lam.data(), seps.data(), E.data());
     S.download_device(u.p);
     SP_HIP(hipStreamSynchronize(s));
     const sp_stats st = S.stats();
-    sp_level_result& r = results[l];
-    r.n_vert = mesh->n;
-    r.steps = st.steps_done;
-    r.energy = E;
-    r.s_eps = seps;
-    r.converged = st.converged;
-    r.reserved = 0;
-    r.seconds = now_s() - t0;
-    if (lambda) std::copy(lam.begin(), lam.end(), lambda + size_t(l) * m);
+    const double secs = now_s() - t0;
+    for (int r = 0; r < nres; ++r) {
+      sp_level_result& o = results[size_t(l) * nres + r];
+      o.n_vert = mesh->n;
+      o.steps = p.n_steps > 0 ? p.n_steps : S.restart_steps[r];
+      o.energy = E[r];
+      o.s_eps = seps[r];
+      o.converged = st.converged;
+      o.reserved = 0;
+      o.seconds = secs;
+    }
+    if (lambda) std::copy(lam.begin(), lam.end(), lambda + size_t(l) * R);
     out.converged = out.converged && st.converged;
+    if (on_level) on_level(l, results + size_t(l) * nres, level_ctx);
   }
   if (u_final) {
     SP_HIP(hipMemcpyAsync(u_final, u.p, u.bytes(), hipMemcpyDeviceToHost, s));

@@ -68,6 +68,8 @@ class sp_level_result(C.Structure):
 
 # void (*)(double* xyz, int64_t n, void* ctx)
 PROJECT_FN = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.c_int64, C.c_void_p)
+# void (*)(int32_t level, const sp_level_result* results, void* ctx)
+LEVEL_FN = C.CFUNCTYPE(None, C.c_int32, C.POINTER(sp_level_result), C.c_void_p)
 
 _lib = None
 
@@ -113,9 +115,9 @@ _SIGS = {
     "sp_mesh_refine": (C.c_int, [P, PROJECT_FN, P, PP]),
     "sp_mesh_parents": (C.c_int, [P, I32, I64]),
     "sp_prolong": (C.c_int, [P, C.c_int32, D, D]),
-    "sp_continue": (C.c_int, [P, C.POINTER(sp_params), C.c_int32, D, C.c_int32,
+    "sp_continue": (C.c_int, [P, C.POINTER(sp_params), C.c_int32, C.c_int32, D, C.c_int32,
                               C.POINTER(sp_level), PROJECT_FN, P, C.POINTER(sp_level_result),
-                              D, PP, D]),
+                              D, PP, D, LEVEL_FN, P]),
     "sp_region_eigen": (C.c_int, [P, C.c_int32, I32, I32, C.c_int32, D, C.c_double, C.c_double,
                                   C.c_int32, D, D, I32]),
     "sp_region_graph": (C.c_int, [P, C.c_int32, I32, I32, C.POINTER(C.c_uint8), I32]),
@@ -290,28 +292,40 @@ def sp_prolong(fine_h, u_coarse):
     return out
 
 
-def sp_continue(mesh_h, prm, m, u0, levels, project=None, want_u=True):
-    """levels: sequence of (eps, tau, refine).  Returns (status, results
-    [list of dicts], lambda [n_levels, m], final mesh handle or None, u_final)."""
+def sp_continue(mesh_h, prm, m, u0, levels, project=None, want_u=True, n_restarts=1,
+                on_level=None):
+    """levels: sequence of (eps, tau, refine); u0 [n_restarts * m, n];
+    on_level(level, [n_restarts result dicts]) is called after each level.
+    Returns (status, results [n_levels][n_restarts] dicts, lambda
+    [n_levels, n_restarts * m], final mesh handle or None, u_final)."""
     n0, t0, _, _ = sp_mesh_info(mesh_h)
     u0 = _f64(u0)
-    if u0.shape != (m, n0):
-        raise ValueError(f"u0 must have shape ({m}, {n0}), got {u0.shape}")
+    R = n_restarts * m
+    if u0.shape != (R, n0):
+        raise ValueError(f"u0 must have shape ({R}, {n0}), got {u0.shape}")
     lv = (sp_level * len(levels))()
     n, t = n0, t0
     for i, (eps, tau, ref) in enumerate(levels):
         lv[i].eps, lv[i].tau, lv[i].refine = float(eps), float(tau), int(bool(ref))
         if ref:  # closed surface: one new vertex per edge, 3 t / 2 edges
             n, t = n + 3 * t // 2, 4 * t
-    res = (sp_level_result * len(levels))()
-    lam = np.empty((len(levels), m))
-    u = np.empty((m, n)) if want_u else None
+    res = (sp_level_result * (len(levels) * n_restarts))()
+    lam = np.empty((len(levels), R))
+    u = np.empty((R, n)) if want_u else None
     fin = C.c_void_p()
     cb = _project_cb(project)
-    rc = _check(lib().sp_continue(mesh_h, C.byref(prm), m, _dp(u0), len(levels), lv, cb, None,
-                                  res, _dp(lam), C.byref(fin), _dp(u)),
+    if on_level is None:
+        lcb = LEVEL_FN()
+    else:
+        def _lcb(level, ptr, _ctx):
+            on_level(int(level), [ptr[r].as_dict() for r in range(n_restarts)])
+        lcb = LEVEL_FN(_lcb)
+    rc = _check(lib().sp_continue(mesh_h, C.byref(prm), n_restarts, m, _dp(u0), len(levels), lv,
+                                  cb, None, res, _dp(lam), C.byref(fin), _dp(u), lcb, None),
                 allow=(SP_ENOCONV,))
-    return rc, [r.as_dict() for r in res], lam, (fin if fin.value else None), u
+    out = [[res[l * n_restarts + r].as_dict() for r in range(n_restarts)]
+           for l in range(len(levels))]
+    return rc, out, lam, (fin if fin.value else None), u
 
 
 def sp_region_eigen(mesh_h, m, labels, u0=None, shift=1e3, tol=1e-12, max_iter=500,
@@ -381,7 +395,7 @@ class Mesh:
 
     def close(self):
         if getattr(self, "h", None):
-            lib().sp_mesh_destroy(self.h)
+            sp_mesh_destroy(self.h)
             self.h = None
 
     __del__ = close
@@ -391,10 +405,162 @@ def solve(mesh, prm, m, eps, u0, **kw):
     return sp_solve(mesh.h, prm, m, eps, u0, **kw)
 
 
-def continue_levels(mesh, prm, m, u0, levels, project=None, want_u=True):
+def continue_levels(mesh, prm, m, u0, levels, project=None, want_u=True, n_restarts=1,
+                    on_level=None):
     """sp_continue on a Mesh; the final mesh comes back as a Mesh (or None)."""
-    rc, res, lam, fin, u = sp_continue(mesh.h, prm, m, u0, levels, project, want_u)
+    rc, res, lam, fin, u = sp_continue(mesh.h, prm, m, u0, levels, project, want_u, n_restarts,
+                                       on_level)
     return rc, res, lam, (Mesh(handle=fin) if fin is not None else None), u
+
+
+# ------------------------------------------------------------------------
+# Entry points that the State and Server owners below use: one function per
+# C entry point, same name, handles passed as the first argument.
+
+def sp_last_error():
+    return lib().sp_last_error().decode()
+
+
+def sp_params_default(tau):
+    p = sp_params()
+    lib().sp_params_default(C.byref(p), float(tau))
+    return p
+
+
+def sp_mesh_destroy(h):
+    lib().sp_mesh_destroy(h)
+
+
+def sp_state_create(mesh_h, prm, m, eps, u0, stream=None):
+    n = sp_mesh_info(mesh_h)[0]
+    m, eps, u0 = _batch(m, eps, u0, n)
+    h = C.c_void_p()
+    s = None if stream is None else C.c_void_p(stream.cuda_stream)
+    _check(lib().sp_state_create(mesh_h, C.byref(prm), m.size, _ip(m), _dp(eps), _dp(u0), s,
+                                 C.byref(h)))
+    return h
+
+
+def sp_state_step(h, k=1):
+    return _check(lib().sp_state_step(h, int(k)), allow=(SP_ENOCONV,))
+
+
+def sp_state_stage(h, which):
+    _check(lib().sp_state_stage(h, int(which)))
+
+
+def sp_state_energy(h, R, nres):
+    lam, s, e = np.empty(R), np.empty(nres), np.empty(nres)
+    _check(lib().sp_state_energy(h, _dp(lam), _dp(s), _dp(e)))
+    return lam, s, e
+
+
+def sp_state_read(h, R, n):
+    u = np.empty((R, n))
+    k = C.c_int64()
+    _check(lib().sp_state_read(h, _dp(u), C.byref(k)))
+    return u, k.value
+
+
+def sp_state_write(h, u, step=0, normalise=False):
+    u = _f64(u)
+    _check(lib().sp_state_write(h, _dp(u), int(step), int(bool(normalise))))
+
+
+def sp_state_multipliers(h, R):
+    out = np.empty(R)
+    _check(lib().sp_state_multipliers(h, _dp(out)))
+    return out
+
+
+def sp_state_labels(h, nres, n):
+    a = np.empty((nres, n), np.int32)
+    b = np.empty_like(a)
+    _check(lib().sp_state_labels(h, _ip(a), _ip(b)))
+    return a, b
+
+
+def sp_state_history(h, r):
+    cnt = C.c_int64()
+    _check(lib().sp_state_history(h, r, 0, None, None, C.byref(cnt)))
+    k = np.empty(cnt.value, np.int64)
+    e = np.empty(cnt.value)
+    _check(lib().sp_state_history(h, r, cnt.value, _ip(k, I64), _dp(e), C.byref(cnt)))
+    return k, e
+
+
+def sp_state_stats(h):
+    st = sp_stats()
+    _check(lib().sp_state_stats(h, C.byref(st)))
+    return st.as_dict()
+
+
+def sp_state_profile(h, on=True):
+    _check(lib().sp_state_profile(h, int(bool(on))))
+
+
+def sp_state_kernel_time(h, which=SP_KERNEL_MATVEC):
+    n, ms, b = C.c_int64(), C.c_double(), C.c_double()
+    _check(lib().sp_state_kernel_time(h, int(which), C.byref(n), C.byref(ms), C.byref(b)))
+    return n.value, ms.value, b.value
+
+
+def sp_state_tiling(h):
+    a, b, c, us = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
+    _check(lib().sp_state_tiling(h, C.byref(a), C.byref(b), C.byref(c), C.byref(us)))
+    return dict(lanes_per_row=a.value, rows_per_chunk=b.value, groups_per_xcd=c.value,
+                matvec_us=us.value)
+
+
+def sp_state_destroy(h):
+    lib().sp_state_destroy(h)
+
+
+def sp_server_create(hbm_budget_bytes, max_batch_columns=0):
+    h = C.c_void_p()
+    _check(lib().sp_server_create(int(hbm_budget_bytes), int(max_batch_columns), C.byref(h)))
+    return h
+
+
+def sp_server_submit(h, mesh_h, prm, m, eps, u0):
+    n = sp_mesh_info(mesh_h)[0]
+    m, eps, u0 = _batch(m, eps, u0, n)
+    t = C.c_int64()
+    _check(lib().sp_server_submit(h, mesh_h, C.byref(prm), m.size, _ip(m), _dp(eps), _dp(u0),
+                                  C.byref(t)))
+    return t.value
+
+
+def sp_server_poll(h, ticket):
+    d = C.c_int32()
+    _check(lib().sp_server_poll(h, int(ticket), C.byref(d)))
+    return bool(d.value)
+
+
+def sp_server_wait(h, ticket, timeout_s=600.0):
+    return _check(lib().sp_server_wait(h, int(ticket), float(timeout_s)),
+                  allow=(SP_EAGAIN,)) == SP_OK
+
+
+def sp_server_fetch(h, ticket, R, nres, n):
+    out = dict(u=np.empty((R, n)), labels=np.empty((nres, n), np.int32), lam=np.empty(R),
+               s_eps=np.empty(nres), energy=np.empty(nres))
+    lat = C.c_double()
+    _check(lib().sp_server_fetch(h, int(ticket), _dp(out["u"]), _ip(out["labels"]),
+                                 _dp(out["lam"]), _dp(out["s_eps"]), _dp(out["energy"]),
+                                 C.byref(lat)))
+    out["latency_s"] = lat.value
+    return out
+
+
+def sp_server_stats(h):
+    p50, p99, cd, n = C.c_double(), C.c_double(), C.c_double(), C.c_int64()
+    _check(lib().sp_server_stats(h, C.byref(p50), C.byref(p99), C.byref(cd), C.byref(n)))
+    return dict(p50_s=p50.value, p99_s=p99.value, cdof_per_s=cd.value, completed=n.value)
+
+
+def sp_server_destroy(h):
+    lib().sp_server_destroy(h)
 
 
 class State:
@@ -402,80 +568,52 @@ class State:
 
     def __init__(self, mesh, prm, m, eps, u0, stream=None):
         self.mesh = mesh
-        self.m, self.eps, u0 = _batch(m, eps, u0, mesh.n_vert)
+        self.m, self.eps, _ = _batch(m, eps)
         self.R = int(self.m.sum())
-        h = C.c_void_p()
-        s = None if stream is None else C.c_void_p(stream.cuda_stream)
-        _check(lib().sp_state_create(mesh.h, C.byref(prm), self.m.size, _ip(self.m),
-                                     _dp(self.eps), _dp(u0), s, C.byref(h)))
-        self.h = h
+        self.h = sp_state_create(mesh.h, prm, m, eps, u0, stream)
 
     def step(self, k=1):
-        return _check(lib().sp_state_step(self.h, int(k)), allow=(SP_ENOCONV,))
+        return sp_state_step(self.h, k)
 
     def stage(self, which):
-        _check(lib().sp_state_stage(self.h, int(which)))
+        sp_state_stage(self.h, which)
 
     def energy(self):
-        lam, s, e = np.empty(self.R), np.empty(self.m.size), np.empty(self.m.size)
-        _check(lib().sp_state_energy(self.h, _dp(lam), _dp(s), _dp(e)))
-        return lam, s, e
+        return sp_state_energy(self.h, self.R, self.m.size)
 
     def read(self):
-        u = np.empty((self.R, self.mesh.n_vert))
-        k = C.c_int64()
-        _check(lib().sp_state_read(self.h, _dp(u), C.byref(k)))
-        return u, k.value
+        return sp_state_read(self.h, self.R, self.mesh.n_vert)
 
     def write(self, u, step=0, normalise=False):
-        u = _f64(u)
-        _check(lib().sp_state_write(self.h, _dp(u), int(step), int(bool(normalise))))
+        sp_state_write(self.h, u, step, normalise)
 
     def multipliers(self):
         """lambda_i^eps [sum m] of the current state."""
-        out = np.empty(self.R)
-        _check(lib().sp_state_multipliers(self.h, _dp(out)))
-        return out
+        return sp_state_multipliers(self.h, self.R)
 
     def labels(self):
-        a = np.empty((self.m.size, self.mesh.n_vert), np.int32)
-        b = np.empty_like(a)
-        _check(lib().sp_state_labels(self.h, _ip(a), _ip(b)))
-        return a, b
+        return sp_state_labels(self.h, self.m.size, self.mesh.n_vert)
 
     def history(self, r):
-        cnt = C.c_int64()
-        _check(lib().sp_state_history(self.h, r, 0, None, None, C.byref(cnt)))
-        k = np.empty(cnt.value, np.int64)
-        e = np.empty(cnt.value)
-        _check(lib().sp_state_history(self.h, r, cnt.value, _ip(k, I64), _dp(e), C.byref(cnt)))
-        return k, e
+        return sp_state_history(self.h, r)
 
     def stats(self):
-        st = sp_stats()
-        _check(lib().sp_state_stats(self.h, C.byref(st)))
-        return st.as_dict()
+        return sp_state_stats(self.h)
 
     def profile(self, on=True):
-        _check(lib().sp_state_profile(self.h, int(bool(on))))
+        sp_state_profile(self.h, on)
 
     def kernel_time(self, which=SP_KERNEL_MATVEC):
         """(launches, total ms, algorithmic bytes per launch) of a kernel class."""
-        n, ms, b = C.c_int64(), C.c_double(), C.c_double()
-        _check(lib().sp_state_kernel_time(self.h, int(which), C.byref(n), C.byref(ms),
-                                          C.byref(b)))
-        return n.value, ms.value, b.value
+        return sp_state_kernel_time(self.h, which)
 
     def tiling(self):
         """Tiling of the row-parallel kernels (see sp_state_tiling)."""
-        a, b, c, us = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
-        _check(lib().sp_state_tiling(self.h, C.byref(a), C.byref(b), C.byref(c), C.byref(us)))
-        return dict(lanes_per_row=a.value, rows_per_chunk=b.value, groups_per_xcd=c.value,
-                    matvec_us=us.value)
+        return sp_state_tiling(self.h)
 
     def close(self):
         if getattr(self, "h", None):
-            lib().sp_state_destroy(self.h)
+            sp_state_destroy(self.h)
             self.h = None
 
     __del__ = close
@@ -485,49 +623,33 @@ class Server:
     """Owner of an sp_server handle (continuous-batching request loop)."""
 
     def __init__(self, hbm_budget_bytes, max_batch_columns=0):
-        h = C.c_void_p()
-        _check(lib().sp_server_create(int(hbm_budget_bytes), int(max_batch_columns), C.byref(h)))
-        self.h = h
+        self.h = sp_server_create(hbm_budget_bytes, max_batch_columns)
         self._shape = {}
 
     def submit(self, mesh, prm, m, eps, u0):
-        m, eps, u0 = _batch(m, eps, u0, mesh.n_vert)
-        t = C.c_int64()
-        _check(lib().sp_server_submit(self.h, mesh.h, C.byref(prm), m.size, _ip(m), _dp(eps),
-                                      _dp(u0), C.byref(t)))
-        self._shape[t.value] = (int(m.sum()), m.size, mesh.n_vert)
-        return t.value
+        mm, _, _ = _batch(m, eps)
+        t = sp_server_submit(self.h, mesh.h, prm, m, eps, u0)
+        self._shape[t] = (int(mm.sum()), mm.size, mesh.n_vert)
+        return t
 
     def poll(self, ticket):
-        d = C.c_int32()
-        _check(lib().sp_server_poll(self.h, int(ticket), C.byref(d)))
-        return bool(d.value)
+        return sp_server_poll(self.h, ticket)
 
     def wait(self, ticket, timeout_s=600.0):
-        return _check(lib().sp_server_wait(self.h, int(ticket), float(timeout_s)),
-                      allow=(SP_EAGAIN,)) == SP_OK
+        return sp_server_wait(self.h, ticket, timeout_s)
 
     def fetch(self, ticket):
         R, nres, n = self._shape[ticket]
-        out = dict(u=np.empty((R, n)), labels=np.empty((nres, n), np.int32), lam=np.empty(R),
-                   s_eps=np.empty(nres), energy=np.empty(nres))
-        lat = C.c_double()
-        _check(lib().sp_server_fetch(self.h, int(ticket), _dp(out["u"]), _ip(out["labels"]),
-                                     _dp(out["lam"]), _dp(out["s_eps"]), _dp(out["energy"]),
-                                     C.byref(lat)))
-        out["latency_s"] = lat.value
+        out = sp_server_fetch(self.h, ticket, R, nres, n)
         del self._shape[ticket]
         return out
 
     def stats(self):
-        p50, p99, cd, n = C.c_double(), C.c_double(), C.c_double(), C.c_int64()
-        _check(lib().sp_server_stats(self.h, C.byref(p50), C.byref(p99), C.byref(cd),
-                                     C.byref(n)))
-        return dict(p50_s=p50.value, p99_s=p99.value, cdof_per_s=cd.value, completed=n.value)
+        return sp_server_stats(self.h)
 
     def close(self):
         if getattr(self, "h", None):
-            lib().sp_server_destroy(self.h)
+            sp_server_destroy(self.h)
             self.h = None
 
     __del__ = close

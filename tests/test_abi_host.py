@@ -29,6 +29,12 @@ def test_header_declares_and_library_exports_every_entry_point():
     assert set(names) == set(sp.EXPORTED)
 
 
+def test_binding_has_a_function_per_entry_point():
+    # the Python binding mirrors the C names one to one (marshalling only)
+    missing = [n for n in sp.EXPORTED if not callable(getattr(sp, n, None))]
+    assert missing == []
+
+
 def test_version_and_defaults():
     assert sp.sp_version() == (1, 1)
     p = sp.params(5e-5)

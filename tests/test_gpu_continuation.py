@@ -7,13 +7,14 @@
 * sp_prolong: bit-exact against the oracle's prolongation on random data
   (the mean of two float64 values, same operation order);
 * sp_continue with a fixed step count per level (so the comparison does not
-  depend on where the stopping rule lands): level 4 sphere, m = 3, three
-  levels of the eps study (the third refines to level 5, which runs on the
+  depend on where the stopping rule lands): level 4 sphere, two restarts of
+  m = 3 in one batch, each against the oracle run alone, three levels of the
+  eps study (the third refines to level 5, which runs on the
   multi-kernel path; levels 0-1 on the one-workgroup path), float64 (bar
   1e-10 on u, lambda, S_eps, E, CG rtol 1e-13) and mixed precision (bar 1e-5);
-* sp_continue with the stopping rule: the same three levels against the
-  oracle run to the rule, per level the same step count and E, S_eps within
-  1e-7 relative (float64).
+* sp_continue with the stopping rule: the same two restarts and three levels
+  against the oracle run to the rule, each restart stopping on its own: per
+  level the same step count and E, S_eps within 1e-7 relative (float64).
 """
 import numpy as np
 import pytest
@@ -94,41 +95,51 @@ def _levels():
 @pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("mixed", 1e-5)])
 def test_continue_fixed_steps_matches_oracle(gpu, precision, bar):
     v, f = icosphere(4)
-    m, steps = 3, 150
-    u0 = uniform_u0(7, 1, m, v.shape[0])
-    print(f"continue, 3 levels x {steps} steps, {precision}", flush=True)
+    m, steps, nres = 3, 150, 2
+    u0 = uniform_u0(7, nres, m, v.shape[0])
+    print(f"continue, {nres} restarts, 3 levels x {steps} steps, {precision}", flush=True)
     mesh = sp.Mesh(v, f)
     prm = sp.params(8e-4, n_steps=steps, precision=precision,
                     cg_rtol=1e-13 if precision == "fp64" else 1e-10)
-    rc, res, lam, fin, u = sp.continue_levels(mesh, prm, m, u0, _levels(), project_sphere)
+    rc, res, lam, fin, u = sp.continue_levels(mesh, prm, m, u0, _levels(), project_sphere,
+                                              n_restarts=nres)
     assert rc == sp.SP_OK
-    rows, xyz, tri, uref = cont.run(v, f, u0, m, _levels(), project_sphere, n_steps=steps)
-    assert fin is not None and fin.n_vert == xyz.shape[0]
-    for r, g, lg in zip(rows, res, lam):
-        assert g["n_vert"] == r["n_vert"] and g["steps"] == steps and g["converged"] == 1
-        assert abs(g["energy"] - r["energy"]) <= bar * abs(r["energy"])
-        assert abs(g["s_eps"] - r["s_eps"]) <= bar * abs(r["s_eps"])
-        assert rel(lg, r["lam"]) < bar
-    assert rel(u, uref) < bar
+    for r in range(nres):
+        rows, xyz, tri, uref = cont.run(v, f, u0[r * m:(r + 1) * m], m, _levels(), project_sphere,
+                                        n_steps=steps)
+        assert fin is not None and fin.n_vert == xyz.shape[0]
+        for lvl, ref in enumerate(rows):
+            g = res[lvl][r]
+            assert g["n_vert"] == ref["n_vert"] and g["steps"] == steps and g["converged"] == 1
+            assert abs(g["energy"] - ref["energy"]) <= bar * abs(ref["energy"])
+            assert abs(g["s_eps"] - ref["s_eps"]) <= bar * abs(ref["s_eps"])
+            assert rel(lam[lvl, r * m:(r + 1) * m], ref["lam"]) < bar
+        assert rel(u[r * m:(r + 1) * m], uref) < bar
     fin.close()
     mesh.close()
 
 
 def test_continue_stop_rule_matches_oracle(gpu):
+    """Two restarts to the stopping rule in one batch: each stops on its own
+    (its own step count per level) and matches the oracle run alone."""
     v, f = icosphere(4)
-    m = 3
-    u0 = uniform_u0(7, 1, m, v.shape[0])
-    print("continue, 3 levels to the stopping rule, fp64", flush=True)
+    m, nres = 3, 2
+    u0 = uniform_u0(7, nres, m, v.shape[0])
+    print("continue, 2 restarts, 3 levels to the stopping rule, fp64", flush=True)
     mesh = sp.Mesh(v, f)
     prm = sp.params(8e-4, n_steps=0, precision="fp64", cg_rtol=1e-13, stop_tol=1e-6)
-    rc, res, lam, fin, u = sp.continue_levels(mesh, prm, m, u0, _levels(), project_sphere)
+    rc, res, lam, fin, u = sp.continue_levels(mesh, prm, m, u0, _levels(), project_sphere,
+                                              n_restarts=nres)
     assert rc == sp.SP_OK
-    rows, *_ = cont.run(v, f, u0, m, _levels(), project_sphere, stop_tol=1e-6)
-    for r, g in zip(rows, res):
-        print(f"  eps {r['eps']}: steps {g['steps']} (oracle {r['steps']}), "
-              f"E {g['energy']:.6f} ({r['energy']:.6f})", flush=True)
-        assert g["steps"] == r["steps"]
-        assert abs(g["energy"] - r["energy"]) <= 1e-7 * r["energy"]
-        assert abs(g["s_eps"] - r["s_eps"]) <= 1e-7 * r["s_eps"]
+    for r in range(nres):
+        rows, *_ = cont.run(v, f, u0[r * m:(r + 1) * m], m, _levels(), project_sphere,
+                            stop_tol=1e-6)
+        for lvl, ref in enumerate(rows):
+            g = res[lvl][r]
+            print(f"  restart {r} eps {ref['eps']}: steps {g['steps']} (oracle {ref['steps']}), "
+                  f"E {g['energy']:.6f} ({ref['energy']:.6f})", flush=True)
+            assert g["steps"] == ref["steps"]
+            assert abs(g["energy"] - ref["energy"]) <= 1e-7 * ref["energy"]
+            assert abs(g["s_eps"] - ref["s_eps"]) <= 1e-7 * ref["s_eps"]
     fin.close()
     mesh.close()
