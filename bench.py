@@ -403,8 +403,9 @@ def main():
         # CG iteration, same step count as the batch (warmup + timed)
         pprm = sp.params(tau, precision="fp64", n_steps=1, energy_every=1, cg_rtol=1e-10,
                          cg_max_iter=2000, check_every=1)
-        cd, tt, errs = 0.0, 0.0, []
+        cd, tt, errs, lerrs, serrs = 0.0, 0.0, [], [], []
         r0 = 0                      # index of the group's first restart in the batch
+        c0 = 0                      # its first column
         for seed, nr, m in groups:
             u1 = uniform_u0(seed, 1, m, n)
             ps = sp.State(mesh, pprm, [m], [eps], u1)
@@ -413,16 +414,21 @@ def main():
             ps.step(args.steps)
             tt += time.perf_counter() - t0
             cd += m * n * args.steps
-            _, _, e64 = ps.energy()
+            l64, _, e64 = ps.energy()
             errs.append(abs(e_b[r0] - e64[0]) / abs(e64[0]))
+            lerrs.append(float(np.max(np.abs(lam_b[c0:c0 + m] - l64) / np.abs(l64))))
+            serrs.append(abs(lam_b[c0:c0 + m].sum() - l64.sum()) / abs(l64.sum()))
             ps.close()
             r0 += nr
+            c0 += nr * m
         plain = cd / tt
         out["plain_fp64"] = {"value": plain, "unit": "cdof/s",
                              "sample": "restart 0 of each m group, one restart per solve, "
                                        "float64, host convergence poll every CG iteration"}
         out["speedup_vs_plain_fp64"] = value / plain
         out["energy_rel_err_vs_fp64"] = max(errs)
+        out["lambda_rel_err_vs_fp64"] = max(lerrs)        # every lambda_i of the sampled restarts
+        out["sum_lambda_rel_err_vs_fp64"] = max(serrs)
         log(f"[bench] plain fp64 {plain:.3e} cdof/s, speedup {value / plain:.2f}, "
             f"energy err {max(errs):.2e}")
 
