@@ -176,3 +176,14 @@ def test_label_partition_brackets_the_lune():
     inner = interior_labels(M, lab)
     assert np.all(inner[lab == -1] == -1) and (inner == -1).sum() > 0
 
+
+
+def test_gauss_bonnet_sides_counts_every_term():
+    # one heptagon needs one extra pentagon on the sphere: 13 pentagons + 1 heptagon
+    n_k = np.zeros(9, int)
+    n_k[5], n_k[6], n_k[7] = 13, 10, 1
+    assert gauss_bonnet_sides(n_k, 2) == (13, 13)
+    # an octagon on the torus (chi = 0) balanced by two pentagons
+    n_k = np.zeros(9, int)
+    n_k[5], n_k[8] = 2, 1
+    assert gauss_bonnet_sides(n_k, 0) == (2, 2)
