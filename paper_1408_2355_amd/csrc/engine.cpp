@@ -25,6 +25,7 @@ namespace sp {
 namespace {
 enum { CF_BB, CF_RZ, CF_TOL2, CF_ALPHA, CF_BETA, CF_RRO, CF_NRM, CF_BBN, CF_ISC, CF_COEF, CF_N };
 enum { CI_ACT, CI_ACTO, CI_ITERS, CI_SWEEPS, CI_SEGLO, CI_SEGLEN, CI_LIVE, CI_N };
+constexpr int kSepsNperMax = 512;  // S_eps element-kernel workgroups per XCD, at most
 }  // namespace
 
 void validate_params(const sp_params& p) {
@@ -88,7 +89,9 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     sp_.nt = int(mesh_->nt);
     sp_.tchunk = 64;
     sp_.nchunk = int((mesh_->nt + sp_.tchunk - 1) / sp_.tchunk);
-    sp_.nper = std::max(1, std::min(64, (sp_.nchunk + 7) / 8));
+    // S_eps workgroups per XCD: as many as 512 (the element kernels are
+    // latency-bound and want every SIMD full); the tuner may pick 64
+    sp_.nper = std::max(1, std::min(kSepsNperMax, (sp_.nchunk + 7) / 8));
     sp_.nres_p = nres_p_;
     seps_tiles_.alloc(nres_p_);
     u_.alloc(nv);
@@ -358,32 +361,41 @@ void Solver::autotune() {
   }
 
   // S_eps element kernel: LDS-staged, direct corner reads or lane-split,
-  // whichever is fastest for this batch's restart tiles
+  // and 64 or the full count of workgroups per XCD, whichever is fastest for
+  // this batch's restart tiles (part_s_ holds the larger count's partials)
   if (sp_.ntile > 0) {
     hipEvent_t e0, e1;
     SP_HIP(hipEventCreate(&e0));
     SP_HIP(hipEventCreate(&e1));
     const int nmode = sp_.lanes_ok ? 3 : 2;
-    double t_mode[3] = {0, 0, 0};
-    for (int mode = 0; mode < nmode; ++mode) {
-      sp_.direct = mode;
-      k::energy_seps(args_, sp_, mesh_->tri.p, mesh_->tarea.p, u_.p, part_s_.p, s_);
-      SP_HIP(hipEventRecord(e0, s_));
-      for (int i = 0; i < 2; ++i)
+    const int nper_max = std::max(1, std::min(kSepsNperMax, (sp_.nchunk + 7) / 8));
+    double t_best = 0.0;
+    int best = 0, best_nper = nper_max;
+    for (int nper : {nper_max, 64}) {
+      if (nper == 64 && nper >= nper_max) continue;
+      sp_.nper = nper;
+      for (int mode = 0; mode < nmode; ++mode) {
+        sp_.direct = mode;
         k::energy_seps(args_, sp_, mesh_->tri.p, mesh_->tarea.p, u_.p, part_s_.p, s_);
-      SP_HIP(hipEventRecord(e1, s_));
-      SP_HIP(hipEventSynchronize(e1));
-      float ms = 0.f;
-      SP_HIP(hipEventElapsedTime(&ms, e0, e1));
-      t_mode[mode] = ms;
-      if (std::getenv("SEGPART_TUNE_VERBOSE"))
-        std::fprintf(stderr, "[segpart tune] S_eps %s: %.1f us\n",
-                     mode == 2 ? "lanes" : mode ? "direct" : "staged", 500.0 * ms);
+        SP_HIP(hipEventRecord(e0, s_));
+        for (int i = 0; i < 2; ++i)
+          k::energy_seps(args_, sp_, mesh_->tri.p, mesh_->tarea.p, u_.p, part_s_.p, s_);
+        SP_HIP(hipEventRecord(e1, s_));
+        SP_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        SP_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (std::getenv("SEGPART_TUNE_VERBOSE"))
+          std::fprintf(stderr, "[segpart tune] S_eps %s, %d groups/xcd: %.1f us\n",
+                       mode == 2 ? "lanes" : mode ? "direct" : "staged", nper, 500.0 * ms);
+        if ((nper == nper_max && mode == 0) || ms < t_best) {
+          t_best = ms;
+          best = mode;
+          best_nper = nper;
+        }
+      }
     }
-    int best = 0;
-    for (int mode = 1; mode < nmode; ++mode)
-      if (t_mode[mode] < t_mode[best]) best = mode;
     sp_.direct = best;
+    sp_.nper = best_nper;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
   }

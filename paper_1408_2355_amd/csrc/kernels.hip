@@ -134,12 +134,6 @@ __device__ void block_store(const Tile& t, double (&s)[ND][4], double* part, int
   }
 }
 
-__device__ __forceinline__ double sum_chunks(const double* p, int nchunk, int rp, int c) {
-  double s = 0.0;
-  for (int ch = 0; ch < nchunk; ++ch) s += p[size_t(ch) * rp + c];
-  return s;
-}
-
 // Column reductions over the chunk partials: a workgroup serves kRC columns
 // with kRL lanes each; lane l adds chunks l, l + kRL, ... and lane 0 adds
 // the lane sums in order (fixed order, so results are reproducible).  Every
@@ -1497,6 +1491,10 @@ __global__ __launch_bounds__(kBlock) void k_energy_seps_direct(StepArgs a, SepsP
 // H_l = sum a a^T), the lanes of each restart take an exclusive prefix of H
 // (shuffles), and since B is bilinear the lane's share is
 //   local + B(G_before, H_l),  G_before = sum of H over the restart's lower lanes.
+// Scaled: the lane's four column factors (deferred normalisation) are read
+// once per tile.  The kernel is bound by load latency, so its registers are
+// capped for 7 waves per SIMD; the triangle index is wave-uniform, so the
+// corner indices and areas come through scalar loads.
 __device__ __forceinline__ double quartic_b(const double (&G)[6], const double (&H)[6]) {
   // symmetric 3x3 as (00, 11, 22, 01, 02, 12)
   const double trG = G[0] + G[1] + G[2], trH = H[0] + H[1] + H[2];
@@ -1515,14 +1513,16 @@ __device__ __forceinline__ double quartic_b(const double (&G)[6], const double (
   return (SG + trG) * (SH + trH) + 2.0 * GH + 4.0 * (gh + dgh + gdh) + 6.0 * dgdh;
 }
 
-__global__ __launch_bounds__(kBlock) void k_energy_seps_lanes(StepArgs a, SepsPlan sp,
+template <bool Scaled>
+__global__ __launch_bounds__(kBlock, 7) void k_energy_seps_lanes(StepArgs a, SepsPlan sp,
                                                               const int* __restrict__ tri,
                                                               const double* __restrict__ tarea,
                                                               const double* __restrict__ u,
                                                               double* __restrict__ part_s) {
   __shared__ double red[kBlock];
   const int rp = a.t.rp;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   constexpr int kW = kBlock / 64;
   for_seps_chunks(sp, [&](int tile, int cb, int ce, int stride) {
     const int4 tl = sp.tiles[tile];
@@ -1536,6 +1536,8 @@ __global__ __launch_bounds__(kBlock) void k_energy_seps_lanes(StepArgs a, SepsPl
     int kmax = 1;
     for (int q = tl.x; q < tl.y; ++q) kmax = max(kmax, a.ct.res_len[q] >> 2);
     double acc = 0.0;
+    V4<double> w = {};  // the lane's column factors (Scaled), loaded once per tile
+    if (Scaled && on) w = ld4(a.usc + c);
     for (int chunk = cb; chunk < ce; chunk += stride) {
       const int t_beg = chunk * sp.tchunk, t_end = min(t_beg + sp.tchunk, sp.nt);
       for (int t = t_beg + wave; t < t_end; t += kW) {
@@ -1545,8 +1547,7 @@ __global__ __launch_bounds__(kBlock) void k_energy_seps_lanes(StepArgs a, SepsPl
           const double* p1 = u + size_t(tri[3 * t + 1]) * rp + c;
           const double* p2 = u + size_t(tri[3 * t + 2]) * rp + c;
           V4<double> x0 = ld4(p0), x1 = ld4(p1), x2 = ld4(p2);
-          if (a.usc) {
-            const V4<double> w = ld4(a.usc + c);
+          if constexpr (Scaled) {
             for (int j = 0; j < 4; ++j) {
               x0.v[j] *= w.v[j];
               x1.v[j] *= w.v[j];
@@ -1673,13 +1674,11 @@ __global__ __launch_bounds__(kBlock) void k_multipliers(StepArgs a, SepsPlan sp,
 // (fixed order); 2 / eps^2 = coef / tau.
 __global__ void k_red_multipliers(StepArgs a, SepsPlan sp, const double* __restrict__ part,
                                   const double* __restrict__ lam, double* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= a.t.rp) return;
-  if (a.ct.seg_len[c] == 0) {
-    out[c] = 0.0;
-    return;
-  }
-  out[c] = lam[c] + (a.ct.coef[c] / a.tau) * sum_chunks(part, 8 * sp.nper, a.t.rp, c);
+  const int c = red_col();
+  const bool real = c < a.t.rp && a.ct.seg_len[c] > 0;
+  const double p = red_sum(part, real ? 8 * sp.nper : 0, a.t.rp, c);
+  if (!red_lead() || c >= a.t.rp) return;
+  out[c] = real ? lam[c] + (a.ct.coef[c] / a.tau) * p : 0.0;
 }
 
 __global__ void k_red_lambda(StepArgs a, double* __restrict__ lam) {
@@ -1695,9 +1694,12 @@ __global__ void k_red_lambda(StepArgs a, double* __restrict__ lam) {
 __global__ void k_red_seps(StepArgs a, SepsPlan sp, const double* __restrict__ part_s,
                            const double* __restrict__ lam, double* __restrict__ seps,
                            double* __restrict__ energy) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= a.ct.nres) return;
-  const double s = sum_chunks(part_s, 8 * sp.nper, sp.nres_p, r) * a.ct.res_ieps2[r];
+  // one partial per element-kernel workgroup and restart, summed by
+  // kRL lanes per restart in a fixed order
+  const int r = red_col();
+  const double ps = red_sum(part_s, r < a.ct.nres ? 8 * sp.nper : 0, sp.nres_p, r);
+  if (!red_lead() || r >= a.ct.nres) return;
+  const double s = ps * a.ct.res_ieps2[r];
   double e = s;
   const int lo = a.ct.res_lo[r], m = a.ct.res_len[r];
   for (int i = 0; i < m; ++i) e += lam[lo + i];
@@ -2316,7 +2318,7 @@ void multipliers(const StepArgs& a, const SepsPlan& sp, const int32_t* tri, cons
   if (sp.ntile > 0)
     hipLaunchKernelGGL(k_multipliers, dim3(8 * sp.nper), dim3(kBlock), 0, s, a, sp, tri, tarea, u,
                        part);
-  hipLaunchKernelGGL(k_red_multipliers, dim3(nblocks(size_t(a.t.rp))), dim3(kBlock), 0, s, a, sp,
+  hipLaunchKernelGGL(k_red_multipliers, dim3(colblocks(a.t)), dim3(kBlock), 0, s, a, sp,
                      part, lam, out);
   SP_LAUNCH_CHECK();
 }
@@ -2334,10 +2336,14 @@ void energy_rq(const StepArgs& a, const double* u, hipStream_t s) {
 void energy_seps(const StepArgs& a, const SepsPlan& sp, const int32_t* tri, const double* tarea,
                  const double* u, double* part_s, hipStream_t s) {
   if (sp.ntile == 0) return;
-  if (sp.direct == 2 && sp.lanes_ok)
-    hipLaunchKernelGGL(k_energy_seps_lanes, dim3(8 * sp.nper), dim3(kBlock), 0, s, a, sp, tri,
-                       tarea, u, part_s);
-  else if (sp.direct && a.usc)
+  if (sp.direct == 2 && sp.lanes_ok) {
+    if (a.usc)
+      hipLaunchKernelGGL(k_energy_seps_lanes<true>, dim3(8 * sp.nper), dim3(kBlock), 0, s, a, sp,
+                         tri, tarea, u, part_s);
+    else
+      hipLaunchKernelGGL(k_energy_seps_lanes<false>, dim3(8 * sp.nper), dim3(kBlock), 0, s, a, sp,
+                         tri, tarea, u, part_s);
+  } else if (sp.direct && a.usc)
     hipLaunchKernelGGL(k_energy_seps_direct<true>, dim3(8 * sp.nper), dim3(kBlock), 0, s, a, sp,
                        tri, tarea, u, part_s);
   else if (sp.direct)
@@ -2353,7 +2359,7 @@ void red_energy(const StepArgs& a, const SepsPlan& sp, const double* part_s, boo
                 double* lam, double* seps, double* energy, hipStream_t s) {
   if (with_lambda)
     hipLaunchKernelGGL(k_red_lambda, dim3(colblocks(a.t)), dim3(kBlock), 0, s, a, lam);
-  hipLaunchKernelGGL(k_red_seps, dim3(nblocks(size_t(a.ct.nres))), dim3(kBlock), 0, s, a, sp,
+  hipLaunchKernelGGL(k_red_seps, dim3(nblocks(size_t(a.ct.nres), kRC)), dim3(kBlock), 0, s, a, sp,
                      part_s, (const double*)lam, seps, energy);
   SP_LAUNCH_CHECK();
 }
