@@ -149,18 +149,49 @@ def serve(args, sp):
         tickets.append(srv.submit(meshes[r["kind"]], prm, [r["m"]] * r["restarts"],
                                   [r["eps"]] * r["restarts"], u0))
     del reqs
-    lat, ok = [], 0
+    # plain float64 sample: the first request of each mesh kind
+    sample = sorted({r["kind"]: i for i, r in reversed(list(enumerate(trace)))}.values())
+    lat, ok, served_e = [], 0, {}
     for i, t in enumerate(tickets):
         done = srv.wait(t, timeout_s=600.0)
         assert done, f"request {i} did not finish"
         out = srv.fetch(t)
         lat.append(out["latency_s"])
         ok += int(np.isfinite(out["energy"]).all())
+        if i in sample:
+            served_e[i] = float(out["energy"][0])
         log(f"[serve] request {i} ({trace[i]['kind']}, m {trace[i]['m']}, "
             f"{trace[i]['restarts']} restarts) done, latency {out['latency_s']:.2f} s")
     wall = time.perf_counter() - t0
     st = srv.stats()
     srv.close()
+    plain = None
+    if not args.no_plain:
+        # the same requests' first restart alone in the plain float64 form
+        # (host poll every CG iteration), 200 steps each
+        cd, tt, errs = 0.0, 0.0, []
+        for i in sample:
+            r = trace[i]
+            mesh = meshes[r["kind"]]
+            n = mesh.n_vert
+            u1 = uniform_u0(r["seed"], r["restarts"], r["m"], n)[:r["m"]]
+            pprm = sp.params(r["eps"] / 200.0, precision="fp64", n_steps=SERVE["steps"],
+                             cg_rtol=1e-10, cg_max_iter=2000, check_every=1)
+            ps = sp.State(mesh, pprm, [r["m"]], [r["eps"]], u1)
+            t1 = time.perf_counter()
+            ps.step(SERVE["steps"])
+            tt += time.perf_counter() - t1
+            cd += r["m"] * n * SERVE["steps"]
+            e64 = ps.energy()[2][0]
+            ps.close()
+            errs.append(abs(served_e[i] - e64) / abs(e64))
+            log(f"[serve] plain float64, request {i} ({r['kind']}, m {r['m']}): "
+                f"energy {e64:.8f}, served {served_e[i]:.8f}")
+        plain = {"value": cd / tt, "unit": "cdof/s",
+                 "sample": f"first request of each mesh kind ({len(sample)} requests), its "
+                           "first restart alone, float64, host convergence poll every CG "
+                           "iteration, 200 steps",
+                 "served_energy_rel_err_vs_fp64": max(errs)}
     for m in meshes.values():
         m.close()
     result = {
@@ -177,6 +208,9 @@ def serve(args, sp):
         "offered_cdof_per_s": work / max(span, 1e-9), "wall_s": wall,
         "server_cdof_per_s": st["cdof_per_s"],
     }
+    if plain is not None:
+        result["plain_fp64"] = plain
+        result["speedup_vs_plain_fp64"] = result["value"] / plain["value"]
     print(json.dumps(result), flush=True)
 
 
