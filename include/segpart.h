@@ -399,7 +399,8 @@ int sp_region_eigen(const sp_mesh* mesh, int32_t n_restarts, const int32_t* m,
  * region's neighbours (its sides, one arc per neighbour).  With triple
  * junctions only, the counts n_k of k-sided regions satisfy the identity
  * derived from Euler's formula (equation gauss-bonnet),
- * 4 n_2 + 3 n_3 + 2 n_4 + n_5 = 6 chi + sum_{k>=7} (k - 6) n_k.  m_r <= 4096. */
+ * 4 n_2 + 3 n_3 + 2 n_4 + n_5 = 6 chi + sum_{k>=7} (k - 6) n_k.  m_r <= 4096 and
+ * sum_r m_r^2 < 2^31 (SP_EINVAL otherwise). */
 int sp_region_graph(const sp_mesh* mesh, int32_t n_restarts, const int32_t* m,
                     const int32_t* labels, uint8_t* adjacency, int32_t* sides);
 

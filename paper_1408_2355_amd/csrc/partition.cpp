@@ -86,9 +86,13 @@ void region_graph(const Mesh& mesh, int nres, const int* m, const int32_t* label
   SP_REQUIRE(nres >= 1 && m && labels && adj, SP_EINVAL, "region_graph: NULL argument");
   const int64_t n = mesh.n;
   std::vector<int> off(nres + 1, 0);
+  int64_t total = 0;
   for (int r = 0; r < nres; ++r) {
     SP_REQUIRE(m[r] >= 1 && m[r] <= 4096, SP_EINVAL, "region_graph: m must be in 1..4096");
-    off[r + 1] = off[r] + m[r] * m[r];
+    total += int64_t(m[r]) * m[r];
+    SP_REQUIRE(total < (int64_t(1) << 31), SP_EINVAL,
+               "region_graph: adjacency too large (sum of m^2 must stay below 2^31)");
+    off[r + 1] = int(total);
   }
   // labels in the renumbered vertex order
   std::vector<int32_t> lab(size_t(n) * nres);

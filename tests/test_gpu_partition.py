@@ -3,7 +3,8 @@
 * sp_region_graph: adjacency and side counts equal the oracle's (exactly) on
   the polyhedral partitions of the level-5 sphere (tetrahedral, cubic,
   dodecahedral: 3, 4 and 5 sides, Gauss-Bonnet 12 = 6 chi) and cubic labels
-  with voids, four restarts in one call;
+  with voids, four restarts in one call; an adjacency of 2^31 entries or more
+  is rejected (SP_EINVAL) before any allocation;
 * sp_region_eigen: the first Dirichlet eigenvalue of every region equals the
   oracle's shift-invert value (1e-9 relative; inverse iteration to 1e-13
   relative change) for the Y-partition lunes of a longitude-latitude sphere
@@ -71,6 +72,19 @@ def test_region_graph_matches_oracle(gpu):
         assert gauss_bonnet_sides(n_k, 2) == (12, 12)
         off += m
     mesh.close()
+
+
+def test_region_graph_rejects_oversized_adjacency(gpu):
+    # sum of m^2 over the restarts must stay below 2^31 (int offsets)
+    v, f = icosphere(1)
+    mesh = sp.Mesh(v, f)
+    try:
+        ms = [4096] * 129
+        with pytest.raises(sp.SegpartError) as e:
+            sp.sp_region_graph(mesh.h, ms, np.zeros((len(ms), v.shape[0]), np.int32))
+        assert e.value.code == sp.SP_EINVAL and "2^31" in str(e.value)
+    finally:
+        mesh.close()
 
 
 def uv_sphere(nlat, nlon):
