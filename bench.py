@@ -408,6 +408,21 @@ def main():
                     traffic_vs_algorithmic=traffic_ratio, traffic_source=traffic_src,
                     launches=launches, avg_us=avg_s * 1e6, bytes_per_launch=bytes_launch,
                     kernel_ms_total={KERNEL_NAMES[i]: kt[i][1] for i in range(3)})
+    # the practical HBM rate: a 2 GiB device-to-device copy (read + write bytes),
+    # after the timed window
+    cx = torch.ones(2**29, dtype=torch.float32, device="cuda:0")
+    cy = torch.empty_like(cx)
+    cy.copy_(cx)
+    ce0, ce1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ce0.record()
+    for _ in range(5):
+        cy.copy_(cx)
+    ce1.record()
+    ce1.synchronize()
+    copy_gbs = 5 * 2 * cx.numel() * 4 / (ce0.elapsed_time(ce1) * 1e-3) / 1e9
+    del cx, cy
+    roofline["copy_GBps"] = copy_gbs
+    roofline["frac_of_copy"] = achieved / copy_gbs
 
     out = {
         "metric": "component-DOF updates/s (batched mixed-precision vs plain FP64 GPU, "
