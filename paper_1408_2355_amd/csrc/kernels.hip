@@ -138,7 +138,9 @@ __device__ void block_store(const Tile& t, double (&s)[ND][4], double* part, int
 // with kRL lanes each; lane l adds chunks l, l + kRL, ... and lane 0 adds
 // the lane sums in order (fixed order, so results are reproducible).  Every
 // thread of the block must call red_sum; the total is valid in lane 0.
-constexpr int kRL = 8;
+// (32 lanes: the streaming kernels write up to 2048 partial rows, and each
+// lane's chain of dependent loads sets the reduction's latency)
+constexpr int kRL = 32;
 constexpr int kRC = kBlock / kRL;
 
 __device__ __forceinline__ int red_col() { return blockIdx.x * kRC + threadIdx.x % kRC; }
@@ -980,87 +982,134 @@ __global__ void k_red_outer(StepArgs a, int oslot, int onext) {
 // -------------------------------------------------------------- node step --
 // Step 2 of Algorithm 2.2 in its practical form: S = sum_j u~_j^2 over the
 // restart's components, u^_i = u~_i exp(-(2 tau/eps^2)(S - u~_i^2)).
+//
+// S comes from segmented sums across the row group (the tg lanes that hold
+// one row's column tile, 4 columns a lane).  In general (any restart length
+// and alignment) a forward scan F (restarting at each restart's first column in
+// the tile) and a backward scan B (restarting at its last one), each a local
+// pass over the lane's 4 columns plus a shuffle scan over the lanes, give
+// S_i = F_i + B_i - u~_i^2 (all terms nonnegative: no cancellation).  A
+// restart that runs past either edge of the tile adds the squares of its
+// columns outside the tile, read from the row.  Every lane of a row group
+// takes part in the shuffles; lanes past the last column group carry empty
+// segments.
 __global__ __launch_bounds__(kBlock) void k_nodal(StepArgs a, const double* __restrict__ u,
                                                   double* __restrict__ out, int keep) {
   const Tile& t = a.ts;
+  const int tg = t.tg, gl = threadIdx.x % tg;
   for (int ct = 0; ct < t.nct; ++ct) {
-  const int g = ct * t.tg + threadIdx.x % t.tg;
-  if (t.tg != 64 && g >= t.G) continue;  // (tg == 64: the whole wavefront stays)
-  const int c0 = 4 * g;
-  int lo[4] = {0, 0, 0, 0}, len[4] = {0, 0, 0, 0}, lv[4] = {0, 0, 0, 0};
-  double cf[4] = {0, 0, 0, 0};
-  if (g < t.G)
+    const int g = ct * tg + gl;
+    const bool in = g < t.G;
+    const int c0 = 4 * g;
+    const int tile_lo = 4 * ct * tg, tile_hi = min(tile_lo + 4 * tg, t.rp);
+    int lo[4] = {0, 0, 0, 0}, len[4] = {0, 0, 0, 0}, lv[4] = {0, 0, 0, 0};
+    double cf[4] = {0, 0, 0, 0};
+    if (in)
+      for (int j = 0; j < 4; ++j) {
+        lo[j] = a.ct.seg_lo[c0 + j];
+        len[j] = a.ct.seg_len[c0 + j];
+        lv[j] = a.ct.live[c0 + j];
+        cf[j] = a.ct.coef[c0 + j];
+      }
+    const int anylv = lv[0] | lv[1] | lv[2] | lv[3];
+    // a row group with no live column has nothing to do (the test is uniform
+    // over the group: a whole wavefront when tg = 64, else every group runs)
+    if (tg == 64 && !__any(anylv)) continue;
+    const bool mixed = keep && !(lv[0] & lv[1] & lv[2] & lv[3]);
+    // first / last column of each column's restart inside the tile
+    bool head[4], tail[4], left[4], right[4];
     for (int j = 0; j < 4; ++j) {
-      lo[j] = a.ct.seg_lo[c0 + j];
-      len[j] = a.ct.seg_len[c0 + j];
-      lv[j] = a.ct.live[c0 + j];
-      cf[j] = a.ct.coef[c0 + j];
+      const bool v = in && len[j] > 0;
+      const int c = c0 + j;
+      head[j] = !v || c == max(lo[j], tile_lo);
+      tail[j] = !v || c == min(lo[j] + len[j], tile_hi) - 1;
+      left[j] = v && lo[j] < tile_lo;
+      right[j] = v && lo[j] + len[j] > tile_hi;
     }
-  const bool mixed = keep && !(lv[0] & lv[1] & lv[2] & lv[3]);
-  // One row per wavefront and every lane's four columns inside one restart
-  // whose lanes all lie in this wavefront: S comes from a segmented sum of
-  // the lanes' partial sums across the wavefront instead of re-reading the
-  // restart's values.  The lane test is wave-uniform (ballot); a wavefront
-  // that fails it (a restart across a tile edge, m not a multiple of 4)
-  // takes the general path below.  Lanes past the last group take part in
-  // the shuffles with an empty segment.
-  const int lane = threadIdx.x & 63;
-  const int tile0 = 4 * (ct * t.tg);
-  const bool one_seg = g < t.G && lo[0] == lo[3] && len[0] > 0 && ((lo[0] | len[0]) & 3) == 0 &&
-                       lo[0] >= tile0 && lo[0] + len[0] <= tile0 + 256;
-  const bool lanes = t.tg == 64 && __all(g >= t.G || one_seg);
-  const int ls = one_seg ? (lo[0] - tile0) >> 2 : lane, le = one_seg ? ls + (len[0] >> 2) : lane + 1;
-  if (!lanes && !(lv[0] | lv[1] | lv[2] | lv[3])) continue;
-  if (lanes && !__any(lv[0] | lv[1] | lv[2] | lv[3])) continue;
-  for_rows(t, [&](int row) {
-    const double* ur = u + size_t(row) * t.rp;
-    if (lanes) {
+    const bool fh = head[0] | head[1] | head[2] | head[3];
+    const bool bt = tail[0] | tail[1] | tail[2] | tail[3];
+    // Fast case (wave-uniform): one row per wavefront and each lane's four
+    // columns inside one restart that starts on a lane and lies in the
+    // tile; then one segmented sum of the lanes' partial sums, broadcast
+    // from the restart's first lane, gives S.
+    const int lane = threadIdx.x & 63;
+    const bool one_seg = in && lo[0] == lo[3] && len[0] > 0 && ((lo[0] | len[0]) & 3) == 0 &&
+                         lo[0] >= tile_lo && lo[0] + len[0] <= tile_hi;
+    const bool lanes = tg == 64 && __all(!in || one_seg);
+    const int ls = one_seg ? (lo[0] - tile_lo) >> 2 : lane, le = one_seg ? ls + (len[0] >> 2) : lane + 1;
+    for_rows(t, [&](int row) {
+      const double* ur = u + size_t(row) * t.rp;
       V4<double> uv = {}, ov = {};
-      if (g < t.G) {
+      if (in) {
         uv = ld4s(ur + c0);
         ov = mixed ? ld4s(out + size_t(row) * t.rp + c0) : uv;
       }
-      double v = 0.0;
-      for (int j = 0; j < 4; ++j) v = fma(uv.v[j], uv.v[j], v);
-      for (int d = 1; d < 64 && __any(lane + d < le); d <<= 1) {
-        const double w = __shfl_down(v, d);
-        if (lane + d < le) v += w;
-      }
-      const double S = __shfl(v, ls);
-      if (g < t.G) {
-        for (int j = 0; j < 4; ++j)
-          if (lv[j]) ov.v[j] = uv.v[j] * exp(-cf[j] * (S - uv.v[j] * uv.v[j]));
-        st4s(out + size_t(row) * t.rp + c0, ov);
-      }
-      return;
-    }
-    V4<double> uv = ld4s(ur + c0), ov = uv;
-    // columns that are not live keep the state's value
-    if (mixed) ov = ld4s(out + size_t(row) * t.rp + c0);
-    double S = 0.0;
-    int cur = -1;
-    for (int j = 0; j < 4; ++j) {
-      if (!lv[j]) continue;
-      if (lo[j] != cur) {
-        // S over the restart's components, in component order (wide loads
-        // where the segment is aligned; the same fma sequence either way)
-        cur = lo[j];
-        S = 0.0;
-        const double* seg = ur + lo[j];
-        int i = 0;
-        if (((lo[j] | len[j]) & 3) == 0) {
-          for (; i < len[j]; i += 4) {
-            const V4<double> w = ld4(seg + i);
-            for (int q = 0; q < 4; ++q) S = fma(w.v[q], w.v[q], S);
-          }
+      if (lanes) {
+        double v = 0.0;
+        for (int j = 0; j < 4; ++j) v = fma(uv.v[j], uv.v[j], v);
+        for (int d = 1; d < 64 && __any(lane + d < le); d <<= 1) {
+          const double w = __shfl_down(v, d);
+          if (lane + d < le) v += w;
         }
-        for (; i < len[j]; ++i) S = fma(seg[i], seg[i], S);
+        const double S = __shfl(v, ls);
+        if (in) {
+          for (int j = 0; j < 4; ++j)
+            if (lv[j]) ov.v[j] = uv.v[j] * exp(-cf[j] * (S - uv.v[j] * uv.v[j]));
+          st4s(out + size_t(row) * t.rp + c0, ov);
+        }
+        return;
       }
-      const double x = uv.v[j];
-      ov.v[j] = x * exp(-cf[j] * (S - x * x));
-    }
-    st4s(out + size_t(row) * t.rp + c0, ov);
-  });
+      double q[4], F[4], B[4];
+      for (int j = 0; j < 4; ++j) q[j] = (in && len[j] > 0) ? uv.v[j] * uv.v[j] : 0.0;
+      F[0] = q[0];
+      for (int j = 1; j < 4; ++j) F[j] = head[j] ? q[j] : F[j - 1] + q[j];
+      B[3] = q[3];
+      for (int j = 2; j >= 0; --j) B[j] = tail[j] ? q[j] : B[j + 1] + q[j];
+      // inclusive segmented scans over the lanes of the row group
+      double tf = F[3], tb = B[0];
+      int ff = fh, fb = bt;
+      for (int d = 1; d < tg; d <<= 1) {
+        const double uf = __shfl_up(tf, d, tg), ub = __shfl_down(tb, d, tg);
+        const int gf = __shfl_up(ff, d, tg), gb = __shfl_down(fb, d, tg);
+        if (gl >= d) {
+          if (!ff) tf = uf + tf;
+          ff |= gf;
+        }
+        if (gl + d < tg) {
+          if (!fb) tb = tb + ub;
+          fb |= gb;
+        }
+      }
+      // carries from the neighbouring lanes (their inclusive values)
+      const double cf_in = __shfl_up(tf, 1, tg), cb_in = __shfl_down(tb, 1, tg);
+      bool open = gl > 0;
+      for (int j = 0; j < 4; ++j) {
+        open = open && !head[j];
+        if (open) F[j] += cf_in;
+      }
+      open = gl + 1 < tg;
+      for (int j = 3; j >= 0; --j) {
+        open = open && !tail[j];
+        if (open) B[j] += cb_in;
+      }
+      if (!in) return;
+      double outside = 0.0;
+      int cur = -1;
+      for (int j = 0; j < 4; ++j) {
+        if (!lv[j]) continue;
+        if ((left[j] || right[j]) && lo[j] != cur) {
+          // the restart's columns outside the tile, in column order
+          cur = lo[j];
+          outside = 0.0;
+          for (int c = lo[j]; c < tile_lo; ++c) outside = fma(ur[c], ur[c], outside);
+          for (int c = tile_hi; c < lo[j] + len[j]; ++c) outside = fma(ur[c], ur[c], outside);
+        }
+        const double S = F[j] + B[j] - q[j] + ((left[j] || right[j]) ? outside : 0.0);
+        const double x = uv.v[j];
+        ov.v[j] = x * exp(-cf[j] * (S - x * x));
+      }
+      st4s(out + size_t(row) * t.rp + c0, ov);
+    });
   }
 }
 
