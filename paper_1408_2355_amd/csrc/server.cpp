@@ -2,12 +2,39 @@
 #include "server.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstring>
+#include <thread>
 
 namespace sp {
 
 namespace {
+// f(lo, hi) over [0, n) in contiguous slices on up to 16 threads (the
+// calling thread takes the first), one slice per 64 MB of doubles at least;
+// for the request-sized host copies, whose cost is mostly first-touch page
+// faults that a single thread takes one by one.
+template <class F>
+void par_for(size_t n, F&& f) {
+  constexpr size_t kMin = size_t(1) << 23;
+  const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+  const size_t T = std::max<size_t>(1, std::min<size_t>(std::min<size_t>(hw, 16), n / kMin));
+  if (T <= 1) {
+    f(size_t(0), n);
+    return;
+  }
+  const size_t step = (n + T - 1) / T;
+  std::vector<std::thread> th;
+  th.reserve(T - 1);
+  for (size_t t = 1; t < T; ++t) {
+    const size_t lo = t * step, hi = std::min(n, lo + step);
+    if (lo < hi) th.emplace_back([&f, lo, hi] { f(lo, hi); });
+  }
+  f(size_t(0), std::min(n, step));
+  for (auto& x : th) x.join();
+}
+
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -63,8 +90,18 @@ int64_t Server::submit(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, 
   for (int x : spec.m) q->R += x;
   SP_REQUIRE(q->R <= max_cols_, SP_EINVAL, "server: request has more components than a batch holds");
   const size_t cnt = size_t(q->R) * mesh->n;
-  q->u0.assign(u0, u0 + cnt);
-  for (double v : q->u0) SP_REQUIRE(std::isfinite(v), SP_EINVAL, "u0 holds a non-finite value");
+  q->u0.alloc(cnt);
+  std::atomic<bool> finite{true};
+  par_for(cnt, [&](size_t lo, size_t hi) {
+    double* dst = q->u0.data();
+    bool ok = true;
+    for (size_t i = lo; i < hi; ++i) {
+      dst[i] = u0[i];
+      ok = ok && std::isfinite(u0[i]);
+    }
+    if (!ok) finite = false;
+  });
+  SP_REQUIRE(finite.load(), SP_EINVAL, "u0 holds a non-finite value");
   const int cap = (q->R + 3) / 4 * 4;
   SP_REQUIRE(batch_bytes(mesh, prm, cap, int(spec.m.size())) <= budget_, SP_ENOMEM,
              "server: request does not fit in the HBM budget");
@@ -217,7 +254,7 @@ void Server::admit(Batch* b, Request* q) {
   b->solver->pack_range(q->c_lo, q->R, tmp.p);
   b->solver->normalise_range(q->c_lo, q->R);
   b->solver->sync();
-  std::vector<double>().swap(q->u0);
+  q->u0.clear();
 }
 
 void Server::retire(Batch* b, Request* q) {
@@ -235,7 +272,11 @@ void Server::retire(Batch* b, Request* q) {
                         hipMemcpyDeviceToHost, S.stream()));
   DevBuf<double> tmp(size_t(q->R) * n);
   S.unpack_range(q->c_lo, q->R, tmp.p);
-  q->u_out.resize(size_t(q->R) * n);
+  // first touch of the output pages on many threads, then the copy
+  q->u_out.alloc(size_t(q->R) * n);
+  par_for(q->u_out.n, [&](size_t lo, size_t hi) {
+    std::memset(q->u_out.data() + lo, 0, (hi - lo) * sizeof(double));
+  });
   SP_HIP(hipMemcpyAsync(q->u_out.data(), tmp.p, tmp.bytes(), hipMemcpyDeviceToHost, S.stream()));
   S.sync();
 }
@@ -427,7 +468,10 @@ int Server::fetch(int64_t ticket, double* u_out, int32_t* labels, double* lambda
     reqs_.erase(it);
   }
   if (q->error != SP_OK) throw Error(q->error, q->error_msg);
-  if (u_out) std::copy(q->u_out.begin(), q->u_out.end(), u_out);
+  if (u_out) {
+    const double* src = q->u_out.data();
+    par_for(q->u_out.n, [&](size_t lo, size_t hi) { std::copy(src + lo, src + hi, u_out + lo); });
+  }
   if (labels) std::copy(q->labels.begin(), q->labels.end(), labels);
   if (lambda) std::copy(q->lam.begin(), q->lam.end(), lambda);
   if (seps) std::copy(q->seps.begin(), q->seps.end(), seps);

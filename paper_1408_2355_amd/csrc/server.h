@@ -24,6 +24,23 @@
 
 namespace sp {
 
+// Host array of doubles left uninitialised on allocation: a request's input
+// and output state (up to gigabytes) is first touched by the parallel copies
+// of the server, not by a serial zero fill.
+struct HostBuf {
+  std::unique_ptr<double[]> p;
+  size_t n = 0;
+  void alloc(size_t k) {
+    p.reset(new double[k]);
+    n = k;
+  }
+  void clear() {
+    p.reset();
+    n = 0;
+  }
+  double* data() { return p.get(); }
+};
+
 class Server {
  public:
   Server(int64_t budget_bytes, int max_cols);
@@ -42,7 +59,7 @@ class Server {
     Mesh* mesh = nullptr;
     sp_params prm{};
     BatchSpec spec;
-    std::vector<double> u0;
+    HostBuf u0;
     int R = 0;
     double t_submit = 0, t_done = 0;
     bool placed = false, admitted = false, done = false;
@@ -51,7 +68,8 @@ class Server {
     Batch* batch = nullptr;
     int c_lo = 0, r_lo = 0;
     int64_t steps = 0;
-    std::vector<double> u_out, lam, seps, energy;
+    HostBuf u_out;
+    std::vector<double> lam, seps, energy;
     std::vector<int32_t> labels;
   };
   struct Batch {
