@@ -407,6 +407,14 @@ void Solver::push_tables() {
   all_live_ = true;
   for (int c = 0; c < rp_; ++c)
     if (h_seg_len_[c] > 0 && !h_live_[c]) all_live_ = false;
+  // the node step's simple kernel: every column in a restart that starts and
+  // ends on a multiple of 4 and does not cross a 256-column tile edge
+  int fast = args_.ts.tg == 64;
+  for (int c = 0; c < rp_ && fast; ++c) {
+    const int lo = h_seg_lo_[c], len = h_seg_len_[c];
+    fast = len > 0 && ((lo | len) & 3) == 0 && lo / 256 == (lo + len - 1) / 256;
+  }
+  args_.nodal_fast = fast;
   const int nres = args_.ct.nres;
   args_.ct.nres = nres;
   SP_HIP(hipMemcpyAsync(const_cast<int*>(args_.ct.seg_lo), h_seg_lo_.data(), rp_ * sizeof(int),

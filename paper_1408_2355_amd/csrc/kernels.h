@@ -49,6 +49,9 @@ struct StepArgs {
   Tile t64;  // tiling of the kernels that gather float64 values (solve set-up,
              // norms, Rayleigh quotients); same n, rp
   int W;
+  int nodal_fast = 0;  // set by the host when every column group lies in one 4-aligned
+                       // restart inside its 256-column tile (ts one row per
+                       // wavefront): the node step then runs without its general path
   const int* cols;
   const double* M64;
   const double* A64;

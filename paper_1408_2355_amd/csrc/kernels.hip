@@ -993,6 +993,7 @@ __global__ void k_red_outer(StepArgs a, int oslot, int onext) {
 // columns outside the tile, read from the row.  Every lane of a row group
 // takes part in the shuffles; lanes past the last column group carry empty
 // segments.
+template <bool General>
 __global__ __launch_bounds__(kBlock) void k_nodal(StepArgs a, const double* __restrict__ u,
                                                   double* __restrict__ out, int keep) {
   const Tile& t = a.ts;
@@ -1035,7 +1036,8 @@ __global__ __launch_bounds__(kBlock) void k_nodal(StepArgs a, const double* __re
     const int lane = threadIdx.x & 63;
     const bool one_seg = in && lo[0] == lo[3] && len[0] > 0 && ((lo[0] | len[0]) & 3) == 0 &&
                          lo[0] >= tile_lo && lo[0] + len[0] <= tile_hi;
-    const bool lanes = tg == 64 && __all(!in || one_seg);
+    // (General = false: the host has checked that every wavefront qualifies)
+    const bool lanes = !General || (tg == 64 && __all(!in || one_seg));
     const int ls = one_seg ? (lo[0] - tile_lo) >> 2 : lane, le = one_seg ? ls + (len[0] >> 2) : lane + 1;
     for_rows(t, [&](int row) {
       const double* ur = u + size_t(row) * t.rp;
@@ -1044,7 +1046,7 @@ __global__ __launch_bounds__(kBlock) void k_nodal(StepArgs a, const double* __re
         uv = ld4s(ur + c0);
         ov = mixed ? ld4s(out + size_t(row) * t.rp + c0) : uv;
       }
-      if (lanes) {
+      if (!General || lanes) {
         double v = 0.0;
         for (int j = 0; j < 4; ++j) v = fma(uv.v[j], uv.v[j], v);
         for (int d = 1; d < 64 && __any(lane + d < le); d <<= 1) {
@@ -2333,7 +2335,10 @@ void red_outer(const StepArgs& a, int o, hipStream_t s) {
 }
 
 void nodal(const StepArgs& a, const double* u, double* out, bool keep, hipStream_t s) {
-  hipLaunchKernelGGL(k_nodal, dim3(a.ts.nblk), dim3(kBlock), 0, s, a, u, out, int(keep));
+  if (a.nodal_fast && a.ts.tg == 64)
+    hipLaunchKernelGGL(k_nodal<false>, dim3(a.ts.nblk), dim3(kBlock), 0, s, a, u, out, int(keep));
+  else
+    hipLaunchKernelGGL(k_nodal<true>, dim3(a.ts.nblk), dim3(kBlock), 0, s, a, u, out, int(keep));
   SP_LAUNCH_CHECK();
 }
 
