@@ -123,3 +123,26 @@ def test_wide_batch_node_step_paths(gpu, precision, bar):
         ref = flow.run(prob, u0[col0[r]:col0[r + 1]], [ms[r]], [0.1], 15)
         assert rel(out["u"][col0[r]:col0[r + 1]], ref["u"]) < bar
         assert abs(out["energy"][r] - ref["energy"][0]) < bar * ref["energy"][0]
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_node_step_restarts_of_any_length_across_tile_edges(gpu, precision, bar):
+    """Restarts of unaligned length that cross both 256-column tile edges
+    (m = 7 from column 255, m = 60 from column 496), a 250-column restart
+    starting on column 5 and short odd ones, on the multi-kernel path: every
+    restart's state after 10 steps against the oracle's steps (the state only:
+    the oracle's pair sum for S_eps is quadratic in m)."""
+    v, f = icosphere(2)
+    n = v.shape[0]
+    ms = [5, 250, 7, 31, 3, 200, 60]
+    eps = [0.2] * len(ms)
+    u0 = uniform_u0(45, 1, sum(ms), n)
+    print(f"restarts {ms} ({sum(ms)} columns), 10 steps, {precision}", flush=True)
+    out = run_gpu(v, f, ms, eps, u0, 1e-3, 10, precision)
+    prob = flow.Problem(v, f, 1e-3)
+    col0 = np.concatenate([[0], np.cumsum(ms)])
+    for r in range(len(ms)):
+        u = flow.normalise(prob.M, u0[col0[r]:col0[r + 1]])
+        for _ in range(10):
+            u = flow.step(prob, u, eps[r])
+        assert rel(out["u"][col0[r]:col0[r + 1]], u) < bar, r
