@@ -46,7 +46,9 @@ extern "C" {
 #endif
 
 #define SP_VERSION_MAJOR 1
-#define SP_VERSION_MINOR 1  /* 1.1: continuation, partition post-processing, multipliers */
+#define SP_VERSION_MINOR 2  /* 1.1: continuation, partition post-processing, multipliers;
+                               1.2: checkpoint/restore, sp_stats.hbm_bytes, per-column
+                               extrapolation history */
 
 enum sp_status {
   SP_OK = 0,
@@ -135,8 +137,16 @@ typedef struct {
                            while fewer steps have been taken.  The solution is the
                            same to cg_rtol, only the start moves.  Costs q float32
                            vectors and one float64 vector per batch.  0 = start
-                           from u.  Ignored in SP_FP64 (always starts from u)       */
+                           from u.  Ignored in SP_FP64 (always starts from u).
+                           Each column keeps its own history: a request admitted
+                           to a running server batch starts from its own state
+                           and the resident columns keep theirs                 */
 } sp_params;
+/* There is no fixed-iteration-count mode: the CG stops on its tolerance.  The
+ * CPU reference this library is checked against solves each heat step exactly
+ * (sparse LU), so a fixed iteration count would compare a different
+ * computation; the parity tests run the float64 solves to a tight cg_rtol
+ * (1e-12 to 1e-14) instead. */
 
 /* Fill *p with defaults for time step tau: n_steps 100, stop_tol 1e-6,
  * max_steps 10^6, energy_every = round(0.1 / tau), SP_MIXED, cg_rtol 1e-10,
@@ -152,6 +162,12 @@ typedef struct {
   double seconds;          /* wall time of the call                                   */
   int32_t converged;       /* 1 if every solve met its tolerance                      */
   int32_t reserved;
+  double hbm_bytes;        /* algorithmic (minimum) HBM bytes of the kernels run so far,
+                              by the per-element model of each kernel: the CG
+                              iterations over the columns still iterating (counted on
+                              the device), every other pass over all live columns (an
+                              upper bound where a kernel skips converged columns), and
+                              the matrix once per gathering launch; not a measurement */
 } sp_stats;
 
 /* ------------------------------------------------------------- batch solve --
@@ -215,9 +231,30 @@ int sp_state_energy(sp_state* st, double* lambda, double* s_eps, double* energy)
 int sp_state_multipliers(sp_state* st, double* lambda_eps);
 /* Copy the current state out ([sum m][n_vert], host) and the step counter. */
 int sp_state_read(sp_state* st, double* u, int64_t* step);
-/* Overwrite the state (checkpoint restore / parity set-up) and step counter;
- * normalise != 0 scales each component to unit L2 norm first. */
+/* Overwrite the state (parity set-up, a new start) and step counter;
+ * normalise != 0 scales each component to unit L2 norm first.  The heat
+ * increments kept for the extrapolated start are forgotten (the next step
+ * starts from u), so in SP_MIXED a run continued from sp_state_read /
+ * sp_state_write agrees with the uninterrupted one only to the solver
+ * tolerance; sp_state_checkpoint / sp_state_restore continue it exactly. */
 int sp_state_write(sp_state* st, const double* u, int64_t step, int32_t normalise);
+/* Checkpoint and resume.  *bytes receives the size of a checkpoint image of
+ * the state: the state itself, the per-column solver scalars and history
+ * lengths, the kept heat increments and the last normalisation's A v (SP_MIXED
+ * with extrapolate > 0), the tilings the kernels used, the step counter and
+ * the energy history.  The image is opaque, in the library's internal layout
+ * (renumbered vertices, padded columns) and version. */
+int sp_state_checkpoint_size(sp_state* st, int64_t* bytes);
+/* Write the image into buf (host, caller-owned, bytes >= the size above;
+ * SP_EINVAL otherwise).  Synchronous. */
+int sp_state_checkpoint(sp_state* st, void* buf, int64_t bytes);
+/* Replace the state by an image written by sp_state_checkpoint for the same
+ * batch: same mesh size, column layout, precision, extrapolate, tau and
+ * restarts (m, eps) -- SP_EINVAL otherwise, with the state unchanged.  After
+ * the restore the run continues exactly (bit for bit) as the one that wrote
+ * the image would have.  Not for states restricted to regions
+ * (sp_region_eigen's internal use). */
+int sp_state_restore(sp_state* st, const void* buf, int64_t bytes);
 /* Labels of the current state, [n_restarts][n_vert] each (nullable). */
 int sp_state_labels(sp_state* st, int32_t* labels, int32_t* labels_argmax);
 /* Energy history of restart r: up to cap (step, E) pairs, oldest first;
@@ -275,6 +312,11 @@ int sp_server_wait(sp_server* srv, int64_t ticket, double timeout_s);
  * not finished, SP_ENOTFOUND for an unknown ticket. */
 int sp_server_fetch(sp_server* srv, int64_t ticket, double* u_out, int32_t* labels,
                     double* lambda, double* s_eps, double* energy, double* latency_s);
+/* Cost of a finished request (before sp_server_fetch): CG iterations summed
+ * over its components (inner iterations in SP_MIXED) and the time steps it
+ * took.  SP_EAGAIN if not finished, SP_ENOTFOUND for an unknown or fetched
+ * ticket.  Nullable outputs. */
+int sp_server_request_stats(sp_server* srv, int64_t ticket, int64_t* col_iters, int64_t* steps);
 /* Latency percentiles over finished requests, achieved component-DOF updates
  * per second since the first submit, and the number of finished requests. */
 int sp_server_stats(sp_server* srv, double* p50_s, double* p99_s, double* cdof_per_s,

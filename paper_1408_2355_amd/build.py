@@ -23,7 +23,7 @@ LIB = os.path.join(PKG, "libsegpart.so")
 
 ARCH = "gfx950"
 SOURCES = ["kernels.hip", "prolong.hip", "mesh.cpp", "engine.cpp", "autotune.cpp", "server.cpp",
-           "continuation.cpp", "partition.cpp", "capi.cpp"]
+           "continuation.cpp", "partition.cpp", "checkpoint.cpp", "capi.cpp"]
 
 
 def hipcc():

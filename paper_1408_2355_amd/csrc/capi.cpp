@@ -159,8 +159,10 @@ int sp_solve(const sp_mesh* mesh, const sp_params* prm, int32_t n_restarts, cons
              sp_stats* stats) {
   return guard([&] {
     const double t0 = now_s();
-    SP_REQUIRE(mesh && mesh->m && prm, SP_EINVAL, "NULL mesh or params");
+    SP_REQUIRE(prm, SP_EINVAL, "NULL params");
+    sp::validate_params(*prm);
     sp::BatchSpec spec = make_spec(n_restarts, m, eps);
+    SP_REQUIRE(mesh && mesh->m, SP_EINVAL, "NULL mesh");
     sp::Solver S(mesh->m.get(), *prm, spec, nullptr);  // private stream
     S.upload_host(u0, true);
     if (prm->n_steps > 0)
@@ -182,9 +184,11 @@ int sp_solve_async(const sp_mesh* mesh, const sp_params* prm, int32_t n_restarts
                    int32_t* d_labels, int32_t* d_labels_argmax, double* d_lambda,
                    double* d_s_eps, double* d_energy, void* hip_stream) {
   return guard([&] {
-    SP_REQUIRE(mesh && mesh->m && prm, SP_EINVAL, "NULL mesh or params");
+    SP_REQUIRE(prm, SP_EINVAL, "NULL params");
+    sp::validate_params(*prm);
     SP_REQUIRE(prm->n_steps > 0, SP_EINVAL, "sp_solve_async needs n_steps > 0");
     sp::BatchSpec spec = make_spec(n_restarts, m, eps);
+    SP_REQUIRE(mesh && mesh->m, SP_EINVAL, "NULL mesh");
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);  // NULL = default stream
     auto* S = new sp::Solver(mesh->m.get(), *prm, spec, &s);
     int rc = SP_OK;
@@ -228,8 +232,10 @@ int sp_state_create(const sp_mesh* mesh, const sp_params* prm, int32_t n_restart
   return guard([&] {
     SP_REQUIRE(out != nullptr, SP_EINVAL, "NULL out");
     *out = nullptr;
-    SP_REQUIRE(mesh && mesh->m && prm, SP_EINVAL, "NULL mesh or params");
+    SP_REQUIRE(prm, SP_EINVAL, "NULL params");
+    sp::validate_params(*prm);
     sp::BatchSpec spec = make_spec(n_restarts, m, eps);
+    SP_REQUIRE(mesh && mesh->m, SP_EINVAL, "NULL mesh");
     std::unique_ptr<sp_state> st(new sp_state());
     st->mesh = mesh->m.get();
     hipStream_t hs = reinterpret_cast<hipStream_t>(hip_stream);
@@ -295,6 +301,30 @@ int sp_state_write(sp_state* st, const double* u, int64_t step, int32_t normalis
     SP_REQUIRE(step >= 0, SP_EINVAL, "step must be >= 0");
     st->solver->upload_host(u, normalise != 0);
     st->solver->set_steps_done(step);
+    return SP_OK;
+  });
+}
+
+int sp_state_checkpoint_size(sp_state* st, int64_t* bytes) {
+  return guard([&] {
+    SP_REQUIRE(st && st->solver && bytes, SP_EINVAL, "NULL state or output");
+    *bytes = st->solver->checkpoint_size();
+    return SP_OK;
+  });
+}
+
+int sp_state_checkpoint(sp_state* st, void* buf, int64_t bytes) {
+  return guard([&] {
+    SP_REQUIRE(st && st->solver, SP_EINVAL, "NULL state");
+    st->solver->checkpoint(buf, bytes);
+    return SP_OK;
+  });
+}
+
+int sp_state_restore(sp_state* st, const void* buf, int64_t bytes) {
+  return guard([&] {
+    SP_REQUIRE(st && st->solver, SP_EINVAL, "NULL state");
+    st->solver->restore(buf, bytes);
     return SP_OK;
   });
 }
@@ -380,10 +410,11 @@ int sp_server_submit(sp_server* srv, const sp_mesh* mesh, const sp_params* prm,
                      int32_t n_restarts, const int32_t* m, const double* eps, const double* u0,
                      int64_t* ticket) {
   return guard([&] {
-    SP_REQUIRE(srv && srv->srv && mesh && mesh->m && prm && ticket, SP_EINVAL, "NULL argument");
+    SP_REQUIRE(srv && srv->srv && prm && ticket, SP_EINVAL, "NULL argument");
     sp::validate_params(*prm);
     SP_REQUIRE(prm->n_steps > 0, SP_EINVAL, "server requests need n_steps > 0");
     sp::BatchSpec spec = make_spec(n_restarts, m, eps);
+    SP_REQUIRE(mesh && mesh->m, SP_EINVAL, "NULL mesh");
     *ticket = srv->srv->submit(mesh->m.get(), *prm, spec, u0);
     return SP_OK;
   });
@@ -417,6 +448,14 @@ int sp_server_stats(sp_server* srv, double* p50_s, double* p99_s, double* cdof_p
   return guard([&] {
     SP_REQUIRE(srv && srv->srv, SP_EINVAL, "NULL server");
     srv->srv->stats(p50_s, p99_s, cdof_per_s, completed);
+    return SP_OK;
+  });
+}
+
+int sp_server_request_stats(sp_server* srv, int64_t ticket, int64_t* col_iters, int64_t* steps) {
+  return guard([&] {
+    SP_REQUIRE(srv && srv->srv, SP_EINVAL, "NULL server");
+    srv->srv->request_stats(ticket, col_iters, steps);
     return SP_OK;
   });
 }

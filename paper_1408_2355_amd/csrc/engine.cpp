@@ -24,7 +24,7 @@ namespace sp {
 
 namespace {
 enum { CF_BB, CF_RZ, CF_TOL2, CF_ALPHA, CF_BETA, CF_RRO, CF_NRM, CF_BBN, CF_ISC, CF_COEF, CF_N };
-enum { CI_ACT, CI_ACTO, CI_ITERS, CI_SWEEPS, CI_SEGLO, CI_SEGLEN, CI_LIVE, CI_N };
+enum { CI_ACT, CI_ACTO, CI_ITERS, CI_SWEEPS, CI_SEGLO, CI_SEGLEN, CI_LIVE, CI_HLEN, CI_N };
 constexpr int kSepsNperMax = 512;  // S_eps element-kernel workgroups per XCD, at most
 }  // namespace
 
@@ -200,6 +200,7 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     a.ct.seg_lo = ci + CI_SEGLO * rp_;
     a.ct.seg_len = ci + CI_SEGLEN * rp_;
     a.ct.live = ci + CI_LIVE * rp_;
+    a.hlen = ci + CI_HLEN * rp_;
     a.ct.res_lo = ci + CI_N * rp_;
     a.ct.res_len = ci + CI_N * rp_ + nres_p_;
     a.ct.res_live = ci + CI_N * rp_ + 2 * nres_p_;
@@ -212,6 +213,7 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
 
     // column tables: restart r owns columns [lo_r, lo_r + m_r)
     h_seg_lo_.assign(rp_, 0);
+    h_hlen_.assign(rp_, 0);
     h_seg_len_.assign(rp_, 0);
     h_live_.assign(rp_, 0);
     h_coef_.assign(rp_, 0.0);
@@ -409,6 +411,8 @@ void Solver::push_tables() {
     if (h_seg_len_[c] > 0 && !h_live_[c]) all_live_ = false;
   // the node step's simple kernel: every column in a restart that starts and
   // ends on a multiple of 4 and does not cross a 256-column tile edge
+  live_cols_ = 0;
+  for (int c = 0; c < rp_; ++c) live_cols_ += (h_seg_len_[c] > 0 && h_live_[c]) ? 1 : 0;
   int fast = args_.ts.tg == 64;
   for (int c = 0; c < rp_ && fast; ++c) {
     const int lo = h_seg_lo_[c], len = h_seg_len_[c];
@@ -494,15 +498,23 @@ int Solver::poll(const int* dev_counter) {
 
 void Solver::sync() { SP_HIP(hipStreamSynchronize(s_)); }
 
+void Solver::acct(double per_elem, double extra) {
+  fixed_bytes_ += per_elem * double(mesh_->n) * double(live_cols_) + extra;
+}
+
+double Solver::mat_bytes(double value_bytes, int n_mats) const {
+  return double(mesh_->n) * double(mesh_->W) * (4.0 + value_bytes * n_mats);
+}
+
 void Solver::upload_host(const double* u0, bool normalise) {
   flush_scale();
   aw_fresh_ = false;
   SP_REQUIRE(u0 != nullptr, SP_EINVAL, "NULL u0");
-  n_prev_ = 0;
   lam_fresh_ = false;
   const size_t cnt = size_t(R_) * mesh_->n;
   for (size_t i = 0; i < cnt; ++i)
     SP_REQUIRE(std::isfinite(u0[i]), SP_EINVAL, "u0 holds a non-finite value");
+  forget_history(0, rp_);
   DevBuf<double> tmp(cnt);
   SP_HIP(hipMemcpyAsync(tmp.p, u0, cnt * sizeof(double), hipMemcpyHostToDevice, s_));
   k::pack(args_.t, 0, R_, tmp.p, mesh_->perm_d.p, u_.p, s_);
@@ -516,8 +528,8 @@ void Solver::upload_device(const double* d_u0, bool normalise, bool check_norms)
   flush_scale();
   aw_fresh_ = false;
   SP_REQUIRE(d_u0 != nullptr, SP_EINVAL, "NULL u0");
-  n_prev_ = 0;
   lam_fresh_ = false;
+  forget_history(0, rp_);
   k::pack(args_.t, 0, R_, d_u0, mesh_->perm_d.p, u_.p, s_);
   if (normalise) {
     if (check_norms) {
@@ -551,9 +563,18 @@ void Solver::pack_range(int c_lo, int Rq, const double* d_src) {
   flush_scale();
   aw_fresh_ = false;
   SP_REQUIRE(c_lo >= 0 && Rq >= 0 && c_lo + Rq <= rp_, SP_EINVAL, "column range");
-  n_prev_ = 0;  // the new columns have no previous increment
+  // the new columns have no previous increment; the other columns keep theirs
+  // (each column extrapolates from its own history)
+  forget_history(c_lo, Rq);
   lam_fresh_ = false;
   k::pack(args_.t, c_lo, Rq, d_src, mesh_->perm_d.p, u_.p, s_);
+}
+
+void Solver::forget_history(int c_lo, int cnt) {
+  if (c_lo == 0 && cnt >= rp_) n_prev_ = 0;
+  if (cnt <= 0) return;
+  std::fill(h_hlen_.begin() + c_lo, h_hlen_.begin() + c_lo + cnt, 0);
+  k::fill_i32(args_.hlen + c_lo, 0, size_t(cnt), s_);
 }
 
 void Solver::unpack_range(int c_lo, int Rq, double* d_dst) {
@@ -596,6 +617,7 @@ void Solver::heat_fp64() {
   flush_scale();
   k::fill_i32(ring_.p, 0, ring_.n, s_);
   k::init_fp64(args_, u_.p, r64_.p, p64_.p, s_);
+  acct(24.0, mat_bytes(8.0, 2));
   k::red_init_fp64(args_, s_);
   int last = 0;
   for (int it = 0; it < prm_.cg_max_iter; ++it) {
@@ -625,34 +647,41 @@ void Solver::heat_mixed() {
     // g = sum_j (-1)^j C(use, j+1) d_{k-j}, e.g. 3 d_k - 3 d_{k-1} + d_{k-2};
     // g overwrites the oldest kept increment (acc) and x0 goes to xg_
     const int use = std::min(n_prev_, q);
-    if (!(use == 1 && acc == dh_[0])) {
+    // q = 1 keeps the newest increment in acc already: nothing to form
+    // unless some live column has no history yet
+    bool skip = use == 1 && acc == dh_[0];
+    for (int c = 0; c < rp_ && skip; ++c) skip = !h_live_[c] || h_hlen_[c] >= 1;
+    if (!skip) {
       ExtrapArgs e;
       e.n = use;
-      int binom = 1;  // C(use, j + 1), built up from C(use, 0) = 1
-      for (int j = 0; j < use; ++j) {
-        binom = binom * (use - j) / (j + 1);
-        e.x[j] = dh_[j];
-        e.c[j] = float((j % 2 == 0) ? binom : -binom);
-      }
+      for (int j = 0; j < use; ++j) e.x[j] = dh_[j];
       k::extrap(args_, e, acc, s_);
+      acct(4.0 * use + 4.0);
     }
     if (fast) {
       // A u and ||M u||^2 from the last step's norm pass: no float64 gather
       k::refine_start(args_, xg_.p, acc, r64_.p, r32_.p, p32_.p, s_);
+      acct(28.0, mat_bytes(8.0, 1));
     } else {
       k::init_outer(args_, u_.p, acc, xg_.p, r64_.p, s_);
+      acct(32.0, mat_bytes(8.0, 3));
       k::red_outer_init(args_, s_);
     }
     x = xg_.p;
   } else {
     k::init_outer(args_, u_.p, nullptr, nullptr, r64_.p, s_);
+    acct(16.0, mat_bytes(8.0, 2));
     k::red_outer_init(args_, s_);
-    if (extrap) k::fill_f32(acc, 0.0f, dbuf_[0].n, s_);
+    if (extrap) {
+      k::fill_f32(acc, 0.0f, dbuf_[0].n, s_);
+      acct(4.0);
+    }
   }
   int olast = 0;
   for (int o = 0; o < prm_.max_outer; ++o) {
     if (!(fast && o == 0)) {
       k::inner_init(args_, o, r64_.p, d32_.p, r32_.p, p32_.p, s_);
+      acct(16.0);
       k::red_inner_init(args_, o, s_);
     }
     // inner CG in direction-ring form: d is formed from the stored
@@ -673,19 +702,25 @@ void Solver::heat_mixed() {
       if (prm_.check_every > 0 && last % prm_.check_every == 0 && last < prm_.cg_max_iter)
         if (poll(ring_.p + last % kRing) == 0) break;
     }
-    if (last % kPRing) k::materialize(args_, pring_, ah_.p, 0, last % kPRing, flushed, d32_.p, s_);
+    if (last % kPRing) {
+      k::materialize(args_, pring_, ah_.p, 0, last % kPRing, flushed, d32_.p, s_);
+      acct(4.0 * (last % kPRing) + (flushed ? 8.0 : 4.0));
+    }
+    acct(4.0 * (last - last % kPRing) + 12.0 * (last / kPRing));  // ring folds inside the solve
     // with a poll after this sweep the new residual is stored only if
     // another sweep follows (most steps need one)
     const bool polled = prm_.check_every > 0 && o + 1 < prm_.max_outer;
     const bool ubase = fast && o == 0;
     args_.usc = ubase && u_pending_ ? args_.cg.isc : nullptr;
     k::outer_update(args_, o, x, ubase ? u_.p : nullptr, r64_.p, d32_.p, acc, !polled, s_);
+    acct(28.0 + (polled ? 0.0 : 8.0) + (acc ? 8.0 : 0.0), mat_bytes(8.0, 1));
     args_.usc = nullptr;
     k::red_outer(args_, o, s_);
     olast = o + 1;
     if (polled) {
       if (poll(args_.oring + olast % kRing) == 0) break;
       k::outer_residual(args_, olast, r64_.p, d32_.p, s_);
+      acct(20.0, mat_bytes(8.0, 1));
     }
   }
   k::flag_nonconv(args_, args_.oring + olast % kRing, s_);
@@ -693,6 +728,8 @@ void Solver::heat_mixed() {
     for (int i = q - 1; i > 0; --i) dh_[i] = dh_[i - 1];
     dh_[0] = acc;
     n_prev_ = std::min(n_prev_ + 1, q);
+    k::hist_advance(args_, q, s_);
+    for (int c = 0; c < rp_; ++c) h_hlen_[c] = h_live_[c] ? std::min(h_hlen_[c] + 1, q) : 0;
   }
   heat_x_ = x;
 }
@@ -754,10 +791,12 @@ void Solver::node_to_r() {
     // node step writes v into u_, whose pending state the solve has used
     u_pending_ = false;
     k::nodal(args_, heat_x_, u_.p, true, s_);
+    acct(16.0);
     node_out_ = u_.p;
   } else {
     flush_scale();
     k::nodal(args_, heat_x_, r64_.p, false, s_);
+    acct(16.0);
     node_out_ = r64_.p;
   }
   heat_x_ = u_.p;
@@ -768,11 +807,14 @@ void Solver::norm_dot_scale(const double* v, bool defer) {
   // step) for the next step's refinement start
   double* w = (xg_.p && (v == r64_.p || defer)) ? xg_.p : nullptr;
   k::norm_dot(args_, v, w, s_);
+  acct(w ? 16.0 : 8.0, mat_bytes(8.0, 2));
   k::red_norm(args_, lam_.p, s_);
-  if (defer)
+  if (defer) {
     u_pending_ = true;  // v is in u_; the state is v * isc
-  else
+  } else {
     k::scale(args_, v, u_.p, s_);
+    acct(16.0);
+  }
   lam_fresh_ = all_live_;
   aw_fresh_ = w != nullptr;
 }
@@ -781,6 +823,7 @@ void Solver::flush_scale() {
   if (!u_pending_) return;
   u_pending_ = false;
   k::scale(args_, u_.p, u_.p, s_);
+  acct(16.0);
 }
 
 void Solver::stage_node() {
@@ -803,10 +846,14 @@ void Solver::energy() {
   // right after a normalisation of every column the Rayleigh quotients are
   // already in lam (see red_norm); otherwise evaluate them now
   const bool need_rq = !lam_fresh_;
-  if (need_rq) k::energy_rq(args_, u_.p, s_);  // quotients: the pending factor cancels
+  if (need_rq) {
+    k::energy_rq(args_, u_.p, s_);  // quotients: the pending factor cancels
+    acct(8.0, mat_bytes(8.0, 2));
+  }
   if (sp_.wide) flush_scale();
   args_.usc = u_pending_ ? args_.cg.isc : nullptr;
   k::energy_seps(args_, sp_, mesh_->tri.p, mesh_->tarea.p, u_.p, part_s_.p, s_);
+  acct(8.0, double(mesh_->nt) * 20.0);
   args_.usc = nullptr;
   k::red_energy(args_, sp_, part_s_.p, need_rq, lam_.p, seps_.p, energy_.p, s_);
 }
@@ -873,7 +920,7 @@ void Solver::step_small(int64_t k) {
     k -= chunk;
   }
   lam_fresh_ = all_live_;
-  n_prev_ = 0;
+  forget_history(0, rp_);
   aw_fresh_ = false;
   heat_x_ = u_.p;
 }
@@ -962,10 +1009,29 @@ sp_stats Solver::stats() {
   out.outer_sweeps = st[1];
   out.col_iters_max = it.empty() ? 0 : *std::max_element(it.begin(), it.end());
   out.converged = st[2] == 0;
+  // CG iterations: the columns still iterating (device count) x the three
+  // kernels' bytes per element, and the matrix once per iteration with work
+  const bool f64 = prm_.precision == SP_FP64 || small_;
+  const double n = double(mesh_->n);
+  out.hbm_bytes = fixed_bytes_ + double(st[3]) * n * (f64 ? 88.0 : 32.0) +
+                  double(st[0]) * mat_bytes(f64 ? 8.0 : 4.0, 1);
   return out;
 }
 
 bool Solver::converged() { return stats().converged != 0; }
+
+int64_t Solver::column_iters(int c_lo, int cnt) {
+  SP_REQUIRE(c_lo >= 0 && cnt >= 0 && c_lo + cnt <= rp_, SP_EINVAL, "column range");
+  std::vector<int> it(size_t(cnt) + 1);
+  if (cnt > 0) {
+    SP_HIP(hipMemcpyAsync(it.data(), args_.cg.iters + c_lo, size_t(cnt) * sizeof(int),
+                          hipMemcpyDeviceToHost, s_));
+    SP_HIP(hipStreamSynchronize(s_));
+  }
+  int64_t tot = 0;
+  for (int i = 0; i < cnt; ++i) tot += it[i];
+  return tot;
+}
 
 const hipEvent_t* Solver::prof_events() {
   if (!prof_) return nullptr;

@@ -81,6 +81,9 @@ class Solver {
   const std::vector<std::vector<std::pair<int64_t, double>>>& history() const { return hist_; }
   sp_stats stats();
   bool converged();
+  // sum over columns [c_lo, c_lo + cnt) of the CG iterations each has taken
+  // (cumulative since the solver was made; synchronous)
+  int64_t column_iters(int c_lo, int cnt);
 
   // event timing of the three large CG kernels (0 matrix product, 1 x/r
   // update, 2 p update) on the solver's stream
@@ -116,11 +119,23 @@ class Solver {
   void normalise_range(int c_lo, int Rq);
   // Skip the stream synchronisation in the destructor (work already done).
   void detach() { detached_ = true; }
-  // Forget the previous heat increment (the next step starts from x0 = u).
+  // Forget the previous heat increments of every column (the next step
+  // starts from x0 = u).
   void reset_guess() {
-    n_prev_ = 0;
+    forget_history(0, rp_);
     aw_fresh_ = false;
   }
+  // Graph replay of the inner CG blocks (on by default; off for batches whose
+  // stream shares the device with other threads' launches, e.g. the server's).
+  void set_graphs(bool on) { graph_on_ = on && graph_on_; }
+
+  // Checkpoint of the whole device state (checkpoint.cpp): its size in bytes,
+  // the image written to a host buffer, and its restore into a solver of the
+  // same batch (mesh size, columns, precision, extrapolation depth, tau, m,
+  // eps), after which the run continues exactly as the one that wrote it.
+  int64_t checkpoint_size();
+  void checkpoint(void* buf, int64_t bytes);
+  void restore(const void* buf, int64_t bytes);
 
   bool record_history = true;          // copy energies to the host at the cadence
   std::vector<int64_t> restart_steps;  // per restart: steps taken (stop mode)
@@ -135,6 +150,14 @@ class Solver {
   void flush_scale();
   int poll(const int* dev_counter);
   void push_tables();
+  // algorithmic HBM bytes (sp_stats.hbm_bytes): per_elem x n x live columns
+  // + extra, for a pass over the live columns (kernels that skip converged
+  // columns are counted in full: an upper bound); the CG iterations are
+  // counted exactly in stats() from the device's active-column counter
+  void acct(double per_elem, double extra = 0.0);
+  double mat_bytes(double value_bytes, int n_mats) const;  // ELL pattern + n_mats value arrays
+  double fixed_bytes_ = 0.0;
+  int live_cols_ = 0;
   std::vector<Tile> tile_candidates() const;
   TuneChoice tune_tiling(const std::string& key, Tile StepArgs::*field,
                          const std::function<void()>& launch);
@@ -161,7 +184,10 @@ class Solver {
   // then the ring rotates so that buffer becomes dh_[0]
   DevBuf<float> dbuf_[kMaxExtrap];
   float* dh_[kMaxExtrap] = {};
-  int n_prev_ = 0;  // increments available (0 .. prm_.extrapolate)
+  int n_prev_ = 0;  // increments available to some column (0 .. prm_.extrapolate)
+  std::vector<int> h_hlen_;  // host copy of the per-column history lengths (args_.hlen)
+  // columns [c_lo, c_lo + cnt) have no previous increment (all columns: n_prev_ = 0)
+  void forget_history(int c_lo, int cnt);
   DevBuf<double> xg_;          // iterate of a solve started from u + g (u stays b's source)
   double* heat_x_ = nullptr;   // where the last heat solve left its result (u_ or xg_)
   bool small_ = false;         // whole steps in one workgroup (small batches)

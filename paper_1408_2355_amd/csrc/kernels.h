@@ -73,6 +73,8 @@ struct StepArgs {
   const uint8_t* mask = nullptr;
   ColTab ct;
   CgCols cg;
+  int* hlen = nullptr;  // per column: heat increments kept for the extrapolated
+                        // start (0 .. extrapolate)
   double* part;        // [3][nchunk][rp] partial sums
   int* ring;           // [kRing] inner active counts
   int* oring;          // [kRing] outer active counts
@@ -89,11 +91,11 @@ struct RingArgs {
   int accumulate = 0;    // 0: d = sum, 1: d += sum
 };
 
-// Linear combination of up to kMaxExtrap float32 vectors (start guess).
+// Extrapolated start: the kept heat increments, newest first (up to
+// kMaxExtrap); each column uses as many as its history length allows.
 constexpr int kMaxExtrap = 8;
 struct ExtrapArgs {
   const float* x[kMaxExtrap] = {};
-  float c[kMaxExtrap] = {};
   int n = 0;
 };
 
@@ -184,9 +186,11 @@ void outer_update(const StepArgs& a, int o, double* x, const double* ubase, doub
                   const float* d, float* dacc, bool store_r, hipStream_t s);
 // r64 -= K d on the columns still refining after sweep o - 1
 void outer_residual(const StepArgs& a, int o, double* r64, const float* d, hipStream_t s);
-// y = sum_j e.c[j] e.x[j] on the live columns, 0 on the others; y may be
-// one of the sources
+// y = sum_{j < h_c} (-1)^j C(h_c, j+1) e.x[j] per live column c, h_c =
+// min(hlen[c], e.n); 0 on the others; y may be one of the sources
 void extrap(const StepArgs& a, const ExtrapArgs& e, float* y, hipStream_t s);
+// hlen[c] = live ? min(hlen[c] + 1, q) : 0 (after a heat solve)
+void hist_advance(const StepArgs& a, int q, hipStream_t s);
 void red_outer(const StepArgs& a, int o, hipStream_t s);
 // node step and normalisation
 // keep: columns that are not live keep out's value (out is the state)

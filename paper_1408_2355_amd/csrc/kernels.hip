@@ -172,6 +172,15 @@ __device__ __forceinline__ double red_sum(const double* p, int nchunk, int rp, i
   return tot;
 }
 
+// x * s rounded on its own, never fused with a following add: a column factor
+// applied as a value is read (deferred normalisation) then gives bit for bit
+// the value a scaled copy of the state holds (k_scale), whichever route a step
+// takes.
+__device__ __forceinline__ double mul_alone(double x, double s) {
+#pragma clang fp contract(off)
+  return x * s;
+}
+
 // Count the columns for which flag is set, into *counter (one atomic per wave).
 __device__ __forceinline__ void count_active(int flag, int* counter) {
   unsigned long long bal = __ballot(flag);
@@ -596,28 +605,53 @@ __global__ __launch_bounds__(kBlock) void k_materialize(StepArgs a, RingArgs ra,
   }
 }
 
-// y = sum_j e.c[j] e.x[j] on the live columns, 0 elsewhere.  y may be one of
-// the sources (each element is read before it is written, by the same thread).
+// Start guess of the heat solve, per column c: y = sum_{j<h} (-1)^j C(h, j+1)
+// x_j, the polynomial extrapolation through the column's last h heat
+// increments x_0 (newest), x_1, ..., with h = min(hlen[c], e.n); 0 on columns
+// that are not live or have no increment yet (a column admitted to a running
+// batch starts from its own state while the others keep their history).  y
+// may be one of the sources (each element is read before it is written, by
+// the same thread).  A source whose 4 coefficients are 0 is not read.
 __global__ __launch_bounds__(kBlock) void k_extrap(StepArgs a, ExtrapArgs e, float* y) {
   const Tile& t = a.ts;
   for (int ct = 0; ct < t.nct; ++ct) {
     const int g = ct * t.tg + threadIdx.x % t.tg;
     if (g >= t.G) continue;
     const int cb = 4 * g;
-    bool lv[4];
-    for (int j = 0; j < 4; ++j) lv[j] = a.ct.live[cb + j] != 0;
+    float cf[kMaxExtrap][4];
+    for (int j = 0; j < 4; ++j) {
+      const int h = a.ct.live[cb + j] ? min(a.hlen[cb + j], e.n) : 0;
+      int binom = 1;  // C(h, q + 1), built up from C(h, 0) = 1
+      for (int q = 0; q < kMaxExtrap; ++q) {
+        if (q < h) {
+          binom = binom * (h - q) / (q + 1);
+          cf[q][j] = float((q % 2 == 0) ? binom : -binom);
+        } else {
+          cf[q][j] = 0.0f;
+        }
+      }
+    }
     for_rows(t, [&](int row) {
       const size_t o = size_t(row) * t.rp + cb;
       float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
       for (int q = 0; q < e.n; ++q) {
+        if (cf[q][0] == 0.0f && cf[q][1] == 0.0f && cf[q][2] == 0.0f && cf[q][3] == 0.0f) continue;
         const V4<float> v = ld4s(e.x[q] + o);
-        for (int j = 0; j < 4; ++j) acc[j] = fmaf(e.c[q], v.v[j], acc[j]);
+        for (int j = 0; j < 4; ++j) acc[j] = cf[q][j] != 0.0f ? fmaf(cf[q][j], v.v[j], acc[j]) : acc[j];
       }
       V4<float> yv;
-      for (int j = 0; j < 4; ++j) yv.v[j] = lv[j] ? acc[j] : 0.0f;
+      for (int j = 0; j < 4; ++j) yv.v[j] = acc[j];
       st4s(y + o, yv);
     });
   }
+}
+
+// After a heat solve: every live column has one more increment kept (at most
+// q); a column that is not live has none (its stored increment is 0).
+__global__ void k_hist_advance(StepArgs a, int q) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.t.rp) return;
+  a.hlen[c] = a.ct.live[c] ? min(a.hlen[c] + 1, q) : 0;
 }
 
 // p = D r + beta p
@@ -905,7 +939,7 @@ __global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot,
         V4<double> xv;
         if (ubase) {
           const V4<double> ub = ld4g(ubase + o);
-          for (int j = 0; j < 4; ++j) xv.v[j] = ub.v[j] * usc[j] + double(av.v[j]);
+          for (int j = 0; j < 4; ++j) xv.v[j] = mul_alone(ub.v[j], usc[j]) + double(av.v[j]);
         } else {
           xv = ld4g(x + o);
         }
@@ -2325,6 +2359,11 @@ void outer_residual(const StepArgs& a, int o, double* r64, const float* d, hipSt
 
 void extrap(const StepArgs& a, const ExtrapArgs& e, float* y, hipStream_t s) {
   hipLaunchKernelGGL(k_extrap, dim3(a.ts.nblk), dim3(kBlock), 0, s, a, e, y);
+  SP_LAUNCH_CHECK();
+}
+
+void hist_advance(const StepArgs& a, int q, hipStream_t s) {
+  hipLaunchKernelGGL(k_hist_advance, dim3((a.t.rp + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a, q);
   SP_LAUNCH_CHECK();
 }
 

@@ -44,7 +44,7 @@ void Solver::set_region_mask(const int32_t* labels, bool interior) {
   SP_HIP(hipMemcpyAsync(mask_.p, mk.data(), mk.size(), hipMemcpyHostToDevice, s_));
   args_.mask = mask_.p;
   small_ = false;  // the one-workgroup path has no restriction
-  n_prev_ = 0;
+  forget_history(0, rp_);
   aw_fresh_ = false;
   lam_fresh_ = false;
   k::apply_mask(args_, u_.p, s_);

@@ -46,14 +46,19 @@ Server::Server(int64_t budget_bytes, int max_cols) : budget_(budget_bytes), max_
 }
 
 Server::~Server() {
+  // Stop the admission thread first: after it has exited no batch is opened
+  // or reaped any more, so batches_ is this thread's alone.
   {
     std::lock_guard<std::mutex> g(mu_);
     stop_ = true;
-    for (auto& b : batches_) b->quit = true;
   }
   cv_.notify_all();
-  for (auto& b : batches_) b->cv.notify_all();
   if (adm_.joinable()) adm_.join();
+  {
+    std::lock_guard<std::mutex> g(mu_);
+    for (auto& b : batches_) b->quit = true;
+  }
+  for (auto& b : batches_) b->cv.notify_all();
   for (auto& b : batches_)
     if (b->th.joinable()) b->th.join();
   batches_.clear();
@@ -78,7 +83,9 @@ int64_t Server::batch_bytes(const Mesh* m, const sp_params& p, int cap, int rcap
       (p.precision != SP_FP64 && p.extrapolate ? 8.0 + 4.0 * p.extrapolate : 0.0);
   const double mats = double(m->W) * n * (4 + 8 + 8 + 8 + 4) + n * 28.0 + double(m->nt) * 20.0;
   const double part = 3.0 * 8.0 * cap * (n / 64.0 + 1.0);
-  return int64_t(n * cap * per_col + mats + part + 64.0 * (cap + rcap) + (1 << 20));
+  // staging of request state (admission and retirement) and of labels
+  const double stage = 8.0 * n * cap + 4.0 * n * rcap;
+  return int64_t(n * cap * per_col + mats + part + stage + 64.0 * (cap + rcap) + (1 << 20));
 }
 
 int64_t Server::submit(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const double* u0) {
@@ -198,6 +205,7 @@ void Server::admission_loop() {
         ++it;
       }
     }
+    if (stop_) break;  // set while a batch was being reaped
     for (auto it = queue_.begin(); it != queue_.end();) {
       if (try_place(*it))
         it = queue_.erase(it);
@@ -248,12 +256,13 @@ void Server::apply_tables(Batch* b, const Tables& t) {
 
 void Server::admit(Batch* b, Request* q) {
   const size_t cnt = size_t(q->R) * b->mesh->n;
-  DevBuf<double> tmp(cnt);
-  SP_HIP(hipMemcpyAsync(tmp.p, q->u0.data(), cnt * sizeof(double), hipMemcpyHostToDevice,
+  SP_REQUIRE(cnt <= b->stage.n, SP_EINVAL, "server: request larger than its batch");
+  SP_HIP(hipMemcpyAsync(b->stage.p, q->u0.data(), cnt * sizeof(double), hipMemcpyHostToDevice,
                         b->solver->stream()));
-  b->solver->pack_range(q->c_lo, q->R, tmp.p);
+  b->solver->pack_range(q->c_lo, q->R, b->stage.p);
   b->solver->normalise_range(q->c_lo, q->R);
   b->solver->sync();
+  q->iters0 = b->solver->column_iters(q->c_lo, q->R);
   q->u0.clear();
 }
 
@@ -270,14 +279,16 @@ void Server::retire(Batch* b, Request* q) {
                         hipMemcpyDeviceToHost, S.stream()));
   SP_HIP(hipMemcpyAsync(q->energy.data(), S.d_energy() + q->r_lo, nres * sizeof(double),
                         hipMemcpyDeviceToHost, S.stream()));
-  DevBuf<double> tmp(size_t(q->R) * n);
-  S.unpack_range(q->c_lo, q->R, tmp.p);
+  const size_t cnt = size_t(q->R) * n;
+  q->col_iters = S.column_iters(q->c_lo, q->R) - q->iters0;
+  S.unpack_range(q->c_lo, q->R, b->stage.p);
   // first touch of the output pages on many threads, then the copy
-  q->u_out.alloc(size_t(q->R) * n);
+  q->u_out.alloc(cnt);
   par_for(q->u_out.n, [&](size_t lo, size_t hi) {
     std::memset(q->u_out.data() + lo, 0, (hi - lo) * sizeof(double));
   });
-  SP_HIP(hipMemcpyAsync(q->u_out.data(), tmp.p, tmp.bytes(), hipMemcpyDeviceToHost, S.stream()));
+  SP_HIP(hipMemcpyAsync(q->u_out.data(), b->stage.p, cnt * sizeof(double), hipMemcpyDeviceToHost,
+                        S.stream()));
   S.sync();
 }
 
@@ -300,6 +311,13 @@ void Server::batch_loop(Batch* b) {
   try {
     b->solver.reset(new Solver(b->mesh, b->prm, BatchSpec{}, nullptr, b->cap, b->rcap));
     b->solver->record_history = false;
+    // Batch threads share the device: no graph capture on them (a capture
+    // on one thread would run beside other threads' launches and device
+    // allocations), and no device allocation after set-up: request state and
+    // labels go through staging buffers sized for the batch.
+    b->solver->set_graphs(false);
+    b->stage.alloc(size_t(b->cap) * size_t(b->mesh->n));
+    b->lab.alloc(size_t(b->rcap) * size_t(b->mesh->n));
   } catch (const Error& e) {
     std::vector<Request*> v;
     {
@@ -376,11 +394,12 @@ void Server::batch_loop(Batch* b) {
             nres_used = std::max(nres_used, q->r_lo + int(q->spec.m.size()));
         }
         const int64_t n = b->mesh->n;
-        DevBuf<int32_t> lab(size_t(std::max(nres_used, 1)) * n);
-        b->solver->labels_device(lab.p, nullptr);
-        lab_dev_host.resize(size_t(std::max(nres_used, 1)) * n);
-        SP_HIP(hipMemcpyAsync(lab_dev_host.data(), lab.p, lab.bytes(), hipMemcpyDeviceToHost,
-                              b->solver->stream()));
+        const size_t nlab = size_t(std::max(nres_used, 1)) * n;
+        SP_REQUIRE(nlab <= b->lab.n, SP_EINVAL, "server: restart slots beyond the batch");
+        b->solver->labels_device(b->lab.p, nullptr);
+        lab_dev_host.resize(nlab);
+        SP_HIP(hipMemcpyAsync(lab_dev_host.data(), b->lab.p, nlab * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, b->solver->stream()));
         for (Request* q : fin) {
           retire(b, q);  // synchronises the stream
           const int nres = int(q->spec.m.size());
@@ -435,6 +454,8 @@ void Server::batch_loop(Batch* b) {
   }
   if (!left.empty()) fail_all(left, SP_EAGAIN, "server stopped before the request finished");
   b->solver.reset();
+  b->stage.release();
+  b->lab.release();
   std::lock_guard<std::mutex> g(mu_);
   used_ -= b->bytes;
   b->exited = true;
@@ -478,6 +499,16 @@ int Server::fetch(int64_t ticket, double* u_out, int32_t* labels, double* lambda
   if (energy) std::copy(q->energy.begin(), q->energy.end(), energy);
   if (latency_s) *latency_s = q->t_done - q->t_submit;
   return SP_OK;
+}
+
+void Server::request_stats(int64_t ticket, int64_t* col_iters, int64_t* steps) {
+  std::lock_guard<std::mutex> g(mu_);
+  auto it = reqs_.find(ticket);
+  SP_REQUIRE(it != reqs_.end(), SP_ENOTFOUND, "unknown ticket");
+  const Request& q = *it->second;
+  SP_REQUIRE(q.done, SP_EAGAIN, "request not finished");
+  if (col_iters) *col_iters = q.col_iters;
+  if (steps) *steps = q.steps;
 }
 
 void Server::stats(double* p50, double* p99, double* cdof_per_s, int64_t* completed) {

@@ -51,6 +51,8 @@ class Server {
   int fetch(int64_t ticket, double* u_out, int32_t* labels, double* lambda, double* seps,
             double* energy, double* latency_s);
   void stats(double* p50, double* p99, double* cdof_per_s, int64_t* completed);
+  // CG iterations summed over a finished request's columns, and its steps
+  void request_stats(int64_t ticket, int64_t* col_iters, int64_t* steps);
 
  private:
   struct Batch;
@@ -68,6 +70,7 @@ class Server {
     Batch* batch = nullptr;
     int c_lo = 0, r_lo = 0;
     int64_t steps = 0;
+    int64_t iters0 = 0, col_iters = 0;  // column CG iterations at admission / taken
     HostBuf u_out;
     std::vector<double> lam, seps, energy;
     std::vector<int32_t> labels;
@@ -78,6 +81,8 @@ class Server {
     int cap = 0, rcap = 0;
     int64_t bytes = 0;
     std::unique_ptr<Solver> solver;
+    DevBuf<double> stage;             // [cap][n] request state in caller layout
+    DevBuf<int32_t> lab;              // [rcap][n] labels of the restart slots
     std::vector<Request*> col_owner;  // per column slot
     std::vector<Request*> res_owner;  // per restart slot
     std::vector<Request*> pending;    // placed, waiting for the step boundary

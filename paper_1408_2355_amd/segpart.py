@@ -46,7 +46,8 @@ class sp_params(C.Structure):
 class sp_stats(C.Structure):
     _fields_ = [("steps_done", C.c_int64), ("cg_iters", C.c_int64),
                 ("outer_sweeps", C.c_int64), ("col_iters_max", C.c_int64),
-                ("seconds", C.c_double), ("converged", C.c_int32), ("reserved", C.c_int32)]
+                ("seconds", C.c_double), ("converged", C.c_int32), ("reserved", C.c_int32),
+                ("hbm_bytes", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -99,6 +100,9 @@ _SIGS = {
     "sp_state_multipliers": (C.c_int, [P, D]),
     "sp_state_write": (C.c_int, [P, D, C.c_int64, C.c_int32]),
     "sp_state_labels": (C.c_int, [P, I32, I32]),
+    "sp_state_checkpoint_size": (C.c_int, [P, I64]),
+    "sp_state_checkpoint": (C.c_int, [P, P, C.c_int64]),
+    "sp_state_restore": (C.c_int, [P, P, C.c_int64]),
     "sp_state_history": (C.c_int, [P, C.c_int32, C.c_int64, I64, D, I64]),
     "sp_state_stats": (C.c_int, [P, C.POINTER(sp_stats)]),
     "sp_state_profile": (C.c_int, [P, C.c_int32]),
@@ -111,6 +115,7 @@ _SIGS = {
     "sp_server_wait": (C.c_int, [P, C.c_int64, C.c_double]),
     "sp_server_fetch": (C.c_int, [P, C.c_int64, D, I32, D, D, D, D]),
     "sp_server_stats": (C.c_int, [P, D, D, D, I64]),
+    "sp_server_request_stats": (C.c_int, [P, C.c_int64, I64, I64]),
     "sp_server_destroy": (None, [P]),
     "sp_mesh_refine": (C.c_int, [P, PROJECT_FN, P, PP]),
     "sp_mesh_parents": (C.c_int, [P, I32, I64]),
@@ -473,6 +478,24 @@ def sp_state_multipliers(h, R):
     return out
 
 
+def sp_state_checkpoint_size(h):
+    b = C.c_int64()
+    _check(lib().sp_state_checkpoint_size(h, C.byref(b)))
+    return b.value
+
+
+def sp_state_checkpoint(h):
+    """The state's checkpoint image as a numpy uint8 array."""
+    buf = np.empty(sp_state_checkpoint_size(h), np.uint8)
+    _check(lib().sp_state_checkpoint(h, buf.ctypes.data_as(P), buf.size))
+    return buf
+
+
+def sp_state_restore(h, image):
+    image = np.ascontiguousarray(image, np.uint8)
+    _check(lib().sp_state_restore(h, image.ctypes.data_as(P), image.size))
+
+
 def sp_state_labels(h, nres, n):
     a = np.empty((nres, n), np.int32)
     b = np.empty_like(a)
@@ -553,6 +576,12 @@ def sp_server_fetch(h, ticket, R, nres, n):
     return out
 
 
+def sp_server_request_stats(h, ticket):
+    it, st = C.c_int64(), C.c_int64()
+    _check(lib().sp_server_request_stats(h, int(ticket), C.byref(it), C.byref(st)))
+    return dict(col_iters=it.value, steps=st.value)
+
+
 def sp_server_stats(h):
     p50, p99, cd, n = C.c_double(), C.c_double(), C.c_double(), C.c_int64()
     _check(lib().sp_server_stats(h, C.byref(p50), C.byref(p99), C.byref(cd), C.byref(n)))
@@ -587,6 +616,14 @@ class State:
     def write(self, u, step=0, normalise=False):
         sp_state_write(self.h, u, step, normalise)
 
+    def checkpoint(self):
+        """Checkpoint image (numpy uint8) of the whole device state."""
+        return sp_state_checkpoint(self.h)
+
+    def restore(self, image):
+        """Continue exactly from an image of sp_state_checkpoint (same batch)."""
+        sp_state_restore(self.h, image)
+
     def multipliers(self):
         """lambda_i^eps [sum m] of the current state."""
         return sp_state_multipliers(self.h, self.R)
@@ -620,16 +657,22 @@ class State:
 
 
 class Server:
-    """Owner of an sp_server handle (continuous-batching request loop)."""
+    """Owner of an sp_server handle (continuous-batching request loop).
+
+    Each request runs on its mesh's device buffers until it is fetched, so
+    the Mesh object is kept referenced per ticket until then (and until the
+    server is closed)."""
 
     def __init__(self, hbm_budget_bytes, max_batch_columns=0):
         self.h = sp_server_create(hbm_budget_bytes, max_batch_columns)
         self._shape = {}
+        self._mesh = {}
 
     def submit(self, mesh, prm, m, eps, u0):
         mm, _, _ = _batch(m, eps)
         t = sp_server_submit(self.h, mesh.h, prm, m, eps, u0)
         self._shape[t] = (int(mm.sum()), mm.size, mesh.n_vert)
+        self._mesh[t] = mesh
         return t
 
     def poll(self, ticket):
@@ -638,10 +681,21 @@ class Server:
     def wait(self, ticket, timeout_s=600.0):
         return sp_server_wait(self.h, ticket, timeout_s)
 
+    def request_stats(self, ticket):
+        """CG column-iterations and steps of a finished, not yet fetched request."""
+        return sp_server_request_stats(self.h, ticket)
+
     def fetch(self, ticket):
         R, nres, n = self._shape[ticket]
-        out = sp_server_fetch(self.h, ticket, R, nres, n)
+        try:
+            out = sp_server_fetch(self.h, ticket, R, nres, n)
+        except SegpartError as e:
+            if e.code != SP_EAGAIN:  # the request is gone (failed): release it
+                self._shape.pop(ticket, None)
+                self._mesh.pop(ticket, None)
+            raise
         del self._shape[ticket]
+        del self._mesh[ticket]
         return out
 
     def stats(self):
@@ -649,7 +703,9 @@ class Server:
 
     def close(self):
         if getattr(self, "h", None):
-            sp_server_destroy(self.h)
+            sp_server_destroy(self.h)  # stops every batch before the meshes go
             self.h = None
+        if getattr(self, "_mesh", None):
+            self._mesh.clear()
 
     __del__ = close

@@ -146,3 +146,47 @@ def test_node_step_restarts_of_any_length_across_tile_edges(gpu, precision, bar)
         for _ in range(10):
             u = flow.step(prob, u, eps[r])
         assert rel(out["u"][col0[r]:col0[r + 1]], u) < bar, r
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
+def test_nonfinite_initial_state_is_rejected(gpu, bad):
+    """A NaN or infinite value anywhere in u0 is SP_EINVAL from every entry
+    point that takes a host u0 (validated before the upload)."""
+    v, f = icosphere(2)
+    mesh = sp.Mesh(v, f)
+    u0 = uniform_u0(43, 2, 3, v.shape[0])
+    u0[4, 17] = bad
+    prm = sp.params(1e-3, n_steps=2, precision="mixed", energy_every=0)
+    with pytest.raises(sp.SegpartError) as e:
+        sp.solve(mesh, prm, [3, 3], [0.1, 0.1], u0)
+    assert e.value.code == sp.SP_EINVAL and "non-finite" in str(e.value)
+    with pytest.raises(sp.SegpartError) as e:
+        sp.State(mesh, prm, [3, 3], [0.1, 0.1], u0)
+    assert e.value.code == sp.SP_EINVAL and "non-finite" in str(e.value)
+    srv = sp.Server(1 << 30, 64)
+    with pytest.raises(sp.SegpartError) as e:
+        srv.submit(mesh, prm, [3, 3], [0.1, 0.1], u0)
+    assert e.value.code == sp.SP_EINVAL and "non-finite" in str(e.value)
+    srv.close()
+    mesh.close()
+
+
+def test_hbm_bytes_model_is_plausible(gpu):
+    """sp_stats.hbm_bytes: the modelled algorithmic bytes per component-DOF
+    update of a mixed run lie between one CG iteration's worth and the float64
+    form's per-step bound (32 B per inner iteration per element plus the fixed
+    passes)."""
+    v, f = icosphere(5)
+    mesh = sp.Mesh(v, f)
+    u0 = uniform_u0(44, 4, 8, v.shape[0])
+    prm = sp.params(5e-4, n_steps=5, precision="mixed", energy_every=1)
+    st = sp.State(mesh, prm, [8] * 4, [0.1] * 4, u0)
+    st.step(5)
+    s = st.stats()
+    st.close()
+    mesh.close()
+    per_cdof = s["hbm_bytes"] / (32 * v.shape[0] * 5)
+    iters = s["cg_iters"] / 5
+    print(f"hbm_bytes {s['hbm_bytes']:.3e}, {per_cdof:.0f} B per cdof update, "
+          f"{iters:.1f} iterations per step", flush=True)
+    assert 32 * 1 < per_cdof < 32 * iters + 400

@@ -2,7 +2,10 @@
 
 A request's result must not depend on which other requests share its batch:
 it is compared with the same request served alone (1e-10 relative in float64
-batches, 1e-5 in mixed) and with the CPU oracle.
+batches, 1e-5 in mixed) and with the CPU oracle.  In mixed precision the heat
+solves start from an extrapolation of each column's own previous increments;
+requests admitted into a running batch must not disturb the residents'
+extrapolation, which shows in the residents' CG iteration counts.
 """
 import time
 
@@ -98,6 +101,56 @@ def test_mixed_request_matches_oracle_in_mix(meshes):
     assert rel(out["lam"], ref["lam"]) < 1e-5
     assert rel(out["energy"], ref["energy"]) < 1e-5
     srv.close()
+
+
+def test_mixed_request_alone_equals_result_in_mix(meshes):
+    """A mixed-precision request (extrapolated starts, 5 increments) served
+    alone, then again while other requests are admitted into its running batch
+    one after another: same u, lambda, S_eps and E within 1e-5 (the mixed
+    bar), both against the oracle too, and no extra CG iterations for it (each
+    admission used to drop every resident's extrapolation history)."""
+    v, f, mesh = meshes[4]
+    steps, m, nres, eps, tau = 400, 4, 2, 0.1, 1e-3
+
+    def prm(n_steps):
+        return sp.params(tau, precision="mixed", n_steps=n_steps, energy_every=0)
+
+    u0 = uniform_u0(301, nres, m, v.shape[0])
+    print("server mixed alone", flush=True)
+    srv = sp.Server(8 << 30, 128)
+    t = srv.submit(mesh, prm(steps), [m] * nres, [eps] * nres, u0)
+    assert srv.wait(t, 300)
+    st_alone = srv.request_stats(t)
+    alone = srv.fetch(t)
+    assert st_alone["steps"] == steps and st_alone["col_iters"] > 0
+    print("server mixed mix", flush=True)
+    ta = srv.submit(mesh, prm(steps), [m] * nres, [eps] * nres, u0)
+    during, k = 0, 0
+    while not srv.poll(ta) and k < 12:
+        ub = uniform_u0(310 + k, 1, 3, v.shape[0])
+        tb = srv.submit(mesh, prm(10), [3], [0.08], ub)    # joins the running batch
+        assert srv.wait(tb, 120)
+        if not srv.poll(ta):
+            during += 1
+        out_b = srv.fetch(tb)
+        assert np.isfinite(out_b["energy"]).all()
+        k += 1
+    assert srv.wait(ta, 300)
+    st_mix = srv.request_stats(ta)
+    mix = srv.fetch(ta)
+    srv.close()
+    print(f"admissions during the run {during}; column CG iterations alone "
+          f"{st_alone['col_iters']}, in the mix {st_mix['col_iters']}", flush=True)
+    assert during >= 2, "the other requests did not overlap the resident one"
+    for key in ("u", "lam", "s_eps", "energy"):
+        assert rel(mix[key], alone[key]) < 1e-5, key
+    ref = flow.run(flow.Problem(v, f, tau), u0, [m] * nres, [eps] * nres, steps)
+    for key in ("u", "lam", "s_eps", "energy"):
+        assert rel(alone[key], ref[key]) < 1e-5, key
+        assert rel(mix[key], ref[key]) < 1e-5, key
+    # the resident kept its start guesses: its iteration count does not grow
+    # with the admissions (a lost history costs ~10 iterations per column each)
+    assert st_mix["col_iters"] <= 1.02 * st_alone["col_iters"] + 2 * m * nres
 
 
 def test_budget_and_ticket_errors(meshes):
