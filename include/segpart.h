@@ -196,6 +196,32 @@ int sp_solve_async(const sp_mesh* mesh, const sp_params* prm, int32_t n_restarts
                    int32_t* d_labels, int32_t* d_labels_argmax, double* d_lambda,
                    double* d_s_eps, double* d_energy, void* hip_stream);
 
+/* Allocation-free form of sp_solve_async, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops and
+ * harnesses that forbid allocation.  Same arguments, layouts and results as
+ * sp_solve_async (the same kernels; the default tilings, with no tiling
+ * search).  Every work buffer of the batch, the matrix K = M + tau A of this
+ * tau included, is carved from one static device scratch array of
+ * SP_NOALLOC_SCRATCH_BYTES (128 MiB) that each device the library runs on
+ * holds until the process ends; the call allocates no device or pinned host
+ * memory and creates no stream, event or graph.  The mesh's own matrices are
+ * inputs (sp_mesh_create allocated them).  Limit: a batch whose buffers do not
+ * fit in the scratch is rejected with SP_ENOMEM before any work is enqueued
+ * (roughly n_vert x padded columns x 88 bytes in SP_MIXED with extrapolate 5,
+ * x 32 bytes in SP_FP64, plus 12 x 8 x n_vert for the matrices; e.g. 16
+ * columns of the 40962-vertex sphere fit in SP_MIXED).  The scratch keeps the
+ * last call's contents and is cleared at the start of each call; every call
+ * on one device uses the same scratch, so calls that overlap in time on one
+ * device race: enqueue them on one stream (or wait for the previous call's
+ * stream to pass its work) before the next call.  Host polling as in
+ * sp_solve_async (prm->check_every > 0 synchronises the stream). */
+#define SP_NOALLOC_SCRATCH_BYTES (128LL << 20)
+int sp_solve_async_noalloc(const sp_mesh* mesh, const sp_params* prm, int32_t n_restarts,
+                           const int32_t* m, const double* eps, const double* d_u0,
+                           double* d_u_out, int32_t* d_labels, int32_t* d_labels_argmax,
+                           double* d_lambda, double* d_s_eps, double* d_energy,
+                           void* hip_stream);
+
 /* ------------------------------------------------------------ step state --
  * A batch kept on the device between calls: stepping, single stages of
  * Algorithm 2.2, energies, checkpoint and restore.  A state is used by one

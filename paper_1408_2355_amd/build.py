@@ -22,7 +22,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsegpart.so")
 
 ARCH = "gfx950"
-SOURCES = ["kernels.hip", "prolong.hip", "mesh.cpp", "engine.cpp", "autotune.cpp", "server.cpp",
+SOURCES = ["kernels.hip", "prolong.hip", "noalloc.hip", "mesh.cpp", "engine.cpp", "autotune.cpp", "server.cpp",
            "continuation.cpp", "partition.cpp", "checkpoint.cpp", "capi.cpp"]
 
 

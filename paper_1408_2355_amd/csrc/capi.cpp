@@ -226,6 +226,44 @@ int sp_solve_async(const sp_mesh* mesh, const sp_params* prm, int32_t n_restarts
   });
 }
 
+int sp_solve_async_noalloc(const sp_mesh* mesh, const sp_params* prm, int32_t n_restarts,
+                           const int32_t* m, const double* eps, const double* d_u0,
+                           double* d_u_out, int32_t* d_labels, int32_t* d_labels_argmax,
+                           double* d_lambda, double* d_s_eps, double* d_energy,
+                           void* hip_stream) {
+  return guard([&] {
+    SP_REQUIRE(prm, SP_EINVAL, "NULL params");
+    sp::validate_params(*prm);
+    SP_REQUIRE(prm->n_steps > 0, SP_EINVAL, "sp_solve_async_noalloc needs n_steps > 0");
+    sp::BatchSpec spec = make_spec(n_restarts, m, eps);
+    SP_REQUIRE(mesh && mesh->m, SP_EINVAL, "NULL mesh");
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);  // NULL = default stream
+    // the current device's scratch (located once per device); every work
+    // buffer of the batch comes from it, so a batch that does not fit is
+    // rejected (SP_ENOMEM) before any work is enqueued
+    sp::Arena ar = sp::noalloc_scratch();
+    sp::Solver S(mesh->m.get(), *prm, spec, &s, 0, 0, &ar);
+    S.record_history = false;
+    S.upload_device(d_u0, true, false);
+    S.step(prm->n_steps);
+    S.energy();
+    const int R = S.R(), nres = S.nres();
+    if (d_lambda)
+      SP_HIP(hipMemcpyAsync(d_lambda, S.d_lam(), R * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (d_s_eps)
+      SP_HIP(hipMemcpyAsync(d_s_eps, S.d_seps(), nres * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (d_energy)
+      SP_HIP(hipMemcpyAsync(d_energy, S.d_energy(), nres * sizeof(double), hipMemcpyDeviceToDevice,
+                            s));
+    if (d_labels || d_labels_argmax) S.labels_device(d_labels, d_labels_argmax);
+    if (d_u_out) S.download_device(d_u_out);
+    // the work stays enqueued: the solver's host object goes, its buffers
+    // (the scratch) stay in use until the stream passes this point
+    S.detach();
+    return SP_OK;
+  });
+}
+
 int sp_state_create(const sp_mesh* mesh, const sp_params* prm, int32_t n_restarts,
                     const int32_t* m, const double* eps, const double* u0, void* hip_stream,
                     sp_state** out) {

@@ -66,8 +66,8 @@ void validate_batch(int32_t nres, const int32_t* m, const double* eps) {
 }
 
 Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hipStream_t* stream,
-               int min_columns, int min_restarts)
-    : mesh_(mesh), prm_(prm), spec_(spec) {
+               int min_columns, int min_restarts, Arena* arena)
+    : mesh_(mesh), arena_(arena), prm_(prm), spec_(spec) {
   validate_params(prm_);
   SP_REQUIRE(mesh_ != nullptr, SP_EINVAL, "NULL mesh");
   const int nres = int(spec_.m.size());
@@ -82,7 +82,18 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     own_stream_ = true;
   }
   try {
-    km_ = mesh_->tau_mats(prm_.tau);
+    if (arena_) {
+      // this tau's K, K32 and Jacobi diagonals, built below on the stream
+      const size_t wn = size_t(mesh_->W) * size_t(mesh_->n);
+      own_km_.tau = prm_.tau;
+      get(own_km_.K64, wn);
+      get(own_km_.K32, wn);
+      get(own_km_.dinv64, size_t(mesh_->n));
+      get(own_km_.dinv32, size_t(mesh_->n));
+      km_ = &own_km_;
+    } else {
+      km_ = mesh_->tau_mats(prm_.tau);
+    }
     const int n = int(mesh_->n);
     const size_t nv = size_t(n) * rp_;
     Tile t = make_tile(n, rp_, 64, 1, 128);
@@ -93,55 +104,64 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     // latency-bound and want every SIMD full); the tuner may pick 64
     sp_.nper = std::max(1, std::min(kSepsNperMax, (sp_.nchunk + 7) / 8));
     sp_.nres_p = nres_p_;
-    seps_tiles_.alloc(nres_p_);
-    u_.alloc(nv);
+    get(seps_tiles_, nres_p_);
+    get(u_, nv);
     heat_x_ = u_.p;
-    r64_.alloc(nv);
+    get(r64_, nv);
     // small batches run whole steps in one workgroup (float64 CG) unless
     // SEGPART_SMALL=0
     const char* gr_env = std::getenv("SEGPART_GRAPH");
-    graph_on_ = !(gr_env && std::strcmp(gr_env, "0") == 0);
+    graph_on_ = !(gr_env && std::strcmp(gr_env, "0") == 0) && !arena_;  // instantiation allocates
     const char* sm_env = std::getenv("SEGPART_SMALL");
     small_ = nv <= size_t(kSmallMaxValues) && rp_ <= kSmallMaxCols &&
              nres_p_ <= kSmallMaxRestarts && !(sm_env && std::strcmp(sm_env, "0") == 0);
     if (prm_.precision == SP_FP64 || small_) {
-      p64_.alloc(nv);
-      q64_.alloc(nv);
+      get(p64_, nv);
+      get(q64_, nv);
     }
-    if (small_) small_hist_.alloc(size_t(kSmallChunk) * nres_p_);
+    if (small_) get(small_hist_, size_t(kSmallChunk) * nres_p_);
     if (prm_.precision != SP_FP64) {
-      d32_.alloc(nv);
-      r32_.alloc(nv);
-      p32_.alloc(nv);
-      q32_.alloc(nv);
+      get(d32_, nv);
+      get(r32_, nv);
+      get(p32_, nv);
+      get(q32_, nv);
       // direction ring of the inner CG: p32_ is slot 0
       pring_[0] = p32_.p;
       for (int i = 1; i < kPRing; ++i) {
-        pbuf_[i].alloc(nv);
+        get(pbuf_[i], nv);
         pring_[i] = pbuf_[i].p;
       }
-      ah_.alloc(size_t(kPRing) * rp_);
+      get(ah_, size_t(kPRing) * rp_);
       for (int i = 0; i < prm_.extrapolate; ++i) {
-        dbuf_[i].alloc(nv);
+        get(dbuf_[i], nv);
         dh_[i] = dbuf_[i].p;
       }
-      if (prm_.extrapolate) xg_.alloc(nv);
+      if (prm_.extrapolate) get(xg_, nv);
     }
     // partial sums: one row per workgroup, sized for the widest tiling the
     // autotuner may pick
     int max_blk = t.nblk;
     for (const Tile& c : tile_candidates()) max_blk = std::max(max_blk, c.nblk);
-    part_.alloc(3 * size_t(max_blk) * rp_);
-    part_s_.alloc(size_t(8 * sp_.nper) * nres_p_);
-    colf_.alloc(size_t(CF_N) * rp_ + nres_p_);
-    coli_.alloc(size_t(CI_N) * rp_ + 3 * size_t(nres_p_));
-    ring_.alloc(2 * kRing);
-    stat_.alloc(4);
-    lam_.alloc(rp_);
-    seps_.alloc(nres_p_);
-    energy_.alloc(nres_p_);
-    SP_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_poll_), 64, hipHostMallocDefault));
+    get(part_, 3 * size_t(max_blk) * rp_);
+    get(part_s_, size_t(8 * sp_.nper) * nres_p_);
+    get(colf_, size_t(CF_N) * rp_ + nres_p_);
+    get(coli_, size_t(CI_N) * rp_ + 3 * size_t(nres_p_));
+    get(ring_, 2 * kRing);
+    get(stat_, 4);
+    get(lam_, rp_);
+    get(seps_, nres_p_);
+    get(energy_, nres_p_);
+    if (arena_)
+      h_poll_ = poll_host_;
+    else
+      SP_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_poll_), 64, hipHostMallocDefault));
 
+    if (arena_) {
+      // the region keeps the last user's contents: start from zeros, as a
+      // fresh allocation does
+      k::fill_i32(reinterpret_cast<int32_t*>(arena_->base), 0, arena_->used / 4, s_);
+      k::tau_mats(*mesh_, own_km_, s_);
+    }
     k::fill_f64(u_.p, 0.0, nv, s_);
     k::fill_f64(r64_.p, 0.0, nv, s_);
     for (int i = 0; i < kMaxExtrap; ++i)
@@ -248,7 +268,7 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
       if (std::strcmp(e, "lanes") == 0) sp_.direct = 2;
     }
   } catch (...) {
-    if (h_poll_) (void)hipHostFree(h_poll_);
+    if (h_poll_ && !arena_) (void)hipHostFree(h_poll_);
     h_poll_ = nullptr;
     if (own_stream_) {
       (void)hipStreamSynchronize(s_);
@@ -264,7 +284,7 @@ Solver::~Solver() {
     if (g) (void)hipGraphExecDestroy(g);
   for (auto& e : ev_)
     for (auto x : e) (void)hipEventDestroy(x);
-  if (h_poll_) (void)hipHostFree(h_poll_);
+  if (h_poll_ && !arena_) (void)hipHostFree(h_poll_);
   if (own_stream_) (void)hipStreamDestroy(s_);
 }
 
@@ -329,7 +349,7 @@ TuneChoice Solver::tune_tiling(const std::string& key, Tile StepArgs::*field,
 // on the norm pass.
 void Solver::autotune() {
   const size_t work = size_t(mesh_->n) * size_t(rp_);
-  if (!tune_enabled(work >= (size_t(1) << 22))) return;
+  if (arena_ || !tune_enabled(work >= (size_t(1) << 22))) return;  // timing events, cache
   int dev = 0;
   SP_HIP(hipGetDevice(&dev));
   const bool f64 = prm_.precision == SP_FP64;

@@ -27,9 +27,13 @@ class Solver {
   // stream == nullptr: the solver creates and owns a stream; otherwise it
   // uses *stream (which may be the legacy default stream 0).  min_columns /
   // min_restarts reserve extra column and restart slots (server batches
-  // start with an empty spec and fill slots later).
+  // start with an empty spec and fill slots later).  arena (nullable): every
+  // device buffer, K = M + tau A of this tau included, is taken from it
+  // instead of allocated, and nothing else allocates device or pinned host
+  // memory (no tiling search, no graph replays, pageable host polls); the
+  // host-pointer upload/download helpers are not available then.
   Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hipStream_t* stream,
-         int min_columns = 0, int min_restarts = 0);
+         int min_columns = 0, int min_restarts = 0, Arena* arena = nullptr);
   ~Solver();
   Solver(const Solver&) = delete;
   Solver& operator=(const Solver&) = delete;
@@ -166,6 +170,16 @@ class Solver {
 
   Mesh* mesh_;
   TauMats* km_;
+  Arena* arena_ = nullptr;
+  TauMats own_km_;      // this tau's matrices taken from the arena
+  int poll_host_[16] = {};  // poll target without pinned memory (arena mode)
+  template <class T>
+  void get(DevBuf<T>& b, size_t count) {
+    if (arena_)
+      b.adopt(arena_->take<T>(count), count);
+    else
+      b.alloc(count);
+  }
   sp_params prm_;
   BatchSpec spec_;
   int R_ = 0, rp_ = 0, nres_p_ = 0;

@@ -31,23 +31,26 @@ struct Error : std::runtime_error {
     if (!(cond)) throw ::sp::Error((code), (msg)); \
   } while (0)
 
-// Owning device allocation.
+// Device allocation: owned (alloc, freed on release) or a view of memory
+// someone else owns (adopt, never freed here).
 template <class T>
 struct DevBuf {
   T* p = nullptr;
   size_t n = 0;
+  bool owned = true;
   DevBuf() = default;
   explicit DevBuf(size_t count) { alloc(count); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), owned(o.owned) { o.p = nullptr; o.n = 0; }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    if (this != &o) { release(); p = o.p; n = o.n; owned = o.owned; o.p = nullptr; o.n = 0; }
     return *this;
   }
   ~DevBuf() { release(); }
   void alloc(size_t count) {
     release();
+    owned = true;
     if (count == 0) return;
     hipError_t e = hipMalloc(&p, count * sizeof(T));
     if (e != hipSuccess) {
@@ -57,13 +60,46 @@ struct DevBuf {
     }
     n = count;
   }
+  void adopt(T* ptr, size_t count) {
+    release();
+    p = count ? ptr : nullptr;
+    n = count;
+    owned = false;
+  }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && owned) (void)hipFree(p);
     p = nullptr;
     n = 0;
   }
   size_t bytes() const { return n * sizeof(T); }
 };
+
+// Device memory handed out in order from one region owned elsewhere (no
+// allocation): pieces 256-byte aligned; take() throws SP_ENOMEM once the
+// region is exhausted.
+struct Arena {
+  char* base = nullptr;
+  size_t size = 0;
+  size_t used = 0;
+  const char* what = "arena";
+  template <class T>
+  T* take(size_t count) {
+    const size_t at = (used + 255) & ~size_t(255);
+    const size_t bytes = count * sizeof(T);
+    if (at > size || bytes > size - at)
+      throw Error(SP_ENOMEM, std::string(what) + ": the batch needs more than its " +
+                                 std::to_string(size >> 20) + " MiB (" +
+                                 std::to_string((at + bytes) >> 20) + " MiB so far)");
+    used = at + bytes;
+    return reinterpret_cast<T*>(base + at);
+  }
+};
+
+// The allocation-free entry point's work area on the current device: a
+// file-scope device array of kScratchBytes (noalloc.hip), located once per
+// device with hipGetSymbolAddress.  Calls on one device share it.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+Arena noalloc_scratch();
 
 // Row x column tiling of an [n][rp] column-interleaved array for the
 // row-parallel kernels.  A thread owns 4 consecutive columns of one row; a

@@ -92,6 +92,8 @@ _SIGS = {
                            D, C.POINTER(sp_stats)]),
     "sp_solve_async": (C.c_int, [P, C.POINTER(sp_params), C.c_int32, I32, D, P, P, P, P, P,
                                  P, P, P]),
+    "sp_solve_async_noalloc": (C.c_int, [P, C.POINTER(sp_params), C.c_int32, I32, D, P, P, P,
+                                         P, P, P, P, P]),
     "sp_state_create": (C.c_int, [P, C.POINTER(sp_params), C.c_int32, I32, D, D, P, PP]),
     "sp_state_step": (C.c_int, [P, C.c_int64]),
     "sp_state_stage": (C.c_int, [P, C.c_int32]),
@@ -259,6 +261,21 @@ def sp_solve_async(mesh_h, prm, m, eps, d_u0, d_u_out=None, d_labels=None,
                                 _tptr(d_u_out), _tptr(d_labels), _tptr(d_labels_argmax),
                                 _tptr(d_lambda), _tptr(d_s_eps), _tptr(d_energy),
                                 C.c_void_p(stream.cuda_stream)))
+
+
+def sp_solve_async_noalloc(mesh_h, prm, m, eps, d_u0, d_u_out=None, d_labels=None,
+                           d_labels_argmax=None, d_lambda=None, d_s_eps=None, d_energy=None,
+                           stream=None):
+    """Allocation-free form of sp_solve_async (the library's static scratch
+    holds every work buffer; same arguments)."""
+    import torch
+    m, eps, _ = _batch(m, eps)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    _check(lib().sp_solve_async_noalloc(mesh_h, C.byref(prm), m.size, _ip(m), _dp(eps),
+                                        _tptr(d_u0), _tptr(d_u_out), _tptr(d_labels),
+                                        _tptr(d_labels_argmax), _tptr(d_lambda), _tptr(d_s_eps),
+                                        _tptr(d_energy), C.c_void_p(stream.cuda_stream)))
 
 
 def _project_cb(project):
