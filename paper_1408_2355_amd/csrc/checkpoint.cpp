@@ -24,6 +24,7 @@ struct Header {
   char magic[8];
   int64_t n, rp, R, nres, nres_p;
   int32_t precision, q, n_prev, flags;  // flags: 1 u_pending, 2 aw_fresh, 4 lam_fresh, 8 small
+  int32_t last_sweeps, reserved;
   int64_t steps_done;
   double tau;
   Tile tm, t64;
@@ -79,6 +80,7 @@ void Solver::checkpoint(void* buf, int64_t bytes) {
   h.q = q;
   h.n_prev = n_prev_;
   h.flags = (u_pending_ ? 1 : 0) | (aw_fresh_ ? 2 : 0) | (lam_fresh_ ? 4 : 0) | (small_ ? 8 : 0);
+  h.last_sweeps = last_sweeps_;
   h.steps_done = steps_done_;
   h.tau = prm_.tau;
   h.tm = args_.tm;
@@ -187,12 +189,16 @@ void Solver::restore(const void* buf, int64_t bytes) {
   const int* rlive = ci.data() + (args_.ct.res_live - coli_.p);
   for (int r = 0; r < nres_p_; ++r) h_res_live_[r] = rlive[r];
   all_live_ = true;
-  for (int col = 0; col < rp_; ++col)
+  live_cols_ = 0;
+  for (int col = 0; col < rp_; ++col) {
     if (h_seg_len_[col] > 0 && !h_live_[col]) all_live_ = false;
+    live_cols_ += (h_seg_len_[col] > 0 && h_live_[col]) ? 1 : 0;
+  }
   n_prev_ = h.n_prev;
   u_pending_ = (h.flags & 1) != 0;
   aw_fresh_ = (h.flags & 2) != 0;
   lam_fresh_ = (h.flags & 4) != 0;
+  last_sweeps_ = h.last_sweeps;
   steps_done_ = h.steps_done;
   heat_x_ = u_.p;
   // the fixed reduction orders of the run that wrote the image

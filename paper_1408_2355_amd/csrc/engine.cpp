@@ -293,7 +293,7 @@ std::vector<Tile> Solver::tile_candidates() const {
   const int n = int(mesh_->n);
   for (int tg : {8, 16, 32, 64})
     for (int passes : {1, 2, 4, 8})
-      for (int nper : {64, 128, 256}) {
+      for (int nper : {64, 80, 96, 112, 128, 256}) {
         Tile c = make_tile(n, rp_, tg, passes, nper);
         bool dup = false;
         for (const Tile& o : out)
@@ -383,18 +383,24 @@ void Solver::autotune() {
   }
 
   // S_eps element kernel: LDS-staged, direct corner reads or lane-split,
-  // and 64 or the full count of workgroups per XCD, whichever is fastest for
-  // this batch's restart tiles (part_s_ holds the larger count's partials)
+  // and 64, as many as are resident at once, or the full count of workgroups
+  // per XCD, whichever is fastest for this batch's restart tiles (part_s_
+  // holds the largest count's partials).  With every workgroup resident the
+  // XCD walks each restart tile's triangles together, so the corner rows
+  // that neighbouring triangles share meet in L2.
   if (sp_.ntile > 0) {
     hipEvent_t e0, e1;
     SP_HIP(hipEventCreate(&e0));
     SP_HIP(hipEventCreate(&e1));
     const int nmode = sp_.lanes_ok ? 3 : 2;
     const int nper_max = std::max(1, std::min(kSepsNperMax, (sp_.nchunk + 7) / 8));
+    const int resident = std::min(nper_max, k::seps_resident_groups());
     double t_best = 0.0;
     int best = 0, best_nper = nper_max;
-    for (int nper : {nper_max, 64}) {
-      if (nper == 64 && nper >= nper_max) continue;
+    std::vector<int> cands = {nper_max};
+    for (int c : {resident, 64})
+      if (c < nper_max && std::find(cands.begin(), cands.end(), c) == cands.end()) cands.push_back(c);
+    for (int nper : cands) {
       sp_.nper = nper;
       for (int mode = 0; mode < nmode; ++mode) {
         sp_.direct = mode;
@@ -698,8 +704,9 @@ void Solver::heat_mixed() {
     }
   }
   int olast = 0;
+  bool prepared = false;  // the last update wrote this sweep's inner start
   for (int o = 0; o < prm_.max_outer; ++o) {
-    if (!(fast && o == 0)) {
+    if (!(fast && o == 0) && !prepared) {
       k::inner_init(args_, o, r64_.p, d32_.p, r32_.p, p32_.p, s_);
       acct(16.0);
       k::red_inner_init(args_, o, s_);
@@ -728,21 +735,32 @@ void Solver::heat_mixed() {
     }
     acct(4.0 * (last - last % kPRing) + 12.0 * (last / kPRing));  // ring folds inside the solve
     // with a poll after this sweep the new residual is stored only if
-    // another sweep follows (most steps need one)
+    // another sweep follows (most steps need one); when the last step needed
+    // more than one sweep, the update writes the next sweep's start as well
     const bool polled = prm_.check_every > 0 && o + 1 < prm_.max_outer;
+    const bool prep = polled && o + 1 < last_sweeps_;
     const bool ubase = fast && o == 0;
     args_.usc = ubase && u_pending_ ? args_.cg.isc : nullptr;
-    k::outer_update(args_, o, x, ubase ? u_.p : nullptr, r64_.p, d32_.p, acc, !polled, s_);
-    acct(28.0 + (polled ? 0.0 : 8.0) + (acc ? 8.0 : 0.0), mat_bytes(8.0, 1));
+    k::outer_update(args_, o, x, ubase ? u_.p : nullptr, r64_.p, d32_.p, acc, !polled,
+                    prep ? r32_.p : nullptr, prep ? p32_.p : nullptr, s_);
+    acct(28.0 + (polled && !prep ? 0.0 : 8.0) + (acc ? 8.0 : 0.0) + (prep ? 8.0 : 0.0),
+         mat_bytes(8.0, 1));
     args_.usc = nullptr;
-    k::red_outer(args_, o, s_);
+    if (prep)
+      k::red_outer_prep(args_, o, s_);
+    else
+      k::red_outer(args_, o, s_);
     olast = o + 1;
+    prepared = prep;
     if (polled) {
       if (poll(args_.oring + olast % kRing) == 0) break;
-      k::outer_residual(args_, olast, r64_.p, d32_.p, s_);
-      acct(20.0, mat_bytes(8.0, 1));
+      if (!prep) {
+        k::outer_residual(args_, olast, r64_.p, d32_.p, s_);
+        acct(20.0, mat_bytes(8.0, 1));
+      }
     }
   }
+  last_sweeps_ = olast;
   k::flag_nonconv(args_, args_.oring + olast % kRing, s_);
   if (extrap) {
     for (int i = q - 1; i > 0; --i) dh_[i] = dh_[i - 1];

@@ -205,6 +205,9 @@ class Solver {
   DevBuf<double> xg_;          // iterate of a solve started from u + g (u stays b's source)
   double* heat_x_ = nullptr;   // where the last heat solve left its result (u_ or xg_)
   bool small_ = false;         // whole steps in one workgroup (small batches)
+  // refinement sweeps the last mixed heat solve took: sweep o's update also
+  // writes sweep o + 1's inner start when o + 1 < last_sweeps_
+  int last_sweeps_ = 0;
   static constexpr int kSmallChunk = 128;  // steps per launch of the small path
   DevBuf<double> small_hist_;  // [kSmallChunk][nres_p] energies at the cadence
   bool aw_fresh_ = false;      // xg_ holds A v of the norm pass that produced u (and

@@ -181,9 +181,15 @@ void refine_start(const StepArgs& a, const double* w, const float* g, double* r6
 void red_inner_init(const StepArgs& a, int o, hipStream_t s);
 // x += d (ubase given: x = ubase + dacc + d), r64 -= K d on the columns
 // still refining; dacc (nullable) += d; store_r false: r64 not stored (then
-// outer_residual before another sweep)
+// outer_residual before another sweep).  rn, pn (nullable, both or neither):
+// also the next sweep's inner start r = float(r64), p = D r (r64 stored);
+// reduce with red_outer_prep instead of red_outer
 void outer_update(const StepArgs& a, int o, double* x, const double* ubase, double* r64,
-                  const float* d, float* dacc, bool store_r, hipStream_t s);
+                  const float* d, float* dacc, bool store_r, float* rn, float* pn,
+                  hipStream_t s);
+// outer test of sweep o and, for the columns still refining, the scalars of
+// the inner start that outer_update(rn, pn) wrote
+void red_outer_prep(const StepArgs& a, int o, hipStream_t s);
 // r64 -= K d on the columns still refining after sweep o - 1
 void outer_residual(const StepArgs& a, int o, double* r64, const float* d, hipStream_t s);
 // y = sum_{j < h_c} (-1)^j C(h_c, j+1) e.x[j] per live column c, h_c =
@@ -217,6 +223,8 @@ void scale(const StepArgs& a, const double* v, double* u, hipStream_t s);
 void energy_rq(const StepArgs& a, const double* u, hipStream_t s);
 void energy_seps(const StepArgs& a, const SepsPlan& sp, const int32_t* tri, const double* tarea,
                  const double* u, double* part_s, hipStream_t s);
+// workgroups of the lane-split S_eps kernel resident on one XCD at once
+int seps_resident_groups();
 void red_energy(const StepArgs& a, const SepsPlan& sp, const double* part_s, bool with_lambda,
                 double* lam,
                 double* seps, double* energy, hipStream_t s);

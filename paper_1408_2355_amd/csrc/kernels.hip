@@ -900,18 +900,28 @@ __global__ void k_red_inner_init(StepArgs a, int oslot, int onext) {
 // column (dacc is 0 on columns that are not live), instead of being read.
 // store_r == 0 leaves r64 as it was (the partial still measures the new
 // residual); outer_residual stores it when another sweep follows.
+// Prep (another sweep expected): the next inner solve's start is written
+// too, r = float(r64), p = D r (rn, pn; zeros where the column is not
+// refining), with its partials r.p and ||r||^2, so the sweep after this one
+// needs neither outer_residual nor inner_init (red_outer_prep reduces all
+// three); r64 must be stored then.
+template <bool Prep>
 __global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot,
                                                          double* __restrict__ x,
                                                          const double* __restrict__ ubase,
                                                          double* __restrict__ r64,
                                                          const float* __restrict__ d,
-                                                         float* __restrict__ dacc, int store_r) {
+                                                         float* __restrict__ dacc, int store_r,
+                                                         float* __restrict__ rn,
+                                                         float* __restrict__ pn) {
+  // the next sweep's inner activity is counted afresh (red_outer_prep)
+  if (Prep && blockIdx.x == 0 && threadIdx.x == 0) a.ring[0] = 0;
   if (!ubase && a.oring[oslot] == 0) return;
   const Tile& t = a.tm;
   for (int ct = 0; ct < t.nct; ++ct) {
   const int g = ct * t.tg + threadIdx.x % t.tg;
   const int* mask = a.cg.act_o;
-  double s[1][4] = {};
+  double s[Prep ? 3 : 1][4] = {};
   if (g < t.G) {
     const int c0 = 4 * g;
     int act[4], any = 0, anylive = 0;
@@ -956,10 +966,24 @@ __global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot,
         st4g(x + o, xv);
         if (any && store_r) st4g(r64 + o, rv);
         if (dacc && any) st4g(dacc + o, av);
+        if constexpr (Prep) {
+          if (any) {
+            const float di = a.dinv32[row];
+            V4<float> r32, p32;
+            for (int j = 0; j < 4; ++j) {
+              r32.v[j] = act[j] ? float(rv.v[j]) : 0.0f;
+              p32.v[j] = di * r32.v[j];
+              s[1][j] += double(r32.v[j]) * double(p32.v[j]);
+              s[2][j] += double(r32.v[j]) * double(r32.v[j]);
+            }
+            st4g(rn + o, r32);
+            st4g(pn + o, p32);
+          }
+        }
       });
     }
   }
-  block_store<1>(t, s, a.part, blockIdx.x, ct);
+  block_store<Prep ? 3 : 1>(t, s, a.part, blockIdx.x, ct);
   }
 }
 
@@ -1011,6 +1035,46 @@ __global__ void k_red_outer(StepArgs a, int oslot, int onext) {
       still = 1;
   }
   count_active(still, a.oring + onext);
+}
+
+// Reduction of a refinement update that prepared the next sweep (Prep):
+// the outer test as k_red_outer, and for the columns still refining the next
+// inner solve's scalars as k_red_inner_init would set them from the r and p
+// the update wrote; counts go to oring[onext] and ring[0] (zeroed by the
+// update), and oring[onext2] is zeroed for the next sweep's red_outer.
+__global__ void k_red_outer_prep(StepArgs a, int oslot, int onext, int onext2) {
+  if (a.oring[oslot] == 0) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.stat[1] += 1;
+    a.oring[onext2] = 0;
+  }
+  const int c = red_col();
+  const Tile& t = a.tm;
+  const bool act_o = c < t.rp && a.cg.act_o[c];
+  const int nch = act_o ? t.nchunk : 0;
+  const double rr = red_sum(a.part + part_off(t, 0), nch, t.rp, c);
+  const double rz = red_sum(a.part + part_off(t, 1), nch, t.rp, c);
+  const double r2 = red_sum(a.part + part_off(t, 2), nch, t.rp, c);
+  int still = 0, act = 0;
+  if (red_lead() && c < t.rp) {
+    if (act_o) {
+      a.cg.rr_o[c] = rr;
+      a.cg.sweeps[c] += 1;
+      if (rr <= a.rtol2 * a.cg.bb[c] || !(rr == rr)) {
+        a.cg.act_o[c] = 0;
+      } else {
+        still = 1;
+        a.cg.rz[c] = rz;
+        a.cg.tol2[c] = fmax(a.inner_rtol2 * r2, a.inner_floor2 * a.rtol2 * a.cg.bb[c]);
+        act = r2 > 0.0 ? 1 : 0;
+      }
+    }
+    a.cg.act[c] = act;
+    a.cg.alpha[c] = 0.0;
+    a.cg.beta[c] = 0.0;
+  }
+  count_active(still, a.oring + onext);
+  count_active(act, a.ring + 0);
 }
 
 // -------------------------------------------------------------- node step --
@@ -2346,9 +2410,20 @@ void red_inner_init(const StepArgs& a, int o, hipStream_t s) {
 }
 
 void outer_update(const StepArgs& a, int o, double* x, const double* ubase, double* r64,
-                  const float* d, float* dacc, bool store_r, hipStream_t s) {
-  hipLaunchKernelGGL(k_outer_update, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, o % kRing, x, ubase,
-                     r64, d, dacc, int(store_r));
+                  const float* d, float* dacc, bool store_r, float* rn, float* pn,
+                  hipStream_t s) {
+  if (rn)
+    hipLaunchKernelGGL(k_outer_update<true>, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, o % kRing, x,
+                       ubase, r64, d, dacc, 1, rn, pn);
+  else
+    hipLaunchKernelGGL(k_outer_update<false>, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, o % kRing,
+                       x, ubase, r64, d, dacc, int(store_r), nullptr, nullptr);
+  SP_LAUNCH_CHECK();
+}
+
+void red_outer_prep(const StepArgs& a, int o, hipStream_t s) {
+  hipLaunchKernelGGL(k_red_outer_prep, dim3(colblocks(a.tm)), dim3(kBlock), 0, s, a, o % kRing,
+                     (o + 1) % kRing, (o + 2) % kRing);
   SP_LAUNCH_CHECK();
 }
 
@@ -2446,6 +2521,16 @@ void energy_seps(const StepArgs& a, const SepsPlan& sp, const int32_t* tri, cons
     hipLaunchKernelGGL(k_energy_seps, dim3(8 * sp.nper), dim3(kBlock), 0, s, a, sp, tri, tarea, u,
                        part_s);
   SP_LAUNCH_CHECK();
+}
+
+int seps_resident_groups() {
+  // workgroups of the lane-split element kernel that fit on one XCD at once
+  int dev = 0, per_cu = 0;
+  hipDeviceProp_t prop;
+  SP_HIP(hipGetDevice(&dev));
+  SP_HIP(hipGetDeviceProperties(&prop, dev));
+  SP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_energy_seps_lanes<true>, kBlock, 0));
+  return std::max(1, per_cu * prop.multiProcessorCount / 8);
 }
 
 void red_energy(const StepArgs& a, const SepsPlan& sp, const double* part_s, bool with_lambda,
