@@ -362,6 +362,9 @@ def main():
                     help="relative reduction of each float32 inner solve")
     ap.add_argument("--check-every", type=int, default=8,
                     help="CG iterations between host convergence polls")
+    ap.add_argument("--precond", default="cheb1", choices=("cheb1", "jacobi"),
+                    help="CG preconditioner of the batched run (degree-1 Chebyshev "
+                         "polynomial in D^-1 K, or Jacobi)")
     ap.add_argument("--extrapolate", type=int, default=5, choices=range(9),
                     help="previous heat increments used for each solve's start "
                          "(0: start from u)")
@@ -430,7 +433,8 @@ def main():
     mesh = sp.Mesh(v, f)
     prm = sp.params(tau, precision="mixed", n_steps=1, energy_every=1, cg_rtol=1e-10,
                     inner_rtol=args.inner_rtol, max_outer=8, cg_max_iter=500,
-                    check_every=args.check_every, extrapolate=args.extrapolate)
+                    check_every=args.check_every, extrapolate=args.extrapolate,
+                    precond=args.precond)
     st = sp.State(mesh, prm, ms, np.full(nres, eps), u0)
     del u0
     log(f"[bench] warmup {args.warmup} steps")
@@ -489,7 +493,8 @@ def main():
         "config": {"workload": f"{args.workload}: {mesh_text(kind)} ({n} vertices), "
                                f"m in {sorted(set(int(x) for x in ms))} x "
                                f"{groups[0][1]} restarts ({R} columns), eps {eps}, tau {tau}, "
-                               "float32 CG in float64 refinement, outer rtol 1e-10, "
+                               f"float32 CG ({args.precond} preconditioner) in float64 "
+                               "refinement, outer rtol 1e-10, "
                                f"energy every step; timed steps {args.warmup + 1}.."
                                f"{args.warmup + args.steps} of the run",
                    "columns": R, "n_vert": n},
@@ -508,10 +513,13 @@ def main():
         # plain float64 form: restart 0 of each m group alone over the same
         # steps as the batch (warmup, then the timed window), polled every CG
         # iteration (the reference point of the speed-up) and every 8 (the
-        # library default)
-        for poll in (1, 8):
+        # library default), with the library's default preconditioner (the
+        # degree-1 Chebyshev polynomial) and, polled every iteration, with
+        # plain Jacobi
+        for poll, pc, key in ((1, "cheb1", "plain_fp64"), (8, "cheb1", "plain_fp64_poll8"),
+                              (1, "jacobi", "plain_fp64_jacobi")):
             pprm = sp.params(tau, precision="fp64", n_steps=1, energy_every=1, cg_rtol=1e-10,
-                             cg_max_iter=2000, check_every=poll)
+                             cg_max_iter=2000, check_every=poll, precond=pc)
             cd, tt, errs, lerrs, serrs = 0.0, 0.0, [], [], []
             r0 = 0                      # index of the group's first restart in the batch
             c0 = 0                      # its first column
@@ -533,13 +541,13 @@ def main():
                 r0 += nr
                 c0 += nr * m
             plain = cd / tt
-            key = "plain_fp64" if poll == 1 else "plain_fp64_poll8"
             out[key] = {"value": plain, "unit": "cdof/s",
                         "sample": "restart 0 of each m group, one restart per solve, float64, "
-                                  "host convergence poll every "
+                                  f"{pc} preconditioner, host convergence poll every "
                                   + ("CG iteration" if poll == 1 else "8 CG iterations")}
             out["speedup_vs_" + key] = value / plain
-            log(f"[bench] plain fp64 (poll {poll}) {plain:.3e} cdof/s, speedup {value / plain:.2f}")
+            log(f"[bench] plain fp64 ({pc}, poll {poll}) {plain:.3e} cdof/s, "
+                f"speedup {value / plain:.2f}")
         out["energy_rel_err_vs_fp64"] = max(errs)
         out["lambda_rel_err_vs_fp64"] = max(lerrs)        # every lambda_i of the sampled restarts
         out["sum_lambda_rel_err_vs_fp64"] = max(serrs)

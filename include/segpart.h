@@ -46,9 +46,10 @@ extern "C" {
 #endif
 
 #define SP_VERSION_MAJOR 1
-#define SP_VERSION_MINOR 2  /* 1.1: continuation, partition post-processing, multipliers;
+#define SP_VERSION_MINOR 3  /* 1.1: continuation, partition post-processing, multipliers;
                                1.2: checkpoint/restore, sp_stats.hbm_bytes, per-column
-                               extrapolation history */
+                               extrapolation history, sp_solve_async_noalloc;
+                               1.3: sp_params.precond (polynomial preconditioner) */
 
 enum sp_status {
   SP_OK = 0,
@@ -141,7 +142,21 @@ typedef struct {
                            Each column keeps its own history: a request admitted
                            to a running server batch starts from its own state
                            and the resident columns keep theirs                 */
+  int32_t precond;      /* CG preconditioner (both precisions).  SP_PRECOND_JACOBI:
+                           z = D^-1 r, D the diagonal of M + tau A.
+                           SP_PRECOND_CHEB1: z = (c0 I + c1 D^-1 K) D^-1 r, the
+                           degree-1 Chebyshev polynomial for the spectrum [a, b]
+                           of D^-1 K (K = M + tau A; a, b estimated once per mesh
+                           and tau by a host Lanczos run, b widened by 2%), i.e.
+                           1 - lambda p(lambda) = T_2((a+b-2 lambda)/(b-a)) /
+                           T_2((a+b)/(b-a)).  Symmetric positive definite for
+                           any spectrum below a + b.  One more gather pass per
+                           iteration, about half the iterations.  Ignored by the
+                           small-batch path (float64, one workgroup, Jacobi).
+                           The solution is the same to cg_rtol, which measures
+                           the unpreconditioned residual either way            */
 } sp_params;
+enum { SP_PRECOND_JACOBI = 0, SP_PRECOND_CHEB1 = 1 };
 /* There is no fixed-iteration-count mode: the CG stops on its tolerance.  The
  * CPU reference this library is checked against solves each heat step exactly
  * (sparse LU), so a fixed iteration count would compare a different
@@ -150,7 +165,8 @@ typedef struct {
 
 /* Fill *p with defaults for time step tau: n_steps 100, stop_tol 1e-6,
  * max_steps 10^6, energy_every = round(0.1 / tau), SP_MIXED, cg_rtol 1e-10,
- * cg_max_iter 500, inner_rtol 1e-5, max_outer 8, check_every 8, extrapolate 5. */
+ * cg_max_iter 500, inner_rtol 1e-5, max_outer 8, check_every 8, extrapolate 5,
+ * precond SP_PRECOND_CHEB1. */
 void sp_params_default(sp_params* p, double tau);
 
 typedef struct {

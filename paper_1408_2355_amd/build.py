@@ -23,7 +23,7 @@ LIB = os.path.join(PKG, "libsegpart.so")
 
 ARCH = "gfx950"
 SOURCES = ["kernels.hip", "prolong.hip", "noalloc.hip", "mesh.cpp", "engine.cpp", "autotune.cpp", "server.cpp",
-           "continuation.cpp", "partition.cpp", "checkpoint.cpp", "capi.cpp"]
+           "continuation.cpp", "partition.cpp", "checkpoint.cpp", "precond.cpp", "capi.cpp"]
 
 
 def hipcc():

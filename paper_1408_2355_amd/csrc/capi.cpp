@@ -91,6 +91,7 @@ void sp_params_default(sp_params* p, double tau) {
   p->max_outer = 8;
   p->check_every = 8;
   p->extrapolate = 5;
+  p->precond = SP_PRECOND_CHEB1;
 }
 
 int sp_mesh_create(int64_t n_vert, const double* xyz, int64_t n_tri, const int32_t* tri,

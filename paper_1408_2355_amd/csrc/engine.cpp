@@ -45,6 +45,8 @@ void validate_params(const sp_params& p) {
   SP_REQUIRE(p.check_every >= 0, SP_EINVAL, "params: check_every must be >= 0");
   SP_REQUIRE(p.extrapolate >= 0 && p.extrapolate <= kMaxExtrap, SP_EINVAL,
              "params: extrapolate must be in 0..8");
+  SP_REQUIRE(p.precond == SP_PRECOND_JACOBI || p.precond == SP_PRECOND_CHEB1, SP_EINVAL,
+             "params: precond must be SP_PRECOND_JACOBI or SP_PRECOND_CHEB1");
   if (p.precision == SP_MIXED) {
     SP_REQUIRE(std::isfinite(p.inner_rtol) && p.inner_rtol > 0 && p.inner_rtol < 1, SP_EINVAL,
                "params: inner_rtol must be in (0, 1)");
@@ -115,9 +117,11 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     const char* sm_env = std::getenv("SEGPART_SMALL");
     small_ = nv <= size_t(kSmallMaxValues) && rp_ <= kSmallMaxCols &&
              nres_p_ <= kSmallMaxRestarts && !(sm_env && std::strcmp(sm_env, "0") == 0);
+    const bool poly = prm_.precond == SP_PRECOND_CHEB1 && !small_;
     if (prm_.precision == SP_FP64 || small_) {
       get(p64_, nv);
       get(q64_, nv);
+      if (poly) get(z64_, nv);
     }
     if (small_) get(small_hist_, size_t(kSmallChunk) * nres_p_);
     if (prm_.precision != SP_FP64) {
@@ -125,6 +129,7 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
       get(r32_, nv);
       get(p32_, nv);
       get(q32_, nv);
+      if (poly) get(z32_, nv);
       // direction ring of the inner CG: p32_ is slot 0
       pring_[0] = p32_.p;
       for (int i = 1; i < kPRing; ++i) {
@@ -143,6 +148,7 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     int max_blk = t.nblk;
     for (const Tile& c : tile_candidates()) max_blk = std::max(max_blk, c.nblk);
     get(part_, 3 * size_t(max_blk) * rp_);
+    if (poly) get(part2_, size_t(max_blk) * rp_);
     get(part_s_, size_t(8 * sp_.nper) * nres_p_);
     get(colf_, size_t(CF_N) * rp_ + nres_p_);
     get(coli_, size_t(CI_N) * rp_ + 3 * size_t(nres_p_));
@@ -164,6 +170,8 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     }
     k::fill_f64(u_.p, 0.0, nv, s_);
     k::fill_f64(r64_.p, 0.0, nv, s_);
+    if (z64_.p) k::fill_f64(z64_.p, 0.0, nv, s_);
+    if (z32_.p) k::fill_f32(z32_.p, 0.0f, nv, s_);
     for (int i = 0; i < kMaxExtrap; ++i)
       if (dh_[i]) k::fill_f32(dh_[i], 0.0f, nv, s_);
     for (int i = 0; i < kPRing; ++i)
@@ -227,6 +235,11 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     a.ct.nres = nres;  // 0 for an empty server batch
     a.ct.nres_p = nres_p_;
     a.part = part_.p;
+    if (poly) {
+      a.poly = 1;
+      a.part2 = part2_.p;
+      mesh_->cheb_coefs(prm_.tau, &a.pc0, &a.pc1);
+    }
     a.ring = ring_.p;
     a.oring = ring_.p + kRing;
     a.stat = stat_.p;
@@ -642,13 +655,17 @@ void Solver::download_device(double* d_u) {
 void Solver::heat_fp64() {
   flush_scale();
   k::fill_i32(ring_.p, 0, ring_.n, s_);
-  k::init_fp64(args_, u_.p, r64_.p, p64_.p, s_);
-  acct(24.0, mat_bytes(8.0, 2));
+  k::init_fp64(args_, u_.p, r64_.p, args_.poly ? nullptr : p64_.p, s_);
+  acct(args_.poly ? 16.0 : 24.0, mat_bytes(8.0, 2));
   k::red_init_fp64(args_, s_);
+  if (args_.poly) {
+    k::precond_init<double>(args_, r64_.p, p64_.p, km_->K64.p, km_->dinv64.p, s_);
+    acct(16.0, mat_bytes(8.0, 1) + 8.0 * double(mesh_->n));
+  }
   int last = 0;
   for (int it = 0; it < prm_.cg_max_iter; ++it) {
-    k::cg_iter<double>(args_, it, u_.p, r64_.p, p64_.p, q64_.p, km_->K64.p, km_->dinv64.p, s_,
-                       prof_events());
+    k::cg_iter<double>(args_, it, u_.p, r64_.p, p64_.p, q64_.p, z64_.p, km_->K64.p,
+                       km_->dinv64.p, s_, prof_events());
     last = it + 1;
     if (prm_.check_every > 0 && last % prm_.check_every == 0 && last < prm_.cg_max_iter)
       if (poll(ring_.p + last % kRing) == 0) break;
@@ -686,8 +703,9 @@ void Solver::heat_mixed() {
     }
     if (fast) {
       // A u and ||M u||^2 from the last step's norm pass: no float64 gather
-      k::refine_start(args_, xg_.p, acc, r64_.p, r32_.p, p32_.p, s_);
-      acct(28.0, mat_bytes(8.0, 1));
+      k::refine_start(args_, xg_.p, acc, r64_.p, r32_.p, args_.poly ? nullptr : p32_.p, s_);
+      acct(args_.poly ? 24.0 : 28.0, mat_bytes(8.0, 1));
+      precond_start();
     } else {
       k::init_outer(args_, u_.p, acc, xg_.p, r64_.p, s_);
       acct(32.0, mat_bytes(8.0, 3));
@@ -707,9 +725,10 @@ void Solver::heat_mixed() {
   bool prepared = false;  // the last update wrote this sweep's inner start
   for (int o = 0; o < prm_.max_outer; ++o) {
     if (!(fast && o == 0) && !prepared) {
-      k::inner_init(args_, o, r64_.p, d32_.p, r32_.p, p32_.p, s_);
-      acct(16.0);
+      k::inner_init(args_, o, r64_.p, d32_.p, r32_.p, args_.poly ? nullptr : p32_.p, s_);
+      acct(args_.poly ? 12.0 : 16.0);
       k::red_inner_init(args_, o, s_);
+      precond_start();
     }
     // inner CG in direction-ring form: d is formed from the stored
     // directions when the ring fills and after the last iteration
@@ -721,7 +740,7 @@ void Solver::heat_mixed() {
         flushed = 1;
         it += kPRing;
       } else {
-        k::cg_iter_ring(args_, it, r32_.p, pring_, q32_.p, ah_.p, d32_.p, &flushed, s_,
+        k::cg_iter_ring(args_, it, r32_.p, pring_, q32_.p, z32_.p, ah_.p, d32_.p, &flushed, s_,
                         prof_events());
         ++it;
       }
@@ -742,14 +761,17 @@ void Solver::heat_mixed() {
     const bool ubase = fast && o == 0;
     args_.usc = ubase && u_pending_ ? args_.cg.isc : nullptr;
     k::outer_update(args_, o, x, ubase ? u_.p : nullptr, r64_.p, d32_.p, acc, !polled,
-                    prep ? r32_.p : nullptr, prep ? p32_.p : nullptr, s_);
-    acct(28.0 + (polled && !prep ? 0.0 : 8.0) + (acc ? 8.0 : 0.0) + (prep ? 8.0 : 0.0),
+                    prep ? r32_.p : nullptr, prep && !args_.poly ? p32_.p : nullptr, s_);
+    acct(28.0 + (polled && !prep ? 0.0 : 8.0) + (acc ? 8.0 : 0.0) +
+             (prep ? (args_.poly ? 4.0 : 8.0) : 0.0),
          mat_bytes(8.0, 1));
     args_.usc = nullptr;
-    if (prep)
+    if (prep) {
       k::red_outer_prep(args_, o, s_);
-    else
+      precond_start();
+    } else {
       k::red_outer(args_, o, s_);
+    }
     olast = o + 1;
     prepared = prep;
     if (polled) {
@@ -772,6 +794,14 @@ void Solver::heat_mixed() {
   heat_x_ = x;
 }
 
+// First direction of a float32 inner solve under the polynomial
+// preconditioner: p = z = P r on the columns starting it, with their r.z.
+void Solver::precond_start() {
+  if (!args_.poly) return;
+  k::precond_init<float>(args_, r32_.p, p32_.p, km_->K32.p, km_->dinv32.p, s_);
+  acct(8.0, mat_bytes(4.0, 1) + 4.0 * double(mesh_->n));
+}
+
 void Solver::cg_block(int flushed) {
   const int v = flushed ? 1 : 0;
   if (cg_graph_[v] && std::memcmp(&cg_graph_args_[v], &args_, sizeof(StepArgs)) != 0) {
@@ -787,7 +817,7 @@ void Solver::cg_block(int flushed) {
     try {
       int f = flushed;
       for (int i = 0; i < kPRing; ++i)
-        k::cg_iter_ring(args_, i, r32_.p, pring_, q32_.p, ah_.p, d32_.p, &f, s_, nullptr);
+        k::cg_iter_ring(args_, i, r32_.p, pring_, q32_.p, z32_.p, ah_.p, d32_.p, &f, s_, nullptr);
     } catch (...) {
       (void)hipStreamEndCapture(s_, &g);
       if (g) (void)hipGraphDestroy(g);
@@ -1049,10 +1079,13 @@ sp_stats Solver::stats() {
   out.converged = st[2] == 0;
   // CG iterations: the columns still iterating (device count) x the three
   // kernels' bytes per element, and the matrix once per iteration with work
+  // (the polynomial preconditioner's pass: r read, z written, the matrix
+  // and the diagonal once more)
   const bool f64 = prm_.precision == SP_FP64 || small_;
-  const double n = double(mesh_->n);
-  out.hbm_bytes = fixed_bytes_ + double(st[3]) * n * (f64 ? 88.0 : 32.0) +
-                  double(st[0]) * mat_bytes(f64 ? 8.0 : 4.0, 1);
+  const double n = double(mesh_->n), vb = f64 ? 8.0 : 4.0;
+  const bool poly = args_.poly != 0;
+  out.hbm_bytes = fixed_bytes_ + double(st[3]) * n * ((f64 ? 88.0 : 32.0) + (poly ? 2 * vb : 0.0)) +
+                  double(st[0]) * (mat_bytes(vb, 1) * (poly ? 2.0 : 1.0) + (poly ? n * vb : 0.0));
   return out;
 }
 

@@ -189,6 +189,8 @@ class Solver {
 
   DevBuf<double> u_, r64_, p64_, q64_;
   DevBuf<float> d32_, r32_, p32_, q32_;
+  DevBuf<double> z64_;  // polynomial preconditioner's output (float64 CG)
+  DevBuf<float> z32_;   // (float32 inner CG)
   DevBuf<float> pbuf_[kPRing];        // direction ring slots 1.. (slot 0 is p32_)
   float* pring_[kPRing] = {};
   DevBuf<double> ah_;                 // [kPRing][rp] alpha of each ring slot
@@ -226,6 +228,7 @@ class Solver {
   // SEGPART_GRAPH=0 turns this off; never used while profiling, on the
   // legacy default stream, or with another polling period.
   void cg_block(int flushed);
+  void precond_start();
   bool graph_on_ = true;
   hipGraphExec_t cg_graph_[2] = {nullptr, nullptr};
   StepArgs cg_graph_args_[2];
@@ -235,6 +238,7 @@ class Solver {
   bool lam_fresh_ = false;  // lam holds the Rayleigh quotients of the current state
   bool all_live_ = true;    // every real column is live
   DevBuf<double> part_, part_s_;
+  DevBuf<double> part2_;  // preconditioner pass partials [nblk][rp]
   DevBuf<double> colf_;  // 8 x rp column doubles + nres_p restart doubles
   DevBuf<int> coli_;     // 7 x rp column ints + 3 x nres_p restart ints
   DevBuf<int> ring_;     // 2 x kRing

@@ -1,6 +1,7 @@
 // Internal types of libsegpart (not part of the C ABI).
 #pragma once
 
+#include <array>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -158,6 +159,11 @@ struct Mesh {
   std::mutex mu;
   std::vector<std::unique_ptr<TauMats>> kcache;
   TauMats* tau_mats(double tau);
+  // coefficients of the CG's degree-1 Chebyshev preconditioner for
+  // K = M + tau A (precond.cpp); host work, cached per tau
+  void cheb_coefs(double tau, double* c0, double* c1);
+  std::mutex pmu;
+  std::vector<std::array<double, 3>> pcache;  // (tau, c0, c1)
 };
 
 Mesh* mesh_create(int64_t n, const double* xyz, int64_t nt, const int32_t* tri);

@@ -75,6 +75,13 @@ struct StepArgs {
   CgCols cg;
   int* hlen = nullptr;  // per column: heat increments kept for the extrapolated
                         // start (0 .. extrapolate)
+  // Polynomial preconditioner of the CG (poly != 0): z = (pc0 I + pc1 D^-1 K)
+  // D^-1 r, the Chebyshev polynomial of degree 1 for the spectrum of D^-1 K;
+  // part2 [nblk][rp] holds its pass's partial sums r.z (tiling tm).  poly == 0:
+  // Jacobi, z = D^-1 r formed inside the update kernels.
+  int poly = 0;
+  double pc0 = 0.0, pc1 = 0.0;
+  double* part2 = nullptr;
   double* part;        // [3][nchunk][rp] partial sums
   int* ring;           // [kRing] inner active counts
   int* oring;          // [kRing] outer active counts
@@ -142,20 +149,27 @@ namespace k {
 std::vector<int4> seps_tiles(const std::vector<int>& res_lo, const std::vector<int>& res_len,
                              int nres);
 void flag_nonconv(const StepArgs& a, const int* counter, hipStream_t s);
-// float64 CG (plain form): x is the state u itself.
+// float64 CG (plain form): x is the state u itself.  p nullable (the
+// preconditioner pass writes the first direction: precond_init).
 void init_fp64(const StepArgs& a, const double* u, double* r, double* p, hipStream_t s);
+// Polynomial preconditioner at the start of a solve (a.poly): p = z = P r on
+// the columns starting this solve (activity count ring[0]), and their r.z
+// into cg.rz.  z is the pass's output buffer (here: the first direction).
+template <typename T>
+void precond_init(const StepArgs& a, const T* r, T* p, const T* K, const T* dinv, hipStream_t s);
 void red_init_fp64(const StepArgs& a, hipStream_t s);
 // one CG iteration on type T vectors (float64 plain or float32 inner); ev,
 // when given, holds 6 events recorded around the matrix product, the x/r
-// update and the p update (before/after each)
+// update and the p update (before/after each).  z: the preconditioner's
+// output (used when a.poly).
 template <typename T>
-void cg_iter(const StepArgs& a, int it, T* x, T* r, T* p, T* q, const T* K, const T* dinv,
+void cg_iter(const StepArgs& a, int it, T* x, T* r, T* p, T* q, T* z, const T* K, const T* dinv,
              hipStream_t s, const hipEvent_t* ev);
 // one iteration of the float32 inner CG in direction-ring form: directions
 // in pring[kPRing] (iteration it uses slot it % kPRing and writes the next),
 // alpha rows in ah[kPRing][rp]; when the ring fills, d (+)= sum alpha p and
 // *flushed is set (later folds accumulate)
-void cg_iter_ring(const StepArgs& a, int it, float* r, float* const* pring, float* q,
+void cg_iter_ring(const StepArgs& a, int it, float* r, float* const* pring, float* q, float* z,
                   double* ah, float* d, int* flushed, hipStream_t s, const hipEvent_t* ev);
 // d (+)= sum over count ring slots from first (cyclic) of alpha_slot p_slot
 void materialize(const StepArgs& a, float* const* pring, const double* ah, int first, int count,
@@ -170,6 +184,7 @@ void matvec(const StepArgs& a, const T* K, const T* p, T* q, hipStream_t s);
 void init_outer(const StepArgs& a, const double* u, const float* g, double* x0, double* r64,
                 hipStream_t s);
 void red_outer_init(const StepArgs& a, hipStream_t s);
+// (p nullable: the polynomial preconditioner's pass writes the first direction)
 void inner_init(const StepArgs& a, int o, const double* r64, float* d, float* r, float* p,
                 hipStream_t s);
 // refinement start and first inner start from the norm pass's A v (w) and
@@ -177,7 +192,7 @@ void inner_init(const StepArgs& a, int o, const double* r64, float* d, float* r,
 // red_inner_init of sweep 0 (the iterate u + g is formed by the first
 // outer_update in ubase mode)
 void refine_start(const StepArgs& a, const double* w, const float* g, double* r64, float* r,
-                  float* p, hipStream_t s);
+                  float* p, hipStream_t s);  // p nullable as in inner_init
 void red_inner_init(const StepArgs& a, int o, hipStream_t s);
 // x += d (ubase given: x = ubase + dacc + d), r64 -= K d on the columns
 // still refining; dacc (nullable) += d; store_r false: r64 not stored (then

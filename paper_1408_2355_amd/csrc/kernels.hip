@@ -226,6 +226,25 @@ __device__ __forceinline__ void for_neighbors(const StepArgs& a, int row, int c0
   }
 }
 
+// for_neighbors with the neighbour's row index: f(k, x_k, o, idx_k).
+template <typename T, typename F>
+__device__ __forceinline__ void for_neighbors_i(const StepArgs& a, int row, int c0,
+                                                const T* __restrict__ x, F&& f) {
+  const int n = a.t.n, rp = a.t.rp;
+  for (int kb = 0; kb < a.W; kb += kSlots) {
+    int idx[kSlots];
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) idx[k] = ldm(a.cols + size_t(kb + k) * n + row);
+    V4<T> xv[kSlots];
+#pragma unroll
+    for (int k = 0; k < kSlots - 1; ++k) xv[k] = ld4(x + size_t(idx[k]) * rp + c0);
+    constexpr int kl = kSlots - 1;
+    xv[kl] = idx[kl] != row ? ld4(x + size_t(idx[kl]) * rp + c0) : V4<T>{};
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) f(kb + k, xv[k], size_t(kb + k) * n + row, idx[k]);
+  }
+}
+
 // --------------------------------------------------------------- assembly --
 // One thread per row.  P1 element matrices on a flat triangle with corners
 // x0, x1, x2 and edges e_a opposite corner a (e0 = x2 - x1, e1 = x0 - x2,
@@ -341,7 +360,7 @@ __global__ __launch_bounds__(kBlock) void k_init_fp64(StepArgs a, const double* 
         s[2][j] += rv.v[j] * rv.v[j];
       }
       st4g(r + size_t(row) * t.rp + c0, rv);
-      st4g(p + size_t(row) * t.rp + c0, pv);
+      if (p) st4g(p + size_t(row) * t.rp + c0, pv);
     });
   }
   block_store<3>(t, s, a.part, blockIdx.x, ct);
@@ -423,8 +442,9 @@ __global__ void k_red_alpha(StepArgs a, int slot, int next, double* __restrict__
   if (ah) ah[c] = al;
 }
 
-// x += alpha p, r -= alpha q, z = D r; partials r.z and r.r.
-template <typename T>
+// x += alpha p, r -= alpha q, z = D r; partials r.z and r.r (Poly: r.r only,
+// the preconditioner's pass forms z and r.z).
+template <typename T, bool Poly>
 __global__ __launch_bounds__(kBlock) void k_cg_update(StepArgs a, int slot, T* __restrict__ x,
                                                       T* __restrict__ r, const T* __restrict__ p,
                                                       const T* __restrict__ q,
@@ -433,7 +453,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(StepArgs a, int slot, T* _
   const Tile& t = a.t;
   for (int ct = 0; ct < t.nct; ++ct) {
   const int g = ct * t.tg + threadIdx.x % t.tg;
-  double s[2][4] = {};
+  double s[Poly ? 1 : 2][4] = {};
   if (g < t.G) {
     const int c0 = 4 * g;
     int act[4];
@@ -455,8 +475,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(StepArgs a, int slot, T* _
             xv.v[j] = fma(al[j], pv.v[j], xv.v[j]);
             rv.v[j] = fma(-al[j], qv.v[j], rv.v[j]);
             const double rd = double(rv.v[j]);
-            s[0][j] += rd * double(di * rv.v[j]);
-            s[1][j] += rd * rd;
+            if constexpr (Poly) {
+              s[0][j] += rd * rd;
+            } else {
+              s[0][j] += rd * double(di * rv.v[j]);
+              s[1][j] += rd * rd;
+            }
           }
         }
         st4s(x + o, xv);
@@ -464,18 +488,23 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(StepArgs a, int slot, T* _
       });
     }
   }
-  block_store<2>(t, s, a.part, blockIdx.x, ct);
+  block_store<Poly ? 1 : 2>(t, s, a.part, blockIdx.x, ct);
   }
 }
 
+// beta = r.z(new) / r.z(old) per column still iterating, which stops once
+// ||r||^2 <= tol2.  Poly: r.z from the preconditioner pass (part2, tiling tm),
+// r.r from the update (part slot 0); otherwise both from the update.
+template <bool Poly>
 __global__ void k_red_beta(StepArgs a, int slot, int next) {
   if (a.ring[slot] == 0) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) a.stat[0] += 1;  // an iteration that did work
   const int c = red_col();
   const Tile& t = a.t;
   const bool act = c < t.rp && a.cg.act[c];
-  const double rzn = red_sum(a.part + part_off(t, 0), act ? t.nchunk : 0, t.rp, c);
-  const double rr = red_sum(a.part + part_off(t, 1), act ? t.nchunk : 0, t.rp, c);
+  const double rzn = Poly ? red_sum(a.part2, act ? a.tm.nchunk : 0, t.rp, c)
+                          : red_sum(a.part + part_off(t, 0), act ? t.nchunk : 0, t.rp, c);
+  const double rr = red_sum(a.part + part_off(t, Poly ? 0 : 1), act ? t.nchunk : 0, t.rp, c);
   int still = 0;
   if (red_lead() && act) {
     a.cg.iters[c] += 1;
@@ -498,7 +527,8 @@ __global__ void k_red_beta(StepArgs a, int slot, int next) {
 // exactly the rounding of the running update.  Per iteration this moves 32
 // bytes per element instead of 44.
 //
-// r -= alpha q, z = D r; partials r.z and r.r.
+// r -= alpha q, z = D r; partials r.z and r.r (Poly: r.r only).
+template <bool Poly>
 __global__ __launch_bounds__(kBlock) void k_cg_update_r(StepArgs a, int slot,
                                                         float* __restrict__ r,
                                                         const float* __restrict__ q,
@@ -507,7 +537,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_r(StepArgs a, int slot,
   const Tile& t = a.t;
   for (int ct = 0; ct < t.nct; ++ct) {
   const int g = ct * t.tg + threadIdx.x % t.tg;
-  double s[2][4] = {};
+  double s[Poly ? 1 : 2][4] = {};
   if (g < t.G) {
     const int c0 = 4 * g;
     int act[4];
@@ -523,29 +553,35 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_r(StepArgs a, int slot,
         const size_t o = size_t(row) * t.rp + c0;
         V4<float> rv = ld4s(r + o);
         const V4<float> qv = ld4s(q + o);
-        const float di = dinv[row];
+        const float di = Poly ? 0.0f : dinv[row];
         for (int j = 0; j < 4; ++j) {
           if (act[j]) {
             rv.v[j] = fmaf(-al[j], qv.v[j], rv.v[j]);
             const double rd = double(rv.v[j]);
-            s[0][j] += rd * double(di * rv.v[j]);
-            s[1][j] += rd * rd;
+            if constexpr (Poly) {
+              s[0][j] += rd * rd;
+            } else {
+              s[0][j] += rd * double(di * rv.v[j]);
+              s[1][j] += rd * rd;
+            }
           }
         }
         st4s(r + o, rv);
       });
     }
   }
-  block_store<2>(t, s, a.part, blockIdx.x, ct);
+  block_store<Poly ? 1 : 2>(t, s, a.part, blockIdx.x, ct);
   }
 }
 
-// p_next = D r + beta p on the columns still iterating, 0 on the others of a
-// group that has one (p_next is a different ring slot from p).
+// p_next = z + beta p on the columns still iterating, 0 on the others of a
+// group that has one (p_next is a different ring slot from p); z = D r
+// (src = r), or the preconditioner's output (Poly: src = z).
+template <bool Poly>
 __global__ __launch_bounds__(kBlock) void k_cg_dir_ring(StepArgs a, int next,
                                                         float* __restrict__ pn,
                                                         const float* __restrict__ p,
-                                                        const float* __restrict__ r,
+                                                        const float* __restrict__ src,
                                                         const float* __restrict__ dinv) {
   if (a.ring[next] == 0) return;
   const Tile& t = a.t;
@@ -564,10 +600,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir_ring(StepArgs a, int next,
   if (!any) continue;
   for_rows(t, [&](int row) {
     const size_t o = size_t(row) * t.rp + c0;
-    const V4<float> pv = ld4s(p + o), rv = ld4s(r + o);
-    const float di = dinv[row];
+    const V4<float> pv = ld4s(p + o), sv = ld4s(src + o);
+    const float di = Poly ? 1.0f : dinv[row];
     V4<float> nv;
-    for (int j = 0; j < 4; ++j) nv.v[j] = act[j] ? fmaf(be[j], pv.v[j], di * rv.v[j]) : 0.0f;
+    for (int j = 0; j < 4; ++j) nv.v[j] = act[j] ? fmaf(be[j], pv.v[j], di * sv.v[j]) : 0.0f;
     st4s(pn + o, nv);
   });
   }
@@ -654,10 +690,10 @@ __global__ void k_hist_advance(StepArgs a, int q) {
   a.hlen[c] = a.ct.live[c] ? min(a.hlen[c] + 1, q) : 0;
 }
 
-// p = D r + beta p
-template <typename T>
+// p = z + beta p, z = D r (src = r) or the preconditioner's output (Poly).
+template <typename T, bool Poly>
 __global__ __launch_bounds__(kBlock) void k_cg_update_p(StepArgs a, int next, T* __restrict__ p,
-                                                        const T* __restrict__ r,
+                                                        const T* __restrict__ src,
                                                         const T* __restrict__ dinv) {
   if (a.ring[next] == 0) return;
   const Tile& t = a.t;
@@ -677,13 +713,73 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_p(StepArgs a, int next, T*
   for_rows(t, [&](int row) {
     const size_t o = size_t(row) * t.rp + c0;
     V4<T> pv = ld4s(p + o);
-    const V4<T> rv = ld4s(r + o);
-    const T di = dinv[row];
+    const V4<T> sv = ld4s(src + o);
+    const T di = Poly ? T(1) : dinv[row];
     for (int j = 0; j < 4; ++j)
-      if (act[j]) pv.v[j] = fma(be[j], pv.v[j], di * rv.v[j]);
+      if (act[j]) pv.v[j] = fma(be[j], pv.v[j], di * sv.v[j]);
     st4s(p + o, pv);
   });
   }
+}
+
+// Polynomial preconditioner pass: z = D^-1 (pc0 r + pc1 K D^-1 r), the
+// degree-1 Chebyshev polynomial in D^-1 K applied to the Jacobi step, on the
+// columns still iterating (0 on the others of a group that has one), with the
+// partials r.z (part2, tiling tm).  A gather like the matrix product: each
+// neighbour's r comes with its own D^-1 (scalar load by index).  Restricted
+// solves keep z on the column's region.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_precond(StepArgs a, int slot,
+                                                       const T* __restrict__ r,
+                                                       T* __restrict__ z,
+                                                       const T* __restrict__ K,
+                                                       const T* __restrict__ dinv) {
+  if (a.ring[slot] == 0) return;
+  const Tile& t = a.tm;
+  const T c0 = T(a.pc0), c1 = T(a.pc1);
+  for (int ct = 0; ct < t.nct; ++ct) {
+  const int g = ct * t.tg + threadIdx.x % t.tg;
+  double s[1][4] = {};
+  if (g < t.G) {
+    const int cb = 4 * g;
+    int act[4], any = 0;
+    for (int j = 0; j < 4; ++j) {
+      act[j] = a.cg.act[cb + j];
+      any |= act[j];
+    }
+    if (any) {
+      for_rows(t, [&](int row) {
+        V4<T> acc = {}, ro = {};
+        for_neighbors_i(a, row, cb, r, [&](int k, const V4<T>& x, size_t o, int idx) {
+          const T v = ldm(K + o) * ldm(dinv + idx);
+          if (k == 0) ro = x;
+          for (int j = 0; j < 4; ++j) acc.v[j] = fma(v, x.v[j], acc.v[j]);
+        });
+        const T di = ldm(dinv + row);
+        V4<T> zv;
+        for (int j = 0; j < 4; ++j) zv.v[j] = act[j] ? di * fma(c1, acc.v[j], c0 * ro.v[j]) : T(0);
+        if constexpr (sizeof(T) == 8) {
+          if (a.mask)  // restricted solve: z stays on the region
+            for (int j = 0; j < 4; ++j)
+              if (!a.mask[size_t(row) * t.rp + cb + j]) zv.v[j] = 0.0;
+        }
+        st4g(z + size_t(row) * t.rp + cb, zv);
+        for (int j = 0; j < 4; ++j) s[0][j] += double(ro.v[j]) * double(zv.v[j]);
+      });
+    }
+  }
+  block_store<1>(t, s, a.part2, blockIdx.x, ct);
+  }
+}
+
+// r.z of the preconditioner's first pass of a solve: cg.rz of every column
+// starting it (cg.act).
+__global__ void k_red_precond_init(StepArgs a) {
+  const int c = red_col();
+  const Tile& t = a.tm;
+  const bool act = c < t.rp && a.cg.act[c];
+  const double rz = red_sum(a.part2, act ? t.nchunk : 0, t.rp, c);
+  if (red_lead() && act) a.cg.rz[c] = rz;
 }
 
 // ------------------------------------------------- mixed-precision refinement --
@@ -800,7 +896,7 @@ __global__ __launch_bounds__(kBlock) void k_refine_start(StepArgs a, const doubl
       }
       st4g(r64 + o, rv);
       st4g(r + o, r32);
-      st4g(p + o, pv);
+      if (p) st4g(p + o, pv);
     });
   }
   block_store<3>(t, s, a.part, blockIdx.x, ct);
@@ -863,7 +959,7 @@ __global__ __launch_bounds__(kBlock) void k_inner_init(StepArgs a, int oslot,
         s[1][j] += double(rv.v[j]) * double(rv.v[j]);
       }
       st4s(r + o, rv);
-      st4s(p + o, pv);
+      if (p) st4s(p + o, pv);
     });
   }
   block_store<2>(t, s, a.part, blockIdx.x, ct);
@@ -977,7 +1073,7 @@ __global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot,
               s[2][j] += double(r32.v[j]) * double(r32.v[j]);
             }
             st4g(rn + o, r32);
-            st4g(pn + o, p32);
+            if (pn) st4g(pn + o, p32);
           }
         }
       });
@@ -2305,22 +2401,45 @@ void red_init_fp64(const StepArgs& a, hipStream_t s) {
 }
 
 template <typename T>
-void cg_iter(const StepArgs& a, int it, T* x, T* r, T* p, T* q, const T* K, const T* dinv,
+void precond_init(const StepArgs& a, const T* r, T* p, const T* K, const T* dinv, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_precond<T>, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, 0, r, p, K, dinv);
+  hipLaunchKernelGGL(k_red_precond_init, dim3(colblocks(a.tm)), dim3(kBlock), 0, s, a);
+  SP_LAUNCH_CHECK();
+}
+template void precond_init<double>(const StepArgs&, const double*, double*, const double*,
+                                   const double*, hipStream_t);
+template void precond_init<float>(const StepArgs&, const float*, float*, const float*,
+                                  const float*, hipStream_t);
+
+template <typename T>
+void cg_iter(const StepArgs& a, int it, T* x, T* r, T* p, T* q, T* z, const T* K, const T* dinv,
              hipStream_t s, const hipEvent_t* ev) {
   const int slot = it % kRing, next = (it + 1) % kRing;
+  const dim3 nb(a.t.nblk), rb(colblocks(a.t)), bl(kBlock);
   if (ev) SP_HIP(hipEventRecord(ev[0], s));
-  hipLaunchKernelGGL(k_cg_spmm<T>, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, slot, K, (const T*)p, q);
+  hipLaunchKernelGGL(k_cg_spmm<T>, dim3(a.tm.nblk), bl, 0, s, a, slot, K, (const T*)p, q);
   if (ev) SP_HIP(hipEventRecord(ev[1], s));
-  hipLaunchKernelGGL(k_red_alpha, dim3(colblocks(a.t)), dim3(kBlock), 0, s, a, slot, next,
-                     (double*)nullptr);
+  hipLaunchKernelGGL(k_red_alpha, rb, bl, 0, s, a, slot, next, (double*)nullptr);
   if (ev) SP_HIP(hipEventRecord(ev[2], s));
-  hipLaunchKernelGGL(k_cg_update<T>, dim3(a.t.nblk), dim3(kBlock), 0, s, a, slot, x, r, (const T*)p,
-                     (const T*)q, dinv);
+  if (a.poly) {
+    hipLaunchKernelGGL((k_cg_update<T, true>), nb, bl, 0, s, a, slot, x, r, (const T*)p,
+                       (const T*)q, dinv);
+    hipLaunchKernelGGL(k_cg_precond<T>, dim3(a.tm.nblk), bl, 0, s, a, slot, (const T*)r, z, K,
+                       dinv);
+  } else {
+    hipLaunchKernelGGL((k_cg_update<T, false>), nb, bl, 0, s, a, slot, x, r, (const T*)p,
+                       (const T*)q, dinv);
+  }
   if (ev) SP_HIP(hipEventRecord(ev[3], s));
-  hipLaunchKernelGGL(k_red_beta, dim3(colblocks(a.t)), dim3(kBlock), 0, s, a, slot, next);
+  if (a.poly)
+    hipLaunchKernelGGL(k_red_beta<true>, rb, bl, 0, s, a, slot, next);
+  else
+    hipLaunchKernelGGL(k_red_beta<false>, rb, bl, 0, s, a, slot, next);
   if (ev) SP_HIP(hipEventRecord(ev[4], s));
-  hipLaunchKernelGGL(k_cg_update_p<T>, dim3(a.t.nblk), dim3(kBlock), 0, s, a, next, p, (const T*)r,
-                     dinv);
+  if (a.poly)
+    hipLaunchKernelGGL((k_cg_update_p<T, true>), nb, bl, 0, s, a, next, p, (const T*)z, dinv);
+  else
+    hipLaunchKernelGGL((k_cg_update_p<T, false>), nb, bl, 0, s, a, next, p, (const T*)r, dinv);
   if (ev) SP_HIP(hipEventRecord(ev[5], s));
   SP_LAUNCH_CHECK();
 }
@@ -2333,29 +2452,41 @@ void matvec(const StepArgs& a, const T* K, const T* p, T* q, hipStream_t s) {
 template void matvec<double>(const StepArgs&, const double*, const double*, double*, hipStream_t);
 template void matvec<float>(const StepArgs&, const float*, const float*, float*, hipStream_t);
 
-void cg_iter_ring(const StepArgs& a, int it, float* r, float* const* pring, float* q,
+void cg_iter_ring(const StepArgs& a, int it, float* r, float* const* pring, float* q, float* z,
                   double* ah, float* d, int* flushed, hipStream_t s, const hipEvent_t* ev) {
   const int slot = it % kRing, next = (it + 1) % kRing;
   const int ps = it % kPRing, pn = (it + 1) % kPRing;
+  const dim3 nb(a.t.nblk), rb(colblocks(a.t)), bl(kBlock);
   if (ev) SP_HIP(hipEventRecord(ev[0], s));
-  hipLaunchKernelGGL(k_cg_spmm<float>, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, slot, a.K32,
+  hipLaunchKernelGGL(k_cg_spmm<float>, dim3(a.tm.nblk), bl, 0, s, a, slot, a.K32,
                      (const float*)pring[ps], q);
   if (ev) SP_HIP(hipEventRecord(ev[1], s));
-  hipLaunchKernelGGL(k_red_alpha, dim3(colblocks(a.t)), dim3(kBlock), 0, s, a, slot, next,
-                     ah + size_t(ps) * a.t.rp);
+  hipLaunchKernelGGL(k_red_alpha, rb, bl, 0, s, a, slot, next, ah + size_t(ps) * a.t.rp);
   if (ev) SP_HIP(hipEventRecord(ev[2], s));
-  hipLaunchKernelGGL(k_cg_update_r, dim3(a.t.nblk), dim3(kBlock), 0, s, a, slot, r,
-                     (const float*)q, a.dinv32);
+  if (a.poly) {
+    hipLaunchKernelGGL(k_cg_update_r<true>, nb, bl, 0, s, a, slot, r, (const float*)q, a.dinv32);
+    hipLaunchKernelGGL(k_cg_precond<float>, dim3(a.tm.nblk), bl, 0, s, a, slot, (const float*)r,
+                       z, (const float*)a.K32, (const float*)a.dinv32);
+  } else {
+    hipLaunchKernelGGL(k_cg_update_r<false>, nb, bl, 0, s, a, slot, r, (const float*)q, a.dinv32);
+  }
   if (ev) SP_HIP(hipEventRecord(ev[3], s));
-  hipLaunchKernelGGL(k_red_beta, dim3(colblocks(a.t)), dim3(kBlock), 0, s, a, slot, next);
+  if (a.poly)
+    hipLaunchKernelGGL(k_red_beta<true>, rb, bl, 0, s, a, slot, next);
+  else
+    hipLaunchKernelGGL(k_red_beta<false>, rb, bl, 0, s, a, slot, next);
   if (pn == 0) {
     // the ring is full: fold its directions into d before slot 0 is reused
     materialize(a, pring, ah, 0, kPRing, *flushed, d, s);
     *flushed = 1;
   }
   if (ev) SP_HIP(hipEventRecord(ev[4], s));
-  hipLaunchKernelGGL(k_cg_dir_ring, dim3(a.t.nblk), dim3(kBlock), 0, s, a, next, pring[pn],
-                     (const float*)pring[ps], (const float*)r, a.dinv32);
+  if (a.poly)
+    hipLaunchKernelGGL(k_cg_dir_ring<true>, nb, bl, 0, s, a, next, pring[pn],
+                       (const float*)pring[ps], (const float*)z, a.dinv32);
+  else
+    hipLaunchKernelGGL(k_cg_dir_ring<false>, nb, bl, 0, s, a, next, pring[pn],
+                       (const float*)pring[ps], (const float*)r, a.dinv32);
   if (ev) SP_HIP(hipEventRecord(ev[5], s));
   SP_LAUNCH_CHECK();
 }
@@ -2374,10 +2505,10 @@ void materialize(const StepArgs& a, float* const* pring, const double* ah, int f
   SP_LAUNCH_CHECK();
 }
 
-template void cg_iter<double>(const StepArgs&, int, double*, double*, double*, double*,
+template void cg_iter<double>(const StepArgs&, int, double*, double*, double*, double*, double*,
                               const double*, const double*, hipStream_t, const hipEvent_t*);
-template void cg_iter<float>(const StepArgs&, int, float*, float*, float*, float*, const float*,
-                             const float*, hipStream_t, const hipEvent_t*);
+template void cg_iter<float>(const StepArgs&, int, float*, float*, float*, float*, float*,
+                             const float*, const float*, hipStream_t, const hipEvent_t*);
 
 void init_outer(const StepArgs& a, const double* u, const float* g, double* x0, double* r64,
                 hipStream_t s) {

@@ -67,7 +67,7 @@ Server::~Server() {
 bool Server::compatible(const sp_params& a, const sp_params& b) {
   return a.tau == b.tau && a.precision == b.precision && a.cg_rtol == b.cg_rtol &&
          a.cg_max_iter == b.cg_max_iter && a.check_every == b.check_every &&
-         a.extrapolate == b.extrapolate &&
+         a.extrapolate == b.extrapolate && a.precond == b.precond &&
          (a.precision == SP_FP64 || (a.inner_rtol == b.inner_rtol && a.max_outer == b.max_outer));
 }
 
@@ -75,14 +75,16 @@ int64_t Server::batch_bytes(const Mesh* m, const sp_params& p, int cap, int rcap
   // state u and outer residual (float64) + CG vectors (float64 pair or
   // float32 quad, plus the rest of the float32 direction ring) and, for the
   // extrapolated start, the float32 increments and a float64 iterate per
-  // element, the float64/float32 K copies of this tau, the mesh matrices,
-  // partial sums and tables
+  // element, the polynomial preconditioner's output, the float64/float32 K
+  // copies of this tau, the mesh matrices, partial sums and tables
   const double n = double(m->n);
+  const bool poly = p.precond == SP_PRECOND_CHEB1;
   const double per_col =
       16.0 + 16.0 + (p.precision != SP_FP64 ? 4.0 * (kPRing - 1) : 0.0) +
-      (p.precision != SP_FP64 && p.extrapolate ? 8.0 + 4.0 * p.extrapolate : 0.0);
+      (p.precision != SP_FP64 && p.extrapolate ? 8.0 + 4.0 * p.extrapolate : 0.0) +
+      (poly ? (p.precision != SP_FP64 ? 4.0 : 8.0) : 0.0);
   const double mats = double(m->W) * n * (4 + 8 + 8 + 8 + 4) + n * 28.0 + double(m->nt) * 20.0;
-  const double part = 3.0 * 8.0 * cap * (n / 64.0 + 1.0);
+  const double part = (poly ? 4.0 : 3.0) * 8.0 * cap * (n / 64.0 + 1.0);
   // staging of request state (admission and retirement) and of labels
   const double stage = 8.0 * n * cap + 4.0 * n * rcap;
   return int64_t(n * cap * per_col + mats + part + stage + 64.0 * (cap + rcap) + (1 << 20));

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libsegpart.so")
 SP_OK, SP_EINVAL, SP_EMESH, SP_ENOMEM, SP_EDEVICE, SP_ENOCONV, SP_EAGAIN, SP_ENOTFOUND = \
     0, -1, -2, -3, -4, -5, -6, -7
 SP_FP64, SP_MIXED = 0, 1
+SP_PRECOND_JACOBI, SP_PRECOND_CHEB1 = 0, 1
 SP_MAT_M, SP_MAT_A = 0, 1
 SP_STAGE_HEAT, SP_STAGE_NODE, SP_STAGE_NORM = 1, 2, 3
 SP_KERNEL_MATVEC, SP_KERNEL_UPDATE, SP_KERNEL_DIRECTION = 0, 1, 2
@@ -40,7 +41,8 @@ class sp_params(C.Structure):
                 ("max_steps", C.c_int64), ("energy_every", C.c_int64),
                 ("precision", C.c_int32), ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int32),
                 ("inner_rtol", C.c_double), ("max_outer", C.c_int32),
-                ("check_every", C.c_int32), ("extrapolate", C.c_int32)]
+                ("check_every", C.c_int32), ("extrapolate", C.c_int32),
+                ("precond", C.c_int32)]
 
 
 class sp_stats(C.Structure):
@@ -178,6 +180,8 @@ def params(tau, **kw):
     for k, v in kw.items():
         if k == "precision" and isinstance(v, str):
             v = {"fp64": SP_FP64, "mixed": SP_MIXED}[v]
+        if k == "precond" and isinstance(v, str):
+            v = {"jacobi": SP_PRECOND_JACOBI, "cheb1": SP_PRECOND_CHEB1}[v]
         if not hasattr(p, k):
             raise KeyError(k)
         setattr(p, k, v)

@@ -37,10 +37,10 @@ def test_binding_has_a_function_per_entry_point():
 
 
 def test_version_and_defaults():
-    assert sp.sp_version() == (1, 2)
+    assert sp.sp_version() == (1, 3)
     p = sp.params(5e-5)
     assert p.tau == 5e-5 and p.energy_every == 2000 and p.precision == sp.SP_MIXED
-    assert p.cg_rtol == 1e-10 and p.check_every == 8
+    assert p.cg_rtol == 1e-10 and p.check_every == 8 and p.precond == sp.SP_PRECOND_CHEB1
     p = sp.params(1e-3, precision="fp64", n_steps=7)
     assert p.precision == sp.SP_FP64 and p.n_steps == 7
 
@@ -134,6 +134,7 @@ def test_rejects_bad_solver_settings():
     for field, value, what in [("cg_rtol", 0.0, "cg_rtol"), ("cg_rtol", 1.0, "cg_rtol"),
                                ("cg_max_iter", 0, "cg_max_iter"),
                                ("extrapolate", 9, "extrapolate"),
+                               ("precond", 2, "precond"), ("precond", -1, "precond"),
                                ("inner_rtol", 0.0, "inner_rtol")]:
         prm = sp.params(1e-3, n_steps=3)
         setattr(prm, field, value)
