@@ -84,20 +84,32 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     own_stream_ = true;
   }
   try {
+    const int n = int(mesh_->n);
+    const size_t nv = size_t(n) * rp_;
+    // small batches run whole steps in one workgroup (float64 CG) unless
+    // SEGPART_SMALL=0
+    const char* sm_env = std::getenv("SEGPART_SMALL");
+    small_ = nv <= size_t(kSmallMaxValues) && rp_ <= kSmallMaxCols &&
+             nres_p_ <= kSmallMaxRestarts && !(sm_env && std::strcmp(sm_env, "0") == 0);
+    const bool poly = prm_.precond == SP_PRECOND_CHEB1 && !small_;
     if (arena_) {
-      // this tau's K, K32 and Jacobi diagonals, built below on the stream
+      // this tau's K, K32, Jacobi diagonals (and preconditioner), built
+      // below on the stream
       const size_t wn = size_t(mesh_->W) * size_t(mesh_->n);
       own_km_.tau = prm_.tau;
       get(own_km_.K64, wn);
       get(own_km_.K32, wn);
       get(own_km_.dinv64, size_t(mesh_->n));
       get(own_km_.dinv32, size_t(mesh_->n));
+      if (poly) {
+        mesh_->cheb_coefs(prm_.tau, &own_km_.pc0, &own_km_.pc1);
+        get(own_km_.P64, wn);
+        get(own_km_.P32, wn);
+      }
       km_ = &own_km_;
     } else {
-      km_ = mesh_->tau_mats(prm_.tau);
+      km_ = mesh_->tau_mats(prm_.tau, poly);
     }
-    const int n = int(mesh_->n);
-    const size_t nv = size_t(n) * rp_;
     Tile t = make_tile(n, rp_, 64, 1, 128);
     sp_.nt = int(mesh_->nt);
     sp_.tchunk = 64;
@@ -110,14 +122,8 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     get(u_, nv);
     heat_x_ = u_.p;
     get(r64_, nv);
-    // small batches run whole steps in one workgroup (float64 CG) unless
-    // SEGPART_SMALL=0
     const char* gr_env = std::getenv("SEGPART_GRAPH");
     graph_on_ = !(gr_env && std::strcmp(gr_env, "0") == 0) && !arena_;  // instantiation allocates
-    const char* sm_env = std::getenv("SEGPART_SMALL");
-    small_ = nv <= size_t(kSmallMaxValues) && rp_ <= kSmallMaxCols &&
-             nres_p_ <= kSmallMaxRestarts && !(sm_env && std::strcmp(sm_env, "0") == 0);
-    const bool poly = prm_.precond == SP_PRECOND_CHEB1 && !small_;
     if (prm_.precision == SP_FP64 || small_) {
       get(p64_, nv);
       get(q64_, nv);
@@ -167,6 +173,7 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
       // fresh allocation does
       k::fill_i32(reinterpret_cast<int32_t*>(arena_->base), 0, arena_->used / 4, s_);
       k::tau_mats(*mesh_, own_km_, s_);
+      if (poly) k::precond_mats(*mesh_, own_km_, s_);
     }
     k::fill_f64(u_.p, 0.0, nv, s_);
     k::fill_f64(r64_.p, 0.0, nv, s_);
@@ -238,7 +245,8 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     if (poly) {
       a.poly = 1;
       a.part2 = part2_.p;
-      mesh_->cheb_coefs(prm_.tau, &a.pc0, &a.pc1);
+      a.P64 = km_->P64.p;
+      a.P32 = km_->P32.p;
     }
     a.ring = ring_.p;
     a.oring = ring_.p + kRing;
@@ -659,13 +667,13 @@ void Solver::heat_fp64() {
   acct(args_.poly ? 16.0 : 24.0, mat_bytes(8.0, 2));
   k::red_init_fp64(args_, s_);
   if (args_.poly) {
-    k::precond_init<double>(args_, r64_.p, p64_.p, km_->K64.p, km_->dinv64.p, s_);
-    acct(16.0, mat_bytes(8.0, 1) + 8.0 * double(mesh_->n));
+    k::precond_init<double>(args_, r64_.p, p64_.p, km_->P64.p, s_);
+    acct(16.0, mat_bytes(8.0, 1));
   }
   int last = 0;
   for (int it = 0; it < prm_.cg_max_iter; ++it) {
     k::cg_iter<double>(args_, it, u_.p, r64_.p, p64_.p, q64_.p, z64_.p, km_->K64.p,
-                       km_->dinv64.p, s_, prof_events());
+                       km_->dinv64.p, km_->P64.p, s_, prof_events());
     last = it + 1;
     if (prm_.check_every > 0 && last % prm_.check_every == 0 && last < prm_.cg_max_iter)
       if (poll(ring_.p + last % kRing) == 0) break;
@@ -798,8 +806,8 @@ void Solver::heat_mixed() {
 // preconditioner: p = z = P r on the columns starting it, with their r.z.
 void Solver::precond_start() {
   if (!args_.poly) return;
-  k::precond_init<float>(args_, r32_.p, p32_.p, km_->K32.p, km_->dinv32.p, s_);
-  acct(8.0, mat_bytes(4.0, 1) + 4.0 * double(mesh_->n));
+  k::precond_init<float>(args_, r32_.p, p32_.p, km_->P32.p, s_);
+  acct(8.0, mat_bytes(4.0, 1));
 }
 
 void Solver::cg_block(int flushed) {
@@ -1079,13 +1087,12 @@ sp_stats Solver::stats() {
   out.converged = st[2] == 0;
   // CG iterations: the columns still iterating (device count) x the three
   // kernels' bytes per element, and the matrix once per iteration with work
-  // (the polynomial preconditioner's pass: r read, z written, the matrix
-  // and the diagonal once more)
+  // (the polynomial preconditioner's pass: r read, z written, its matrix)
   const bool f64 = prm_.precision == SP_FP64 || small_;
   const double n = double(mesh_->n), vb = f64 ? 8.0 : 4.0;
   const bool poly = args_.poly != 0;
   out.hbm_bytes = fixed_bytes_ + double(st[3]) * n * ((f64 ? 88.0 : 32.0) + (poly ? 2 * vb : 0.0)) +
-                  double(st[0]) * (mat_bytes(vb, 1) * (poly ? 2.0 : 1.0) + (poly ? n * vb : 0.0));
+                  double(st[0]) * mat_bytes(vb, 1) * (poly ? 2.0 : 1.0);
   return out;
 }
 

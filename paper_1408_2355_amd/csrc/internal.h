@@ -129,11 +129,16 @@ constexpr int kMaxPer = 256;  // workgroups per XCD range at most (partials size
 Tile make_tile(int n, int rp, int tg_cap = 64, int passes = 1, int nper_cap = kMaxPer);
 
 // Per-time-step matrices for one tau: K = M + tau A in float64 and float32,
-// and the inverse diagonals used by the Jacobi preconditioner.
+// the inverse diagonals used by the Jacobi preconditioner and, once a solver
+// asks for it, the polynomial preconditioner P = D^-1 (c0 I + c1 K D^-1) on
+// K's pattern (precond.cpp).
 struct TauMats {
   double tau = 0;
   DevBuf<double> K64, dinv64;
   DevBuf<float> K32, dinv32;
+  double pc0 = 0, pc1 = 0;
+  DevBuf<double> P64;
+  DevBuf<float> P32;
 };
 
 struct Mesh {
@@ -158,7 +163,8 @@ struct Mesh {
   int device = 0;
   std::mutex mu;
   std::vector<std::unique_ptr<TauMats>> kcache;
-  TauMats* tau_mats(double tau);
+  // with_precond: P64/P32 built too (once per tau)
+  TauMats* tau_mats(double tau, bool with_precond = false);
   // coefficients of the CG's degree-1 Chebyshev preconditioner for
   // K = M + tau A (precond.cpp); host work, cached per tau
   void cheb_coefs(double tau, double* c0, double* c1);
@@ -178,6 +184,8 @@ namespace k {
 void assemble(const Mesh& m, const double* xyz_new, const int32_t* inc_ptr, const int32_t* inc,
               hipStream_t s);
 void tau_mats(const Mesh& m, TauMats& t, hipStream_t s);
+// t.P64 / t.P32 from t.K64, t.dinv64 and t.pc0 / t.pc1
+void precond_mats(const Mesh& m, TauMats& t, hipStream_t s);
 void fill_i32(int32_t* p, int32_t v, size_t n, hipStream_t s);
 void fill_f64(double* p, double v, size_t n, hipStream_t s);
 void fill_f32(float* p, float v, size_t n, hipStream_t s);

@@ -75,12 +75,14 @@ struct StepArgs {
   CgCols cg;
   int* hlen = nullptr;  // per column: heat increments kept for the extrapolated
                         // start (0 .. extrapolate)
-  // Polynomial preconditioner of the CG (poly != 0): z = (pc0 I + pc1 D^-1 K)
-  // D^-1 r, the Chebyshev polynomial of degree 1 for the spectrum of D^-1 K;
-  // part2 [nblk][rp] holds its pass's partial sums r.z (tiling tm).  poly == 0:
-  // Jacobi, z = D^-1 r formed inside the update kernels.
+  // Polynomial preconditioner of the CG (poly != 0): z = P r with
+  // P = D^-1 (c0 I + c1 K D^-1), the Chebyshev polynomial of degree 1 for the
+  // spectrum of D^-1 K applied to the Jacobi step, stored on K's pattern
+  // (P64 / P32); part2 [nblk][rp] holds its pass's partial sums r.z (tiling
+  // tm).  poly == 0: Jacobi, z = D^-1 r formed inside the update kernels.
   int poly = 0;
-  double pc0 = 0.0, pc1 = 0.0;
+  const double* P64 = nullptr;
+  const float* P32 = nullptr;
   double* part2 = nullptr;
   double* part;        // [3][nchunk][rp] partial sums
   int* ring;           // [kRing] inner active counts
@@ -156,15 +158,15 @@ void init_fp64(const StepArgs& a, const double* u, double* r, double* p, hipStre
 // the columns starting this solve (activity count ring[0]), and their r.z
 // into cg.rz.  z is the pass's output buffer (here: the first direction).
 template <typename T>
-void precond_init(const StepArgs& a, const T* r, T* p, const T* K, const T* dinv, hipStream_t s);
+void precond_init(const StepArgs& a, const T* r, T* p, const T* P, hipStream_t s);
 void red_init_fp64(const StepArgs& a, hipStream_t s);
 // one CG iteration on type T vectors (float64 plain or float32 inner); ev,
 // when given, holds 6 events recorded around the matrix product, the x/r
-// update and the p update (before/after each).  z: the preconditioner's
-// output (used when a.poly).
+// update and the p update (before/after each).  z, P: the preconditioner's
+// output and matrix (used when a.poly).
 template <typename T>
 void cg_iter(const StepArgs& a, int it, T* x, T* r, T* p, T* q, T* z, const T* K, const T* dinv,
-             hipStream_t s, const hipEvent_t* ev);
+             const T* P, hipStream_t s, const hipEvent_t* ev);
 // one iteration of the float32 inner CG in direction-ring form: directions
 // in pring[kPRing] (iteration it uses slot it % kPRing and writes the next),
 // alpha rows in ah[kPRing][rp]; when the ring fills, d (+)= sum alpha p and

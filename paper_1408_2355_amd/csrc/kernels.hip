@@ -226,25 +226,6 @@ __device__ __forceinline__ void for_neighbors(const StepArgs& a, int row, int c0
   }
 }
 
-// for_neighbors with the neighbour's row index: f(k, x_k, o, idx_k).
-template <typename T, typename F>
-__device__ __forceinline__ void for_neighbors_i(const StepArgs& a, int row, int c0,
-                                                const T* __restrict__ x, F&& f) {
-  const int n = a.t.n, rp = a.t.rp;
-  for (int kb = 0; kb < a.W; kb += kSlots) {
-    int idx[kSlots];
-#pragma unroll
-    for (int k = 0; k < kSlots; ++k) idx[k] = ldm(a.cols + size_t(kb + k) * n + row);
-    V4<T> xv[kSlots];
-#pragma unroll
-    for (int k = 0; k < kSlots - 1; ++k) xv[k] = ld4(x + size_t(idx[k]) * rp + c0);
-    constexpr int kl = kSlots - 1;
-    xv[kl] = idx[kl] != row ? ld4(x + size_t(idx[kl]) * rp + c0) : V4<T>{};
-#pragma unroll
-    for (int k = 0; k < kSlots; ++k) f(kb + k, xv[k], size_t(kb + k) * n + row, idx[k]);
-  }
-}
-
 // --------------------------------------------------------------- assembly --
 // One thread per row.  P1 element matrices on a flat triangle with corners
 // x0, x1, x2 and edges e_a opposite corner a (e0 = x2 - x1, e1 = x0 - x2,
@@ -311,6 +292,21 @@ __global__ void k_tau_mats(size_t total, int n, double tau, const double* __rest
     dinv64[i] = d;
     dinv32[i] = float(d);
   }
+}
+
+// P = D^-1 (c0 I + c1 K D^-1) on K's pattern: slot 0 (the diagonal)
+// d_i (c0 + c1 K_ii d_i), off-diagonal slots c1 d_i K_ij d_j (padding: 0).
+__global__ void k_precond_mats(size_t total, int n, double c0, double c1,
+                               const int* __restrict__ cols, const double* __restrict__ K,
+                               const double* __restrict__ dinv, double* __restrict__ P64,
+                               float* __restrict__ P32) {
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int row = int(i % size_t(n));
+  const double di = dinv[row], dj = dinv[cols[i]];
+  const double v = i < size_t(n) ? di * (c0 + c1 * K[i] * dj) : c1 * di * K[i] * dj;
+  P64[i] = v;
+  P32[i] = float(v);
 }
 
 // Marks a solve that ended with columns still active (iteration cap hit).
@@ -722,21 +718,19 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_p(StepArgs a, int next, T*
   }
 }
 
-// Polynomial preconditioner pass: z = D^-1 (pc0 r + pc1 K D^-1 r), the
-// degree-1 Chebyshev polynomial in D^-1 K applied to the Jacobi step, on the
-// columns still iterating (0 on the others of a group that has one), with the
-// partials r.z (part2, tiling tm).  A gather like the matrix product: each
-// neighbour's r comes with its own D^-1 (scalar load by index).  Restricted
-// solves keep z on the column's region.
+// Polynomial preconditioner pass: z = P r with P = D^-1 (c0 I + c1 K D^-1),
+// the degree-1 Chebyshev polynomial in D^-1 K applied to the Jacobi step
+// (a matrix of K's pattern, built once per tau: precond_mats), on the
+// columns still iterating (0 on the others of a group that has one), with
+// the partials r.z (part2, tiling tm).  Restricted solves keep z on the
+// column's region.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cg_precond(StepArgs a, int slot,
                                                        const T* __restrict__ r,
                                                        T* __restrict__ z,
-                                                       const T* __restrict__ K,
-                                                       const T* __restrict__ dinv) {
+                                                       const T* __restrict__ P) {
   if (a.ring[slot] == 0) return;
   const Tile& t = a.tm;
-  const T c0 = T(a.pc0), c1 = T(a.pc1);
   for (int ct = 0; ct < t.nct; ++ct) {
   const int g = ct * t.tg + threadIdx.x % t.tg;
   double s[1][4] = {};
@@ -750,14 +744,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_precond(StepArgs a, int slot,
     if (any) {
       for_rows(t, [&](int row) {
         V4<T> acc = {}, ro = {};
-        for_neighbors_i(a, row, cb, r, [&](int k, const V4<T>& x, size_t o, int idx) {
-          const T v = ldm(K + o) * ldm(dinv + idx);
+        for_neighbors(a, row, cb, r, [&](int k, const V4<T>& x, size_t o) {
+          const T v = ldm(P + o);
           if (k == 0) ro = x;
           for (int j = 0; j < 4; ++j) acc.v[j] = fma(v, x.v[j], acc.v[j]);
         });
-        const T di = ldm(dinv + row);
         V4<T> zv;
-        for (int j = 0; j < 4; ++j) zv.v[j] = act[j] ? di * fma(c1, acc.v[j], c0 * ro.v[j]) : T(0);
+        for (int j = 0; j < 4; ++j) zv.v[j] = act[j] ? acc.v[j] : T(0);
         if constexpr (sizeof(T) == 8) {
           if (a.mask)  // restricted solve: z stays on the region
             for (int j = 0; j < 4; ++j)
@@ -2367,6 +2360,13 @@ void tau_mats(const Mesh& m, TauMats& t, hipStream_t s) {
   SP_LAUNCH_CHECK();
 }
 
+void precond_mats(const Mesh& m, TauMats& t, hipStream_t s) {
+  const size_t total = size_t(m.W) * size_t(m.n);
+  hipLaunchKernelGGL(k_precond_mats, dim3(nblocks(total)), dim3(kBlock), 0, s, total, int(m.n),
+                     t.pc0, t.pc1, m.cols.p, t.K64.p, t.dinv64.p, t.P64.p, t.P32.p);
+  SP_LAUNCH_CHECK();
+}
+
 void fill_i32(int32_t* p, int32_t v, size_t n, hipStream_t s) {
   if (!n) return;
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(nblocks(n)), dim3(kBlock), 0, s, p, v, n);
@@ -2401,19 +2401,19 @@ void red_init_fp64(const StepArgs& a, hipStream_t s) {
 }
 
 template <typename T>
-void precond_init(const StepArgs& a, const T* r, T* p, const T* K, const T* dinv, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_precond<T>, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, 0, r, p, K, dinv);
+void precond_init(const StepArgs& a, const T* r, T* p, const T* P, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_precond<T>, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, 0, r, p, P);
   hipLaunchKernelGGL(k_red_precond_init, dim3(colblocks(a.tm)), dim3(kBlock), 0, s, a);
   SP_LAUNCH_CHECK();
 }
 template void precond_init<double>(const StepArgs&, const double*, double*, const double*,
-                                   const double*, hipStream_t);
+                                   hipStream_t);
 template void precond_init<float>(const StepArgs&, const float*, float*, const float*,
-                                  const float*, hipStream_t);
+                                  hipStream_t);
 
 template <typename T>
 void cg_iter(const StepArgs& a, int it, T* x, T* r, T* p, T* q, T* z, const T* K, const T* dinv,
-             hipStream_t s, const hipEvent_t* ev) {
+             const T* P, hipStream_t s, const hipEvent_t* ev) {
   const int slot = it % kRing, next = (it + 1) % kRing;
   const dim3 nb(a.t.nblk), rb(colblocks(a.t)), bl(kBlock);
   if (ev) SP_HIP(hipEventRecord(ev[0], s));
@@ -2424,8 +2424,7 @@ void cg_iter(const StepArgs& a, int it, T* x, T* r, T* p, T* q, T* z, const T* K
   if (a.poly) {
     hipLaunchKernelGGL((k_cg_update<T, true>), nb, bl, 0, s, a, slot, x, r, (const T*)p,
                        (const T*)q, dinv);
-    hipLaunchKernelGGL(k_cg_precond<T>, dim3(a.tm.nblk), bl, 0, s, a, slot, (const T*)r, z, K,
-                       dinv);
+    hipLaunchKernelGGL(k_cg_precond<T>, dim3(a.tm.nblk), bl, 0, s, a, slot, (const T*)r, z, P);
   } else {
     hipLaunchKernelGGL((k_cg_update<T, false>), nb, bl, 0, s, a, slot, x, r, (const T*)p,
                        (const T*)q, dinv);
@@ -2466,7 +2465,7 @@ void cg_iter_ring(const StepArgs& a, int it, float* r, float* const* pring, floa
   if (a.poly) {
     hipLaunchKernelGGL(k_cg_update_r<true>, nb, bl, 0, s, a, slot, r, (const float*)q, a.dinv32);
     hipLaunchKernelGGL(k_cg_precond<float>, dim3(a.tm.nblk), bl, 0, s, a, slot, (const float*)r,
-                       z, (const float*)a.K32, (const float*)a.dinv32);
+                       z, a.P32);
   } else {
     hipLaunchKernelGGL(k_cg_update_r<false>, nb, bl, 0, s, a, slot, r, (const float*)q, a.dinv32);
   }
@@ -2506,9 +2505,11 @@ void materialize(const StepArgs& a, float* const* pring, const double* ah, int f
 }
 
 template void cg_iter<double>(const StepArgs&, int, double*, double*, double*, double*, double*,
-                              const double*, const double*, hipStream_t, const hipEvent_t*);
+                              const double*, const double*, const double*, hipStream_t,
+                              const hipEvent_t*);
 template void cg_iter<float>(const StepArgs&, int, float*, float*, float*, float*, float*,
-                             const float*, const float*, hipStream_t, const hipEvent_t*);
+                             const float*, const float*, const float*, hipStream_t,
+                             const hipEvent_t*);
 
 void init_outer(const StepArgs& a, const double* u, const float* g, double* x0, double* r64,
                 hipStream_t s) {

@@ -240,25 +240,41 @@ Mesh* mesh_create(int64_t n, const double* xyz, int64_t nt, const int32_t* tri) 
 }
 
 // K = M + tau A and its Jacobi diagonal, built once per (mesh, tau) on a
-// private stream and cached; callers on any stream may use the result.
-TauMats* Mesh::tau_mats(double tau) {
+// private stream and cached; callers on any stream may use the result.  The
+// polynomial preconditioner's matrix is added the first time a caller asks.
+TauMats* Mesh::tau_mats(double tau, bool with_precond) {
+  double c0 = 0, c1 = 0;
+  if (with_precond) cheb_coefs(tau, &c0, &c1);  // host work, outside mu
   std::lock_guard<std::mutex> g(mu);
-  for (auto& t : kcache)
-    if (t->tau == tau) return t.get();
-  std::unique_ptr<TauMats> t(new TauMats());
-  t->tau = tau;
-  t->K64.alloc(size_t(W) * n);
-  t->K32.alloc(size_t(W) * n);
-  t->dinv64.alloc(n);
-  t->dinv32.alloc(n);
+  TauMats* t = nullptr;
+  for (auto& e : kcache)
+    if (e->tau == tau) t = e.get();
+  if (t && (!with_precond || t->P64.p)) return t;
+  std::unique_ptr<TauMats> fresh;
+  if (!t) {
+    fresh.reset(new TauMats());
+    t = fresh.get();
+    t->tau = tau;
+    t->K64.alloc(size_t(W) * n);
+    t->K32.alloc(size_t(W) * n);
+    t->dinv64.alloc(n);
+    t->dinv32.alloc(n);
+  }
+  if (with_precond) {
+    t->pc0 = c0;
+    t->pc1 = c1;
+    t->P64.alloc(size_t(W) * n);
+    t->P32.alloc(size_t(W) * n);
+  }
   hipStream_t s;
   SP_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-  k::tau_mats(*this, *t, s);
+  if (fresh) k::tau_mats(*this, *t, s);
+  if (with_precond) k::precond_mats(*this, *t, s);
   hipError_t e = hipStreamSynchronize(s);
   (void)hipStreamDestroy(s);
   SP_HIP(e);
-  kcache.push_back(std::move(t));
-  return kcache.back().get();
+  if (fresh) kcache.push_back(std::move(fresh));
+  return t;
 }
 
 }  // namespace sp

@@ -83,7 +83,8 @@ int64_t Server::batch_bytes(const Mesh* m, const sp_params& p, int cap, int rcap
       16.0 + 16.0 + (p.precision != SP_FP64 ? 4.0 * (kPRing - 1) : 0.0) +
       (p.precision != SP_FP64 && p.extrapolate ? 8.0 + 4.0 * p.extrapolate : 0.0) +
       (poly ? (p.precision != SP_FP64 ? 4.0 : 8.0) : 0.0);
-  const double mats = double(m->W) * n * (4 + 8 + 8 + 8 + 4) + n * 28.0 + double(m->nt) * 20.0;
+  const double mats = double(m->W) * n * (4 + 8 + 8 + 8 + 4 + (poly ? 12 : 0)) + n * 28.0 +
+                      double(m->nt) * 20.0;
   const double part = (poly ? 4.0 : 3.0) * 8.0 * cap * (n / 64.0 + 1.0);
   // staging of request state (admission and retirement) and of labels
   const double stage = 8.0 * n * cap + 4.0 * n * rcap;
