@@ -37,7 +37,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
-KERNEL_NAMES = ("matvec q=(M+tau A)p", "update r", "direction p")
+KERNEL_NAMES = ("matvec q=(M+tau A)p", "update r", "direction p", "precond z=P r")
 
 WORKLOADS = {
     # name: (mesh kind, [(seed, restarts, m)], eps, tau)
@@ -451,7 +451,7 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     s1 = st.stats()
-    kt = [st.kernel_time(k) for k in range(3)]
+    kt = [st.kernel_time(k) for k in range(len(KERNEL_NAMES))]
     st.profile(False)
     lam_b, seps_b, e_b = st.energy()
     value = R * n * args.steps / dt
@@ -467,7 +467,8 @@ def main():
                     unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=traffic,
                     traffic_vs_algorithmic=traffic_ratio, traffic_source=traffic_src,
                     launches=launches, avg_us=avg_s * 1e6, bytes_per_launch=bytes_launch,
-                    kernel_ms_total={KERNEL_NAMES[i]: kt[i][1] for i in range(3)})
+                    kernel_ms_total={KERNEL_NAMES[i]: kt[i][1]
+                                     for i in range(len(KERNEL_NAMES)) if kt[i][0]})
     # the practical HBM rate: a 2 GiB device-to-device copy (read + write bytes),
     # after the timed window
     cx = torch.ones(2**29, dtype=torch.float32, device="cuda:0")

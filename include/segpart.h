@@ -308,13 +308,16 @@ int sp_state_stats(sp_state* st, sp_stats* stats);
  * three large kernels of every CG iteration.  enable != 0 starts recording
  * (and clears the totals); enable == 0 stops. */
 int sp_state_profile(sp_state* st, int32_t enable);
-enum { SP_KERNEL_MATVEC = 0, SP_KERNEL_UPDATE = 1, SP_KERNEL_DIRECTION = 2 };
+enum { SP_KERNEL_MATVEC = 0, SP_KERNEL_UPDATE = 1, SP_KERNEL_DIRECTION = 2,
+       SP_KERNEL_PRECOND = 3 };
 /* For kernel class `which` -- SP_KERNEL_MATVEC (q = (M + tau A) p and the
  * per-column p.q), SP_KERNEL_UPDATE (x += alpha p, r -= alpha q, z = D r and
- * the per-column r.z, r.r) or SP_KERNEL_DIRECTION (p = z + beta p) -- the
- * launch count and summed duration (ms) since profiling was enabled, and the
- * algorithmic (minimum) HBM bytes of one launch over the live columns:
- * float32 vectors in SP_MIXED, float64 in SP_FP64. */
+ * the per-column r.z, r.r; without z under SP_PRECOND_CHEB1),
+ * SP_KERNEL_DIRECTION (p = z + beta p) or SP_KERNEL_PRECOND (z = P r and
+ * the per-column r.z, SP_PRECOND_CHEB1 only) -- the launch count and summed
+ * duration (ms) since profiling was enabled, and the algorithmic (minimum)
+ * HBM bytes of one launch over the live columns: float32 vectors in
+ * SP_MIXED, float64 in SP_FP64. */
 int sp_state_kernel_time(sp_state* st, int32_t which, int64_t* launches, double* total_ms,
                          double* bytes_per_launch);
 /* Tiling the state's matrix-product kernels use (the autotuned one): lanes

@@ -1116,7 +1116,7 @@ const hipEvent_t* Solver::prof_events() {
   if (ev_used_ == ev_.size()) {
     if (ev_.size() >= 4096) prof_flush();
     if (ev_used_ == ev_.size()) {
-      std::array<hipEvent_t, 6> e{};
+      std::array<hipEvent_t, 8> e{};
       for (auto& x : e) SP_HIP(hipEventCreate(&x));
       ev_.push_back(e);
     }
@@ -1128,7 +1128,7 @@ void Solver::prof_flush() {
   if (ev_used_ == 0) return;
   SP_HIP(hipStreamSynchronize(s_));
   for (size_t i = 0; i < ev_used_; ++i) {
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < (args_.poly ? 4 : 3); ++k) {
       float ms = 0.f;
       SP_HIP(hipEventElapsedTime(&ms, ev_[i][2 * k], ev_[i][2 * k + 1]));
       prof_ms_[k] += ms;
@@ -1146,7 +1146,7 @@ void Solver::read_stat(long long* st) {
 void Solver::profile(bool on) {
   prof_flush();
   prof_ = on;
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < kKernelClasses; ++k) {
     prof_launches_[k] = 0;
     prof_ms_[k] = 0.0;
   }
@@ -1154,7 +1154,7 @@ void Solver::profile(bool on) {
 }
 
 void Solver::kernel_time(int which, int64_t* launches, double* ms, double* bytes_per_launch) {
-  SP_REQUIRE(which >= 0 && which < 3, SP_EINVAL, "kernel class must be 0, 1 or 2");
+  SP_REQUIRE(which >= 0 && which < kKernelClasses, SP_EINVAL, "kernel class must be 0, 1, 2 or 3");
   prof_flush();
   if (launches) *launches = prof_launches_[which];
   if (ms) *ms = prof_ms_[which];
@@ -1165,6 +1165,9 @@ void Solver::kernel_time(int which, int64_t* launches, double* ms, double* bytes
     //   1  x += a p, r -= a q read x, r, p, q, write x, r; + the diagonal
     //      (mixed: r -= a q   read r, q, write r; + the diagonal)
     //   2  p = D r + b p      read r, p, write p; + the diagonal
+    //   3  z = P r            read r, write z; + the matrix P
+    // (with the polynomial preconditioner 1 and 2 read no diagonal and 2
+    // reads z for D r)
     // Launches after convergence exit at once and move no data.
     long long st[4];
     read_stat(st);
@@ -1173,9 +1176,10 @@ void Solver::kernel_time(int which, int64_t* launches, double* ms, double* bytes
     const double s = prm_.precision == SP_FP64 ? 8.0 : 4.0;
     const double n = double(mesh_->n);
     // (the mixed inner CG keeps no iterate: its update reads r, q, writes r)
-    const double per[3] = {2.0, prm_.precision == SP_FP64 ? 6.0 : 3.0, 3.0};
+    const double per[kKernelClasses] = {2.0, prm_.precision == SP_FP64 ? 6.0 : 3.0, 3.0, 2.0};
+    const double mat = n * double(mesh_->W) * (4.0 + s);
     double b = n * col_iters * per[which] * s;
-    b += work_iters * (which == 0 ? n * double(mesh_->W) * (4.0 + s) : n * s);
+    b += work_iters * (which == 0 || which == 3 ? mat : args_.poly ? 0.0 : n * s);
     *bytes_per_launch = prof_launches_[which] ? b / double(prof_launches_[which]) : 0.0;
   }
 }

@@ -22,6 +22,10 @@ struct BatchSpec {
 void validate_params(const sp_params& p);
 void validate_batch(int32_t nres, const int32_t* m, const double* eps);
 
+// Kernel classes of the CG profile (sp_state_kernel_time): matrix product,
+// x/r update, p update, polynomial preconditioner pass.
+constexpr int kKernelClasses = 4;
+
 class Solver {
  public:
   // stream == nullptr: the solver creates and owns a stream; otherwise it
@@ -256,10 +260,10 @@ class Solver {
   std::vector<std::vector<std::pair<int64_t, double>>> hist_;
 
   bool prof_ = false;
-  std::vector<std::array<hipEvent_t, 6>> ev_;
+  std::vector<std::array<hipEvent_t, 8>> ev_;
   size_t ev_used_ = 0;
-  int64_t prof_launches_[3] = {0, 0, 0};
-  double prof_ms_[3] = {0.0, 0.0, 0.0};
+  int64_t prof_launches_[kKernelClasses] = {};
+  double prof_ms_[kKernelClasses] = {};
   long long prof_stat0_[4] = {0, 0, 0, 0};
   void prof_flush();
   const hipEvent_t* prof_events();

@@ -161,8 +161,9 @@ template <typename T>
 void precond_init(const StepArgs& a, const T* r, T* p, const T* P, hipStream_t s);
 void red_init_fp64(const StepArgs& a, hipStream_t s);
 // one CG iteration on type T vectors (float64 plain or float32 inner); ev,
-// when given, holds 6 events recorded around the matrix product, the x/r
-// update and the p update (before/after each).  z, P: the preconditioner's
+// when given, holds 8 events recorded around the matrix product, the x/r
+// update, the p update and (a.poly) the preconditioner pass (before/after
+// each; without a.poly the last pair stays unrecorded).  z, P: the preconditioner's
 // output and matrix (used when a.poly).
 template <typename T>
 void cg_iter(const StepArgs& a, int it, T* x, T* r, T* p, T* q, T* z, const T* K, const T* dinv,

@@ -2424,12 +2424,15 @@ void cg_iter(const StepArgs& a, int it, T* x, T* r, T* p, T* q, T* z, const T* K
   if (a.poly) {
     hipLaunchKernelGGL((k_cg_update<T, true>), nb, bl, 0, s, a, slot, x, r, (const T*)p,
                        (const T*)q, dinv);
+    if (ev) SP_HIP(hipEventRecord(ev[3], s));
+    if (ev) SP_HIP(hipEventRecord(ev[6], s));
     hipLaunchKernelGGL(k_cg_precond<T>, dim3(a.tm.nblk), bl, 0, s, a, slot, (const T*)r, z, P);
+    if (ev) SP_HIP(hipEventRecord(ev[7], s));
   } else {
     hipLaunchKernelGGL((k_cg_update<T, false>), nb, bl, 0, s, a, slot, x, r, (const T*)p,
                        (const T*)q, dinv);
+    if (ev) SP_HIP(hipEventRecord(ev[3], s));
   }
-  if (ev) SP_HIP(hipEventRecord(ev[3], s));
   if (a.poly)
     hipLaunchKernelGGL(k_red_beta<true>, rb, bl, 0, s, a, slot, next);
   else
@@ -2464,12 +2467,15 @@ void cg_iter_ring(const StepArgs& a, int it, float* r, float* const* pring, floa
   if (ev) SP_HIP(hipEventRecord(ev[2], s));
   if (a.poly) {
     hipLaunchKernelGGL(k_cg_update_r<true>, nb, bl, 0, s, a, slot, r, (const float*)q, a.dinv32);
+    if (ev) SP_HIP(hipEventRecord(ev[3], s));
+    if (ev) SP_HIP(hipEventRecord(ev[6], s));
     hipLaunchKernelGGL(k_cg_precond<float>, dim3(a.tm.nblk), bl, 0, s, a, slot, (const float*)r,
                        z, a.P32);
+    if (ev) SP_HIP(hipEventRecord(ev[7], s));
   } else {
     hipLaunchKernelGGL(k_cg_update_r<false>, nb, bl, 0, s, a, slot, r, (const float*)q, a.dinv32);
+    if (ev) SP_HIP(hipEventRecord(ev[3], s));
   }
-  if (ev) SP_HIP(hipEventRecord(ev[3], s));
   if (a.poly)
     hipLaunchKernelGGL(k_red_beta<true>, rb, bl, 0, s, a, slot, next);
   else

@@ -23,7 +23,7 @@ SP_FP64, SP_MIXED = 0, 1
 SP_PRECOND_JACOBI, SP_PRECOND_CHEB1 = 0, 1
 SP_MAT_M, SP_MAT_A = 0, 1
 SP_STAGE_HEAT, SP_STAGE_NODE, SP_STAGE_NORM = 1, 2, 3
-SP_KERNEL_MATVEC, SP_KERNEL_UPDATE, SP_KERNEL_DIRECTION = 0, 1, 2
+SP_KERNEL_MATVEC, SP_KERNEL_UPDATE, SP_KERNEL_DIRECTION, SP_KERNEL_PRECOND = 0, 1, 2, 3
 
 _NAMES = {SP_EINVAL: "SP_EINVAL", SP_EMESH: "SP_EMESH", SP_ENOMEM: "SP_ENOMEM",
           SP_EDEVICE: "SP_EDEVICE", SP_ENOCONV: "SP_ENOCONV", SP_EAGAIN: "SP_EAGAIN",

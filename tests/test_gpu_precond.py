@@ -91,3 +91,30 @@ def test_cheb1_state_stepping_matches_one_call():
     b.close()
     mesh.close()
     assert np.array_equal(ua, ub)
+
+
+@pytest.mark.parametrize("pc", ["jacobi", "cheb1"])
+def test_kernel_profile_classes(pc):
+    """sp_state_kernel_time: the preconditioner pass is a class of its own
+    (launched once per iteration with the polynomial preconditioner, never
+    with Jacobi), every class reports positive algorithmic bytes."""
+    v, f = icosphere(5)
+    u0, ms = batch_u0(v.shape[0], [(64, 2, 5)])
+    mesh = sp.Mesh(v, f)
+    prm = sp.params(5e-4, precision="mixed", n_steps=1, energy_every=0, precond=pc)
+    st = sp.State(mesh, prm, ms, np.full(ms.size, 0.08), u0)
+    st.step(2)
+    st.profile(True)
+    st.step(3)
+    kt = [st.kernel_time(k) for k in range(4)]
+    st.profile(False)
+    st.close()
+    mesh.close()
+    n_iter = kt[sp.SP_KERNEL_MATVEC][0]
+    assert n_iter > 0
+    for k in range(3):
+        assert kt[k][0] == n_iter and kt[k][1] > 0 and kt[k][2] > 0
+    if pc == "cheb1":
+        assert kt[sp.SP_KERNEL_PRECOND][0] == n_iter and kt[sp.SP_KERNEL_PRECOND][2] > 0
+    else:
+        assert kt[sp.SP_KERNEL_PRECOND][0] == 0
