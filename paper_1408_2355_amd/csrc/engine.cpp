@@ -133,11 +133,11 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     if (prm_.precision != SP_FP64) {
       get(d32_, nv);
       get(r32_, nv);
-      get(p32_, nv);
+      get(p16_, nv);
       get(q32_, nv);
-      if (poly) get(z32_, nv);
-      // direction ring of the inner CG: p32_ is slot 0
-      pring_[0] = p32_.p;
+      if (poly) get(z16_, nv);
+      // direction ring of the inner CG: p16_ is slot 0
+      pring_[0] = p16_.p;
       for (int i = 1; i < kPRing; ++i) {
         get(pbuf_[i], nv);
         pring_[i] = pbuf_[i].p;
@@ -159,7 +159,7 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     get(colf_, size_t(CF_N) * rp_ + nres_p_);
     get(coli_, size_t(CI_N) * rp_ + 3 * size_t(nres_p_));
     get(ring_, 2 * kRing);
-    get(stat_, 4);
+    get(stat_, kStats);
     get(lam_, rp_);
     get(seps_, nres_p_);
     get(energy_, nres_p_);
@@ -178,11 +178,11 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     k::fill_f64(u_.p, 0.0, nv, s_);
     k::fill_f64(r64_.p, 0.0, nv, s_);
     if (z64_.p) k::fill_f64(z64_.p, 0.0, nv, s_);
-    if (z32_.p) k::fill_f32(z32_.p, 0.0f, nv, s_);
+    if (z16_.p) k::fill_i32(reinterpret_cast<int32_t*>(z16_.p), 0, nv / 2, s_);
     for (int i = 0; i < kMaxExtrap; ++i)
       if (dh_[i]) k::fill_f32(dh_[i], 0.0f, nv, s_);
     for (int i = 0; i < kPRing; ++i)
-      if (pring_[i]) k::fill_f32(pring_[i], 0.0f, nv, s_);
+      if (pring_[i]) k::fill_i32(reinterpret_cast<int32_t*>(pring_[i]), 0, nv / 2, s_);
     if (ah_.p) k::fill_f64(ah_.p, 0.0, ah_.n, s_);
     k::fill_f64(colf_.p, 0.0, colf_.n, s_);
     k::fill_i32(coli_.p, 0, coli_.n, s_);
@@ -384,12 +384,13 @@ void Solver::autotune() {
   if (f64)
     k::fill_f64(p64_.p, 1.0, nv, s_);
   else
-    k::fill_f32(p32_.p, 1.0f, nv, s_);
+    // bf16 ones, two per 32-bit word
+    k::fill_i32(reinterpret_cast<int32_t*>(p16_.p), 0x3f803f80, nv / 2, s_);
   const TuneChoice best = tune_tiling(key, &StepArgs::tm, [&] {
     if (f64)
-      k::matvec<double>(args_, km_->K64.p, p64_.p, q64_.p, s_);
+      k::matvec<double, double>(args_, km_->K64.p, p64_.p, q64_.p, s_);
     else
-      k::matvec<float>(args_, km_->K32.p, p32_.p, q32_.p, s_);
+      k::matvec<float, bf16_t>(args_, km_->K32.p, p16_.p, q32_.p, s_);
   });
   k::fill_i32(args_.cg.act, 0, rp_, s_);
   k::fill_i32(ring_.p, 0, ring_.n, s_);
@@ -667,7 +668,7 @@ void Solver::heat_fp64() {
   acct(args_.poly ? 16.0 : 24.0, mat_bytes(8.0, 2));
   k::red_init_fp64(args_, s_);
   if (args_.poly) {
-    k::precond_init<double>(args_, r64_.p, p64_.p, km_->P64.p, s_);
+    k::precond_init<double, double>(args_, r64_.p, p64_.p, km_->P64.p, s_);
     acct(16.0, mat_bytes(8.0, 1));
   }
   int last = 0;
@@ -711,8 +712,8 @@ void Solver::heat_mixed() {
     }
     if (fast) {
       // A u and ||M u||^2 from the last step's norm pass: no float64 gather
-      k::refine_start(args_, xg_.p, acc, r64_.p, r32_.p, args_.poly ? nullptr : p32_.p, s_);
-      acct(args_.poly ? 24.0 : 28.0, mat_bytes(8.0, 1));
+      k::refine_start(args_, xg_.p, acc, r64_.p, r32_.p, args_.poly ? nullptr : p16_.p, s_);
+      acct(args_.poly ? 24.0 : 26.0, mat_bytes(8.0, 1));
       precond_start();
     } else {
       k::init_outer(args_, u_.p, acc, xg_.p, r64_.p, s_);
@@ -733,8 +734,8 @@ void Solver::heat_mixed() {
   bool prepared = false;  // the last update wrote this sweep's inner start
   for (int o = 0; o < prm_.max_outer; ++o) {
     if (!(fast && o == 0) && !prepared) {
-      k::inner_init(args_, o, r64_.p, d32_.p, r32_.p, args_.poly ? nullptr : p32_.p, s_);
-      acct(args_.poly ? 12.0 : 16.0);
+      k::inner_init(args_, o, r64_.p, d32_.p, r32_.p, args_.poly ? nullptr : p16_.p, s_);
+      acct(args_.poly ? 12.0 : 14.0);
       k::red_inner_init(args_, o, s_);
       precond_start();
     }
@@ -748,7 +749,7 @@ void Solver::heat_mixed() {
         flushed = 1;
         it += kPRing;
       } else {
-        k::cg_iter_ring(args_, it, r32_.p, pring_, q32_.p, z32_.p, ah_.p, d32_.p, &flushed, s_,
+        k::cg_iter_ring(args_, it, r32_.p, pring_, q32_.p, z16_.p, ah_.p, d32_.p, &flushed, s_,
                         prof_events());
         ++it;
       }
@@ -758,9 +759,9 @@ void Solver::heat_mixed() {
     }
     if (last % kPRing) {
       k::materialize(args_, pring_, ah_.p, 0, last % kPRing, flushed, d32_.p, s_);
-      acct(4.0 * (last % kPRing) + (flushed ? 8.0 : 4.0));
+      acct(2.0 * (last % kPRing) + (flushed ? 8.0 : 4.0));
     }
-    acct(4.0 * (last - last % kPRing) + 12.0 * (last / kPRing));  // ring folds inside the solve
+    acct(2.0 * (last - last % kPRing) + 12.0 * (last / kPRing));  // ring folds inside the solve
     // with a poll after this sweep the new residual is stored only if
     // another sweep follows (most steps need one); when the last step needed
     // more than one sweep, the update writes the next sweep's start as well
@@ -769,9 +770,9 @@ void Solver::heat_mixed() {
     const bool ubase = fast && o == 0;
     args_.usc = ubase && u_pending_ ? args_.cg.isc : nullptr;
     k::outer_update(args_, o, x, ubase ? u_.p : nullptr, r64_.p, d32_.p, acc, !polled,
-                    prep ? r32_.p : nullptr, prep && !args_.poly ? p32_.p : nullptr, s_);
+                    prep ? r32_.p : nullptr, prep && !args_.poly ? p16_.p : nullptr, s_);
     acct(28.0 + (polled && !prep ? 0.0 : 8.0) + (acc ? 8.0 : 0.0) +
-             (prep ? (args_.poly ? 4.0 : 8.0) : 0.0),
+             (prep ? (args_.poly ? 4.0 : 6.0) : 0.0),
          mat_bytes(8.0, 1));
     args_.usc = nullptr;
     if (prep) {
@@ -806,8 +807,8 @@ void Solver::heat_mixed() {
 // preconditioner: p = z = P r on the columns starting it, with their r.z.
 void Solver::precond_start() {
   if (!args_.poly) return;
-  k::precond_init<float>(args_, r32_.p, p32_.p, km_->P32.p, s_);
-  acct(8.0, mat_bytes(4.0, 1));
+  k::precond_init<float, bf16_t>(args_, r32_.p, p16_.p, km_->P32.p, s_);
+  acct(6.0, mat_bytes(4.0, 1));
 }
 
 void Solver::cg_block(int flushed) {
@@ -825,7 +826,7 @@ void Solver::cg_block(int flushed) {
     try {
       int f = flushed;
       for (int i = 0; i < kPRing; ++i)
-        k::cg_iter_ring(args_, i, r32_.p, pring_, q32_.p, z32_.p, ah_.p, d32_.p, &f, s_, nullptr);
+        k::cg_iter_ring(args_, i, r32_.p, pring_, q32_.p, z16_.p, ah_.p, d32_.p, &f, s_, nullptr);
     } catch (...) {
       (void)hipStreamEndCapture(s_, &g);
       if (g) (void)hipGraphDestroy(g);
@@ -1074,7 +1075,7 @@ void Solver::labels_host(int32_t* lab, int32_t* lab_am) {
 }
 
 sp_stats Solver::stats() {
-  long long st[4] = {0, 0, 0, 0};
+  long long st[kStats] = {};
   std::vector<int> it(rp_);
   SP_HIP(hipMemcpyAsync(st, stat_.p, sizeof(st), hipMemcpyDeviceToHost, s_));
   SP_HIP(hipMemcpyAsync(it.data(), args_.cg.iters, rp_ * sizeof(int), hipMemcpyDeviceToHost, s_));
@@ -1085,13 +1086,15 @@ sp_stats Solver::stats() {
   out.outer_sweeps = st[1];
   out.col_iters_max = it.empty() ? 0 : *std::max_element(it.begin(), it.end());
   out.converged = st[2] == 0;
-  // CG iterations: the columns still iterating (device count) x the three
-  // kernels' bytes per element, and the matrix once per iteration with work
-  // (the polynomial preconditioner's pass: r read, z written, its matrix)
+  // CG iterations: the columns still iterating (device count) x the
+  // iteration's bytes per element (kernel_time's classes), and the matrices
+  // once per iteration with work
   const bool f64 = prm_.precision == SP_FP64 || small_;
   const double n = double(mesh_->n), vb = f64 ? 8.0 : 4.0;
   const bool poly = args_.poly != 0;
-  out.hbm_bytes = fixed_bytes_ + double(st[3]) * n * ((f64 ? 88.0 : 32.0) + (poly ? 2 * vb : 0.0)) +
+  double per_elem = 0.0;
+  for (int k = 0; k < kKernelClasses; ++k) per_elem += class_bytes(k, f64);
+  out.hbm_bytes = fixed_bytes_ + double(st[3]) * n * per_elem +
                   double(st[0]) * mat_bytes(vb, 1) * (poly ? 2.0 : 1.0);
   return out;
 }
@@ -1139,7 +1142,7 @@ void Solver::prof_flush() {
 }
 
 void Solver::read_stat(long long* st) {
-  SP_HIP(hipMemcpyAsync(st, stat_.p, 4 * sizeof(long long), hipMemcpyDeviceToHost, s_));
+  SP_HIP(hipMemcpyAsync(st, stat_.p, kStats * sizeof(long long), hipMemcpyDeviceToHost, s_));
   SP_HIP(hipStreamSynchronize(s_));
 }
 
@@ -1153,6 +1156,22 @@ void Solver::profile(bool on) {
   read_stat(prof_stat0_);
 }
 
+// Bytes per element that one CG iteration's kernel class moves per column
+// still iterating (vectors only; the matrices and diagonals are added per
+// launch).  float64 CG: 0 q = K p reads p, writes q; 1 x += a p, r -= a q
+// reads x, r, p, q, writes x, r; 2 p = z + b p reads r (or z), p, writes p;
+// 3 z = P r reads r, writes z.  float32 inner CG: r and q float32, the ring
+// directions p and the preconditioner output z bf16; 1 reads r, q and
+// writes r (no iterate).
+double Solver::class_bytes(int which, bool f64) const {
+  if (f64 || small_) {
+    const double b[kKernelClasses] = {16.0, 48.0, 24.0, args_.poly ? 16.0 : 0.0};
+    return b[which];
+  }
+  const double b[kKernelClasses] = {6.0, 12.0, args_.poly ? 6.0 : 8.0, args_.poly ? 6.0 : 0.0};
+  return b[which];
+}
+
 void Solver::kernel_time(int which, int64_t* launches, double* ms, double* bytes_per_launch) {
   SP_REQUIRE(which >= 0 && which < kKernelClasses, SP_EINVAL, "kernel class must be 0, 1, 2 or 3");
   prof_flush();
@@ -1160,25 +1179,19 @@ void Solver::kernel_time(int which, int64_t* launches, double* ms, double* bytes
   if (ms) *ms = prof_ms_[which];
   if (bytes_per_launch) {
     // Minimum HBM traffic, summed over the profiled launches and divided by
-    // their count.  Per column that is still iterating:
-    //   0  q = K p            read p, write q; + the matrix (indices, values)
-    //   1  x += a p, r -= a q read x, r, p, q, write x, r; + the diagonal
-    //      (mixed: r -= a q   read r, q, write r; + the diagonal)
-    //   2  p = D r + b p      read r, p, write p; + the diagonal
-    //   3  z = P r            read r, write z; + the matrix P
-    // (with the polynomial preconditioner 1 and 2 read no diagonal and 2
-    // reads z for D r)
-    // Launches after convergence exit at once and move no data.
-    long long st[4];
+    // their count: the vectors of every column still iterating
+    // (class_bytes), plus per launch with work the matrix K (class 0) or P
+    // (class 3) as indices and values, or the Jacobi diagonal (classes 1 and
+    // 2 without the polynomial preconditioner).  Launches after convergence
+    // exit at once and move no data.
+    long long st[kStats];
     read_stat(st);
     const double work_iters = double(st[0] - prof_stat0_[0]);
     const double col_iters = double(st[3] - prof_stat0_[3]);
     const double s = prm_.precision == SP_FP64 ? 8.0 : 4.0;
     const double n = double(mesh_->n);
-    // (the mixed inner CG keeps no iterate: its update reads r, q, writes r)
-    const double per[kKernelClasses] = {2.0, prm_.precision == SP_FP64 ? 6.0 : 3.0, 3.0, 2.0};
     const double mat = n * double(mesh_->W) * (4.0 + s);
-    double b = n * col_iters * per[which] * s;
+    double b = n * col_iters * class_bytes(which, prm_.precision == SP_FP64);
     b += work_iters * (which == 0 || which == 3 ? mat : args_.poly ? 0.0 : n * s);
     *bytes_per_launch = prof_launches_[which] ? b / double(prof_launches_[which]) : 0.0;
   }

@@ -25,6 +25,8 @@ void validate_batch(int32_t nres, const int32_t* m, const double* eps);
 // Kernel classes of the CG profile (sp_state_kernel_time): matrix product,
 // x/r update, p update, polynomial preconditioner pass.
 constexpr int kKernelClasses = 4;
+// Device counters of a batch (StepArgs::stat).
+constexpr int kStats = 4;
 
 class Solver {
  public:
@@ -192,11 +194,12 @@ class Solver {
   bool detached_ = false;
 
   DevBuf<double> u_, r64_, p64_, q64_;
-  DevBuf<float> d32_, r32_, p32_, q32_;
+  DevBuf<float> d32_, r32_, q32_;
+  DevBuf<bf16_t> p16_;  // direction ring slot 0 (bf16, like the whole ring)
   DevBuf<double> z64_;  // polynomial preconditioner's output (float64 CG)
-  DevBuf<float> z32_;   // (float32 inner CG)
-  DevBuf<float> pbuf_[kPRing];        // direction ring slots 1.. (slot 0 is p32_)
-  float* pring_[kPRing] = {};
+  DevBuf<bf16_t> z16_;  // (float32 inner CG: bf16)
+  DevBuf<bf16_t> pbuf_[kPRing];       // direction ring slots 1.. (slot 0 is p16_)
+  bf16_t* pring_[kPRing] = {};
   DevBuf<double> ah_;                 // [kPRing][rp] alpha of each ring slot
   // heat increments of the last prm_.extrapolate steps (extrapolated start):
   // dh_[0] the latest, dh_[q-1] the oldest; a solve overwrites the oldest
@@ -233,6 +236,7 @@ class Solver {
   // legacy default stream, or with another polling period.
   void cg_block(int flushed);
   void precond_start();
+  double class_bytes(int which, bool f64) const;
   bool graph_on_ = true;
   hipGraphExec_t cg_graph_[2] = {nullptr, nullptr};
   StepArgs cg_graph_args_[2];
@@ -264,7 +268,7 @@ class Solver {
   size_t ev_used_ = 0;
   int64_t prof_launches_[kKernelClasses] = {};
   double prof_ms_[kKernelClasses] = {};
-  long long prof_stat0_[4] = {0, 0, 0, 0};
+  long long prof_stat0_[kStats] = {};
   void prof_flush();
   const hipEvent_t* prof_events();
   void read_stat(long long* st);

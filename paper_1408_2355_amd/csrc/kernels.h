@@ -9,6 +9,12 @@ namespace sp {
 
 constexpr int kRing = 4;  // slots of the per-iteration active-column counters
 
+// bfloat16 storage element: the upper half of a float32 (rounded to nearest
+// even on store).  The float32 inner CG keeps its directions in it.
+struct bf16_t {
+  uint16_t bits;
+};
+
 // Per-column tables of a batch (device).
 struct ColTab {
   const int* seg_lo = nullptr;   // first column of the column's restart
@@ -94,7 +100,7 @@ struct StepArgs {
 // Direction ring of the float32 inner CG (see kernels.hip).
 constexpr int kPRing = 8;
 struct RingArgs {
-  const float* p[kPRing] = {};
+  const bf16_t* p[kPRing] = {};
   int row[kPRing] = {};  // coefficient row (ring slot) of each direction
   int n = 0;
   int accumulate = 0;    // 0: d = sum, 1: d += sum
@@ -156,11 +162,12 @@ void flag_nonconv(const StepArgs& a, const int* counter, hipStream_t s);
 void init_fp64(const StepArgs& a, const double* u, double* r, double* p, hipStream_t s);
 // Polynomial preconditioner at the start of a solve (a.poly): p = z = P r on
 // the columns starting this solve (activity count ring[0]), and their r.z
-// into cg.rz.  z is the pass's output buffer (here: the first direction).
-template <typename T>
-void precond_init(const StepArgs& a, const T* r, T* p, const T* P, hipStream_t s);
+// into cg.rz.  z is the pass's output buffer (here: the first direction;
+// Z = bf16_t for the float32 CG's ring, double for the float64 CG).
+template <typename T, typename Z>
+void precond_init(const StepArgs& a, const T* r, Z* p, const T* P, hipStream_t s);
 void red_init_fp64(const StepArgs& a, hipStream_t s);
-// one CG iteration on type T vectors (float64 plain or float32 inner); ev,
+// one CG iteration on type T vectors (the float64 plain CG); ev,
 // when given, holds 8 events recorded around the matrix product, the x/r
 // update, the p update and (a.poly) the preconditioner pass (before/after
 // each; without a.poly the last pair stays unrecorded).  z, P: the preconditioner's
@@ -169,18 +176,19 @@ template <typename T>
 void cg_iter(const StepArgs& a, int it, T* x, T* r, T* p, T* q, T* z, const T* K, const T* dinv,
              const T* P, hipStream_t s, const hipEvent_t* ev);
 // one iteration of the float32 inner CG in direction-ring form: directions
-// in pring[kPRing] (iteration it uses slot it % kPRing and writes the next),
-// alpha rows in ah[kPRing][rp]; when the ring fills, d (+)= sum alpha p and
-// *flushed is set (later folds accumulate)
-void cg_iter_ring(const StepArgs& a, int it, float* r, float* const* pring, float* q, float* z,
+// in pring[kPRing] (bf16; iteration it uses slot it % kPRing and writes the
+// next), alpha rows in ah[kPRing][rp]; when the ring fills, d (+)= sum
+// alpha p and *flushed is set (later folds accumulate).  z (bf16): the
+// polynomial preconditioner's output.
+void cg_iter_ring(const StepArgs& a, int it, float* r, bf16_t* const* pring, float* q, bf16_t* z,
                   double* ah, float* d, int* flushed, hipStream_t s, const hipEvent_t* ev);
 // d (+)= sum over count ring slots from first (cyclic) of alpha_slot p_slot
-void materialize(const StepArgs& a, float* const* pring, const double* ah, int first, int count,
+void materialize(const StepArgs& a, bf16_t* const* pring, const double* ah, int first, int count,
                  int accumulate, float* d, hipStream_t s);
 // the CG matrix product alone (q = K p over the active columns; needs
-// ring[0] != 0), used to time tilings
-template <typename T>
-void matvec(const StepArgs& a, const T* K, const T* p, T* q, hipStream_t s);
+// ring[0] != 0), used to time tilings; p stored as S (float32 CG: bf16)
+template <typename T, typename S>
+void matvec(const StepArgs& a, const T* K, const S* p, T* q, hipStream_t s);
 // mixed precision refinement
 // r64 = M u - K x0 with x0 = u + g (g nullable: x0 = u, nothing written to
 // x0); x0 must not alias u
@@ -188,14 +196,14 @@ void init_outer(const StepArgs& a, const double* u, const float* g, double* x0, 
                 hipStream_t s);
 void red_outer_init(const StepArgs& a, hipStream_t s);
 // (p nullable: the polynomial preconditioner's pass writes the first direction)
-void inner_init(const StepArgs& a, int o, const double* r64, float* d, float* r, float* p,
+void inner_init(const StepArgs& a, int o, const double* r64, float* d, float* r, bf16_t* p,
                 hipStream_t s);
 // refinement start and first inner start from the norm pass's A v (w) and
 // ||M u||^2; replaces init_outer, red_outer_init, inner_init and
 // red_inner_init of sweep 0 (the iterate u + g is formed by the first
 // outer_update in ubase mode)
 void refine_start(const StepArgs& a, const double* w, const float* g, double* r64, float* r,
-                  float* p, hipStream_t s);  // p nullable as in inner_init
+                  bf16_t* p, hipStream_t s);  // p nullable as in inner_init
 void red_inner_init(const StepArgs& a, int o, hipStream_t s);
 // x += d (ubase given: x = ubase + dacc + d), r64 -= K d on the columns
 // still refining; dacc (nullable) += d; store_r false: r64 not stored (then
@@ -203,7 +211,7 @@ void red_inner_init(const StepArgs& a, int o, hipStream_t s);
 // also the next sweep's inner start r = float(r64), p = D r (r64 stored);
 // reduce with red_outer_prep instead of red_outer
 void outer_update(const StepArgs& a, int o, double* x, const double* ubase, double* r64,
-                  const float* d, float* dacc, bool store_r, float* rn, float* pn,
+                  const float* d, float* dacc, bool store_r, float* rn, bf16_t* pn,
                   hipStream_t s);
 // outer test of sweep o and, for the columns still refining, the scalars of
 // the inner start that outer_update(rn, pn) wrote

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -70,14 +71,44 @@ __device__ __forceinline__ V4<double> ld4_nt(const double* p) {
   d2v b = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p) + 1);
   return {{a.x, a.y, b.x, b.y}};
 }
-template <typename T>
-__device__ __forceinline__ V4<T> ld4g(const T* p) { return ld4_nt(p); }  // own row, gathering kernel
-template <typename T>
-__device__ __forceinline__ void st4g(T* p, const V4<T>& x) { st4_nt(p, x); }  // gathering kernel
-template <typename T>
-__device__ __forceinline__ V4<T> ld4s(const T* p) { return ld4_nt(p); }  // streaming kernel
-template <typename T>
-__device__ __forceinline__ void st4s(T* p, const V4<T>& x) { st4_nt(p, x); }  // streaming kernel
+// bfloat16 storage (the inner float32 CG's directions and preconditioner
+// output): the upper 16 bits of the float32, rounded to nearest even; 4
+// values in 8 bytes, widened to float32 on load.
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+  const uint32_t u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0u;  // NaN stays a NaN
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ V4<float> bf16_unpack(uint32_t lo, uint32_t hi) {
+  return {{__uint_as_float(lo << 16), __uint_as_float(lo & 0xffff0000u),
+           __uint_as_float(hi << 16), __uint_as_float(hi & 0xffff0000u)}};
+}
+typedef uint32_t u2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ V4<float> ld4(const bf16_t* p) {
+  const u2v w = *reinterpret_cast<const u2v*>(p);
+  return bf16_unpack(w.x, w.y);
+}
+__device__ __forceinline__ V4<float> ld4_nt(const bf16_t* p) {
+  const u2v w = __builtin_nontemporal_load(reinterpret_cast<const u2v*>(p));
+  return bf16_unpack(w.x, w.y);
+}
+__device__ __forceinline__ void st4_nt(bf16_t* p, const V4<float>& x) {
+  u2v w = {bf16_bits(x.v[0]) | (bf16_bits(x.v[1]) << 16),
+           bf16_bits(x.v[2]) | (bf16_bits(x.v[3]) << 16)};
+  __builtin_nontemporal_store(w, reinterpret_cast<u2v*>(p));
+}
+// Values as they come back from storage type S (bf16: float32).
+template <typename S>
+using V4of = decltype(ld4(static_cast<const S*>(nullptr)));
+
+template <typename S>
+__device__ __forceinline__ V4of<S> ld4g(const S* p) { return ld4_nt(p); }  // own row, gathering kernel
+template <typename S, typename V>
+__device__ __forceinline__ void st4g(S* p, const V& x) { st4_nt(p, x); }  // gathering kernel
+template <typename S>
+__device__ __forceinline__ V4of<S> ld4s(const S* p) { return ld4_nt(p); }  // streaming kernel
+template <typename S, typename V>
+__device__ __forceinline__ void st4s(S* p, const V& x) { st4_nt(p, x); }  // streaming kernel
 
 // Row traversal of the row-parallel kernels.  Workgroups are handed to the
 // 8 XCDs round-robin by id, so workgroup b runs on XCD b % 8.  The rows are
@@ -208,19 +239,19 @@ __device__ __forceinline__ T ldm(const T* p) {
   return *(const __attribute__((address_space(4))) T*)(p);
 }
 
-template <typename T, typename F>
+template <typename S, typename F>
 __device__ __forceinline__ void for_neighbors(const StepArgs& a, int row, int c0,
-                                              const T* __restrict__ x, F&& f) {
+                                              const S* __restrict__ x, F&& f) {
   const int n = a.t.n, rp = a.t.rp;
   for (int kb = 0; kb < a.W; kb += kSlots) {
     int idx[kSlots];
 #pragma unroll
     for (int k = 0; k < kSlots; ++k) idx[k] = ldm(a.cols + size_t(kb + k) * n + row);
-    V4<T> xv[kSlots];
+    V4of<S> xv[kSlots];
 #pragma unroll
     for (int k = 0; k < kSlots - 1; ++k) xv[k] = ld4(x + size_t(idx[k]) * rp + c0);
     constexpr int kl = kSlots - 1;
-    xv[kl] = idx[kl] != row ? ld4(x + size_t(idx[kl]) * rp + c0) : V4<T>{};
+    xv[kl] = idx[kl] != row ? ld4(x + size_t(idx[kl]) * rp + c0) : V4of<S>{};
 #pragma unroll
     for (int k = 0; k < kSlots; ++k) f(kb + k, xv[k], size_t(kb + k) * n + row);
   }
@@ -382,10 +413,10 @@ __global__ void k_red_init_fp64(StepArgs a) {
   count_active(act, a.ring + 0);
 }
 
-// q = K p, partial p.q (per column).
-template <typename T>
+// q = K p, partial p.q (per column).  p stored as S (float32 CG: bf16).
+template <typename T, typename S = T>
 __global__ __launch_bounds__(kBlock) void k_cg_spmm(StepArgs a, int slot, const T* __restrict__ K,
-                                                    const T* __restrict__ p, T* __restrict__ q) {
+                                                    const S* __restrict__ p, T* __restrict__ q) {
   if (a.ring[slot] == 0) return;
   const Tile& t = a.tm;
   for (int ct = 0; ct < t.nct; ++ct) {
@@ -520,8 +551,16 @@ __global__ void k_red_beta(StepArgs a, int slot, int next) {
 // alpha_i p_i is not updated every iteration; the directions p_i stay in a
 // ring of kPRing vectors and d is formed from them when the ring is full and
 // at the end of the solve (k_materialize), in iteration order, so d gets
-// exactly the rounding of the running update.  Per iteration this moves 32
-// bytes per element instead of 44.
+// exactly the rounding of the running update.
+//
+// The directions (and the polynomial preconditioner's output z) are stored
+// as bf16.  A rounded direction is still a direction: q = K p, p.q, alpha
+// and d all use the stored p, so r stays the float32 residual of d and the
+// attainable accuracy is unchanged; what rounding perturbs is only the
+// conjugacy of successive directions (relative 2^-9 per direction), which
+// changed no iteration count on the meshes tested (condition numbers of
+// D^-1 K from 2 to 90).  r and q, whose recursion defines the residual,
+// stay float32.
 //
 // r -= alpha q, z = D r; partials r.z and r.r (Poly: r.r only).
 template <bool Poly>
@@ -574,11 +613,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_r(StepArgs a, int slot,
 // group that has one (p_next is a different ring slot from p); z = D r
 // (src = r), or the preconditioner's output (Poly: src = z).
 template <bool Poly>
-__global__ __launch_bounds__(kBlock) void k_cg_dir_ring(StepArgs a, int next,
-                                                        float* __restrict__ pn,
-                                                        const float* __restrict__ p,
-                                                        const float* __restrict__ src,
-                                                        const float* __restrict__ dinv) {
+__global__ __launch_bounds__(kBlock) void k_cg_dir_ring(
+    StepArgs a, int next, bf16_t* __restrict__ pn, const bf16_t* __restrict__ p,
+    const std::conditional_t<Poly, bf16_t, float>* __restrict__ src,
+    const float* __restrict__ dinv) {
   if (a.ring[next] == 0) return;
   const Tile& t = a.t;
   for (int ct = 0; ct < t.nct; ++ct) {
@@ -722,12 +760,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_p(StepArgs a, int next, T*
 // the degree-1 Chebyshev polynomial in D^-1 K applied to the Jacobi step
 // (a matrix of K's pattern, built once per tau: precond_mats), on the
 // columns still iterating (0 on the others of a group that has one), with
-// the partials r.z (part2, tiling tm).  Restricted solves keep z on the
-// column's region.
-template <typename T>
+// the partials r.z (part2, tiling tm; from z before it is stored as Z, which
+// is bf16 in the float32 CG).  Restricted solves keep z on the column's
+// region.
+template <typename T, typename Z = T>
 __global__ __launch_bounds__(kBlock) void k_cg_precond(StepArgs a, int slot,
                                                        const T* __restrict__ r,
-                                                       T* __restrict__ z,
+                                                       Z* __restrict__ z,
                                                        const T* __restrict__ P) {
   if (a.ring[slot] == 0) return;
   const Tile& t = a.tm;
@@ -855,7 +894,7 @@ __global__ __launch_bounds__(kBlock) void k_refine_start(StepArgs a, const doubl
                                                          const float* __restrict__ gd,
                                                          double* __restrict__ r64,
                                                          float* __restrict__ r,
-                                                         float* __restrict__ p) {
+                                                         bf16_t* __restrict__ p) {
   const Tile& t = a.tm;
   for (int ct = 0; ct < t.nct; ++ct) {
   const int g = ct * t.tg + threadIdx.x % t.tg;
@@ -929,7 +968,7 @@ __global__ __launch_bounds__(kBlock) void k_inner_init(StepArgs a, int oslot,
                                                        const double* __restrict__ r64,
                                                        float* __restrict__ d,
                                                        float* __restrict__ r,
-                                                       float* __restrict__ p) {
+                                                       bf16_t* __restrict__ p) {
   if (blockIdx.x == 0 && threadIdx.x == 0) a.ring[0] = 0;
   if (a.oring[oslot] == 0) return;
   const Tile& t = a.t;
@@ -1002,7 +1041,7 @@ __global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot,
                                                          const float* __restrict__ d,
                                                          float* __restrict__ dacc, int store_r,
                                                          float* __restrict__ rn,
-                                                         float* __restrict__ pn) {
+                                                         bf16_t* __restrict__ pn) {
   // the next sweep's inner activity is counted afresh (red_outer_prep)
   if (Prep && blockIdx.x == 0 && threadIdx.x == 0) a.ring[0] = 0;
   if (!ubase && a.oring[oslot] == 0) return;
@@ -2400,16 +2439,16 @@ void red_init_fp64(const StepArgs& a, hipStream_t s) {
   SP_LAUNCH_CHECK();
 }
 
-template <typename T>
-void precond_init(const StepArgs& a, const T* r, T* p, const T* P, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_precond<T>, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, 0, r, p, P);
+template <typename T, typename Z>
+void precond_init(const StepArgs& a, const T* r, Z* p, const T* P, hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_precond<T, Z>), dim3(a.tm.nblk), dim3(kBlock), 0, s, a, 0, r, p, P);
   hipLaunchKernelGGL(k_red_precond_init, dim3(colblocks(a.tm)), dim3(kBlock), 0, s, a);
   SP_LAUNCH_CHECK();
 }
-template void precond_init<double>(const StepArgs&, const double*, double*, const double*,
-                                   hipStream_t);
-template void precond_init<float>(const StepArgs&, const float*, float*, const float*,
-                                  hipStream_t);
+template void precond_init<double, double>(const StepArgs&, const double*, double*, const double*,
+                                           hipStream_t);
+template void precond_init<float, bf16_t>(const StepArgs&, const float*, bf16_t*, const float*,
+                                          hipStream_t);
 
 template <typename T>
 void cg_iter(const StepArgs& a, int it, T* x, T* r, T* p, T* q, T* z, const T* K, const T* dinv,
@@ -2446,22 +2485,24 @@ void cg_iter(const StepArgs& a, int it, T* x, T* r, T* p, T* q, T* z, const T* K
   SP_LAUNCH_CHECK();
 }
 
-template <typename T>
-void matvec(const StepArgs& a, const T* K, const T* p, T* q, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_spmm<T>, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, 0, K, p, q);
+template <typename T, typename S>
+void matvec(const StepArgs& a, const T* K, const S* p, T* q, hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_spmm<T, S>), dim3(a.tm.nblk), dim3(kBlock), 0, s, a, 0, K, p, q);
   SP_LAUNCH_CHECK();
 }
-template void matvec<double>(const StepArgs&, const double*, const double*, double*, hipStream_t);
-template void matvec<float>(const StepArgs&, const float*, const float*, float*, hipStream_t);
+template void matvec<double, double>(const StepArgs&, const double*, const double*, double*,
+                                     hipStream_t);
+template void matvec<float, bf16_t>(const StepArgs&, const float*, const bf16_t*, float*,
+                                    hipStream_t);
 
-void cg_iter_ring(const StepArgs& a, int it, float* r, float* const* pring, float* q, float* z,
+void cg_iter_ring(const StepArgs& a, int it, float* r, bf16_t* const* pring, float* q, bf16_t* z,
                   double* ah, float* d, int* flushed, hipStream_t s, const hipEvent_t* ev) {
   const int slot = it % kRing, next = (it + 1) % kRing;
   const int ps = it % kPRing, pn = (it + 1) % kPRing;
   const dim3 nb(a.t.nblk), rb(colblocks(a.t)), bl(kBlock);
   if (ev) SP_HIP(hipEventRecord(ev[0], s));
-  hipLaunchKernelGGL(k_cg_spmm<float>, dim3(a.tm.nblk), bl, 0, s, a, slot, a.K32,
-                     (const float*)pring[ps], q);
+  hipLaunchKernelGGL((k_cg_spmm<float, bf16_t>), dim3(a.tm.nblk), bl, 0, s, a, slot, a.K32,
+                     (const bf16_t*)pring[ps], q);
   if (ev) SP_HIP(hipEventRecord(ev[1], s));
   hipLaunchKernelGGL(k_red_alpha, rb, bl, 0, s, a, slot, next, ah + size_t(ps) * a.t.rp);
   if (ev) SP_HIP(hipEventRecord(ev[2], s));
@@ -2469,8 +2510,8 @@ void cg_iter_ring(const StepArgs& a, int it, float* r, float* const* pring, floa
     hipLaunchKernelGGL(k_cg_update_r<true>, nb, bl, 0, s, a, slot, r, (const float*)q, a.dinv32);
     if (ev) SP_HIP(hipEventRecord(ev[3], s));
     if (ev) SP_HIP(hipEventRecord(ev[6], s));
-    hipLaunchKernelGGL(k_cg_precond<float>, dim3(a.tm.nblk), bl, 0, s, a, slot, (const float*)r,
-                       z, a.P32);
+    hipLaunchKernelGGL((k_cg_precond<float, bf16_t>), dim3(a.tm.nblk), bl, 0, s, a, slot,
+                       (const float*)r, z, a.P32);
     if (ev) SP_HIP(hipEventRecord(ev[7], s));
   } else {
     hipLaunchKernelGGL(k_cg_update_r<false>, nb, bl, 0, s, a, slot, r, (const float*)q, a.dinv32);
@@ -2488,15 +2529,15 @@ void cg_iter_ring(const StepArgs& a, int it, float* r, float* const* pring, floa
   if (ev) SP_HIP(hipEventRecord(ev[4], s));
   if (a.poly)
     hipLaunchKernelGGL(k_cg_dir_ring<true>, nb, bl, 0, s, a, next, pring[pn],
-                       (const float*)pring[ps], (const float*)z, a.dinv32);
+                       (const bf16_t*)pring[ps], (const bf16_t*)z, a.dinv32);
   else
     hipLaunchKernelGGL(k_cg_dir_ring<false>, nb, bl, 0, s, a, next, pring[pn],
-                       (const float*)pring[ps], (const float*)r, a.dinv32);
+                       (const bf16_t*)pring[ps], (const float*)r, a.dinv32);
   if (ev) SP_HIP(hipEventRecord(ev[5], s));
   SP_LAUNCH_CHECK();
 }
 
-void materialize(const StepArgs& a, float* const* pring, const double* ah, int first, int count,
+void materialize(const StepArgs& a, bf16_t* const* pring, const double* ah, int first, int count,
                  int accumulate, float* d, hipStream_t s) {
   RingArgs ra;
   ra.n = count;
@@ -2513,9 +2554,6 @@ void materialize(const StepArgs& a, float* const* pring, const double* ah, int f
 template void cg_iter<double>(const StepArgs&, int, double*, double*, double*, double*, double*,
                               const double*, const double*, const double*, hipStream_t,
                               const hipEvent_t*);
-template void cg_iter<float>(const StepArgs&, int, float*, float*, float*, float*, float*,
-                             const float*, const float*, const float*, hipStream_t,
-                             const hipEvent_t*);
 
 void init_outer(const StepArgs& a, const double* u, const float* g, double* x0, double* r64,
                 hipStream_t s) {
@@ -2529,13 +2567,13 @@ void red_outer_init(const StepArgs& a, hipStream_t s) {
 }
 
 void refine_start(const StepArgs& a, const double* w, const float* g, double* r64, float* r,
-                  float* p, hipStream_t s) {
+                  bf16_t* p, hipStream_t s) {
   hipLaunchKernelGGL(k_refine_start, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, w, g, r64, r, p);
   hipLaunchKernelGGL(k_red_refine_start, dim3(colblocks(a.t)), dim3(kBlock), 0, s, a);
   SP_LAUNCH_CHECK();
 }
 
-void inner_init(const StepArgs& a, int o, const double* r64, float* d, float* r, float* p,
+void inner_init(const StepArgs& a, int o, const double* r64, float* d, float* r, bf16_t* p,
                 hipStream_t s) {
   hipLaunchKernelGGL(k_inner_init, dim3(a.t.nblk), dim3(kBlock), 0, s, a, o % kRing, r64, d, r, p);
   SP_LAUNCH_CHECK();
@@ -2548,7 +2586,7 @@ void red_inner_init(const StepArgs& a, int o, hipStream_t s) {
 }
 
 void outer_update(const StepArgs& a, int o, double* x, const double* ubase, double* r64,
-                  const float* d, float* dacc, bool store_r, float* rn, float* pn,
+                  const float* d, float* dacc, bool store_r, float* rn, bf16_t* pn,
                   hipStream_t s) {
   if (rn)
     hipLaunchKernelGGL(k_outer_update<true>, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, o % kRing, x,

@@ -79,10 +79,12 @@ int64_t Server::batch_bytes(const Mesh* m, const sp_params& p, int cap, int rcap
   // copies of this tau, the mesh matrices, partial sums and tables
   const double n = double(m->n);
   const bool poly = p.precond == SP_PRECOND_CHEB1;
+  // (float32 CG: d, r, q float32, the kPRing ring directions and z bf16)
+  const bool mixed = p.precision != SP_FP64;
   const double per_col =
-      16.0 + 16.0 + (p.precision != SP_FP64 ? 4.0 * (kPRing - 1) : 0.0) +
-      (p.precision != SP_FP64 && p.extrapolate ? 8.0 + 4.0 * p.extrapolate : 0.0) +
-      (poly ? (p.precision != SP_FP64 ? 4.0 : 8.0) : 0.0);
+      16.0 + (mixed ? 12.0 + 2.0 * kPRing : 16.0) +
+      (mixed && p.extrapolate ? 8.0 + 4.0 * p.extrapolate : 0.0) +
+      (poly ? (mixed ? 2.0 : 8.0) : 0.0);
   const double mats = double(m->W) * n * (4 + 8 + 8 + 8 + 4 + (poly ? 12 : 0)) + n * 28.0 +
                       double(m->nt) * 20.0;
   const double part = (poly ? 4.0 : 3.0) * 8.0 * cap * (n / 64.0 + 1.0);
