@@ -18,7 +18,7 @@ namespace sp {
 
 namespace {
 
-constexpr char kMagic[8] = {'S', 'P', 'C', 'K', 'P', 'T', '0', '1'};
+constexpr char kMagic[8] = {'S', 'P', 'C', 'K', 'P', 'T', '0', '2'};
 
 struct Header {
   char magic[8];
@@ -27,7 +27,7 @@ struct Header {
   int32_t last_sweeps, reserved;
   int64_t steps_done;
   double tau;
-  Tile tm, t64;
+  Tile tm, t64, tp;
   int32_t seps_direct, seps_nper;
   int64_t hist_pairs;  // energy-history pairs over all restarts
   int64_t total;       // bytes of the whole image
@@ -85,6 +85,7 @@ void Solver::checkpoint(void* buf, int64_t bytes) {
   h.tau = prm_.tau;
   h.tm = args_.tm;
   h.t64 = args_.t64;
+  h.tp = args_.tp;
   h.seps_direct = sp_.direct;
   h.seps_nper = sp_.nper;
   int64_t pairs = 0;
@@ -204,6 +205,7 @@ void Solver::restore(const void* buf, int64_t bytes) {
   // the fixed reduction orders of the run that wrote the image
   args_.tm = h.tm;
   args_.t64 = h.t64;
+  args_.tp = h.tp;
   sp_.direct = h.seps_direct;
   sp_.nper = h.seps_nper;
 }

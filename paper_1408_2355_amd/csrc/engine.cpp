@@ -197,6 +197,7 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     a.ts = make_tile(n, rp_, 64, 1, 256);
     a.tm = t;   // gathering kernels: replaced by the autotuner's picks
     a.t64 = t;
+    a.tp = t;
     a.W = mesh_->W;
     a.cols = mesh_->cols.p;
     a.M64 = mesh_->M64.p;
@@ -402,6 +403,24 @@ void Solver::autotune() {
     const TuneChoice b64 = tune_tiling(key + "_gather64", &StepArgs::t64,
                                        [&] { k::norm_dot(args_, u_.p, nullptr, s_); });
     args_.t64 = make_tile(int(mesh_->n), rp_, b64.tg_cap, b64.passes, b64.nper_cap);
+  }
+  if (args_.poly) {
+    // the preconditioner pass gathers r (float32 or float64): its own tiling
+    k::fill_i32(args_.cg.act, 1, rp_, s_);
+    k::fill_i32(ring_.p, 1, 1, s_);
+    if (f64)
+      k::fill_f64(r64_.p, 1.0, nv, s_);
+    else
+      k::fill_f32(r32_.p, 1.0f, nv, s_);
+    const TuneChoice bp = tune_tiling(key + "_precond", &StepArgs::tp, [&] {
+      if (f64)
+        k::precond_init<double, double>(args_, r64_.p, p64_.p, km_->P64.p, s_);
+      else
+        k::precond_init<float, bf16_t>(args_, r32_.p, p16_.p, km_->P32.p, s_);
+    });
+    k::fill_i32(args_.cg.act, 0, rp_, s_);
+    k::fill_i32(ring_.p, 0, ring_.n, s_);
+    args_.tp = make_tile(int(mesh_->n), rp_, bp.tg_cap, bp.passes, bp.nper_cap);
   }
 
   // S_eps element kernel: LDS-staged, direct corner reads or lane-split,

@@ -54,6 +54,8 @@ struct StepArgs {
             // float32 in mixed precision); same n, rp
   Tile t64;  // tiling of the kernels that gather float64 values (solve set-up,
              // norms, Rayleigh quotients); same n, rp
+  Tile tp;   // tiling of the polynomial preconditioner's pass (its own gather,
+              // timed separately: its operand is the float32 r)
   int W;
   int nodal_fast = 0;  // set by the host when every column group lies in one 4-aligned
                        // restart inside its 256-column tile (ts one row per
@@ -85,7 +87,7 @@ struct StepArgs {
   // P = D^-1 (c0 I + c1 K D^-1), the Chebyshev polynomial of degree 1 for the
   // spectrum of D^-1 K applied to the Jacobi step, stored on K's pattern
   // (P64 / P32); part2 [nblk][rp] holds its pass's partial sums r.z (tiling
-  // tm).  poly == 0: Jacobi, z = D^-1 r formed inside the update kernels.
+  // tp).  poly == 0: Jacobi, z = D^-1 r formed inside the update kernels.
   int poly = 0;
   const double* P64 = nullptr;
   const float* P32 = nullptr;

@@ -529,7 +529,7 @@ __global__ void k_red_beta(StepArgs a, int slot, int next) {
   const int c = red_col();
   const Tile& t = a.t;
   const bool act = c < t.rp && a.cg.act[c];
-  const double rzn = Poly ? red_sum(a.part2, act ? a.tm.nchunk : 0, t.rp, c)
+  const double rzn = Poly ? red_sum(a.part2, act ? a.tp.nchunk : 0, t.rp, c)
                           : red_sum(a.part + part_off(t, 0), act ? t.nchunk : 0, t.rp, c);
   const double rr = red_sum(a.part + part_off(t, Poly ? 0 : 1), act ? t.nchunk : 0, t.rp, c);
   int still = 0;
@@ -760,7 +760,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_p(StepArgs a, int next, T*
 // the degree-1 Chebyshev polynomial in D^-1 K applied to the Jacobi step
 // (a matrix of K's pattern, built once per tau: precond_mats), on the
 // columns still iterating (0 on the others of a group that has one), with
-// the partials r.z (part2, tiling tm; from z before it is stored as Z, which
+// the partials r.z (part2, tiling tp; from z before it is stored as Z, which
 // is bf16 in the float32 CG).  Restricted solves keep z on the column's
 // region.
 template <typename T, typename Z = T>
@@ -769,7 +769,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_precond(StepArgs a, int slot,
                                                        Z* __restrict__ z,
                                                        const T* __restrict__ P) {
   if (a.ring[slot] == 0) return;
-  const Tile& t = a.tm;
+  const Tile& t = a.tp;
   for (int ct = 0; ct < t.nct; ++ct) {
   const int g = ct * t.tg + threadIdx.x % t.tg;
   double s[1][4] = {};
@@ -808,7 +808,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_precond(StepArgs a, int slot,
 // starting it (cg.act).
 __global__ void k_red_precond_init(StepArgs a) {
   const int c = red_col();
-  const Tile& t = a.tm;
+  const Tile& t = a.tp;
   const bool act = c < t.rp && a.cg.act[c];
   const double rz = red_sum(a.part2, act ? t.nchunk : 0, t.rp, c);
   if (red_lead() && act) a.cg.rz[c] = rz;
@@ -2441,8 +2441,8 @@ void red_init_fp64(const StepArgs& a, hipStream_t s) {
 
 template <typename T, typename Z>
 void precond_init(const StepArgs& a, const T* r, Z* p, const T* P, hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_precond<T, Z>), dim3(a.tm.nblk), dim3(kBlock), 0, s, a, 0, r, p, P);
-  hipLaunchKernelGGL(k_red_precond_init, dim3(colblocks(a.tm)), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL((k_cg_precond<T, Z>), dim3(a.tp.nblk), dim3(kBlock), 0, s, a, 0, r, p, P);
+  hipLaunchKernelGGL(k_red_precond_init, dim3(colblocks(a.tp)), dim3(kBlock), 0, s, a);
   SP_LAUNCH_CHECK();
 }
 template void precond_init<double, double>(const StepArgs&, const double*, double*, const double*,
@@ -2465,7 +2465,7 @@ void cg_iter(const StepArgs& a, int it, T* x, T* r, T* p, T* q, T* z, const T* K
                        (const T*)q, dinv);
     if (ev) SP_HIP(hipEventRecord(ev[3], s));
     if (ev) SP_HIP(hipEventRecord(ev[6], s));
-    hipLaunchKernelGGL(k_cg_precond<T>, dim3(a.tm.nblk), bl, 0, s, a, slot, (const T*)r, z, P);
+    hipLaunchKernelGGL(k_cg_precond<T>, dim3(a.tp.nblk), bl, 0, s, a, slot, (const T*)r, z, P);
     if (ev) SP_HIP(hipEventRecord(ev[7], s));
   } else {
     hipLaunchKernelGGL((k_cg_update<T, false>), nb, bl, 0, s, a, slot, x, r, (const T*)p,
@@ -2510,7 +2510,7 @@ void cg_iter_ring(const StepArgs& a, int it, float* r, bf16_t* const* pring, flo
     hipLaunchKernelGGL(k_cg_update_r<true>, nb, bl, 0, s, a, slot, r, (const float*)q, a.dinv32);
     if (ev) SP_HIP(hipEventRecord(ev[3], s));
     if (ev) SP_HIP(hipEventRecord(ev[6], s));
-    hipLaunchKernelGGL((k_cg_precond<float, bf16_t>), dim3(a.tm.nblk), bl, 0, s, a, slot,
+    hipLaunchKernelGGL((k_cg_precond<float, bf16_t>), dim3(a.tp.nblk), bl, 0, s, a, slot,
                        (const float*)r, z, a.P32);
     if (ev) SP_HIP(hipEventRecord(ev[7], s));
   } else {
