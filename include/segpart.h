@@ -141,7 +141,14 @@ typedef struct {
                            from u.  Ignored in SP_FP64 (always starts from u).
                            Each column keeps its own history: a request admitted
                            to a running server batch starts from its own state
-                           and the resident columns keep theirs                 */
+                           and the resident columns keep theirs.  q >= 2 is the
+                           largest order: before each extrapolation every column
+                           picks its order j in 0..q as the one whose backward
+                           difference of its kept increments, D_j = sum_{i<=j}
+                           (-1)^i C(j, i) d_{k-i}, is smallest on a sample of
+                           about 8192 vertices (q when the differences still fall
+                           at the deepest one kept): low orders while the flow
+                           still smooths a rough start, q once it is smooth  */
   int32_t precond;      /* CG preconditioner (both precisions).  SP_PRECOND_JACOBI:
                            z = D^-1 r, D the diagonal of M + tau A.
                            SP_PRECOND_CHEB1: z = (c0 I + c1 D^-1 K) D^-1 r, the

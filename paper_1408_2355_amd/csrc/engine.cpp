@@ -24,7 +24,7 @@ namespace sp {
 
 namespace {
 enum { CF_BB, CF_RZ, CF_TOL2, CF_ALPHA, CF_BETA, CF_RRO, CF_NRM, CF_BBN, CF_ISC, CF_COEF, CF_N };
-enum { CI_ACT, CI_ACTO, CI_ITERS, CI_SWEEPS, CI_SEGLO, CI_SEGLEN, CI_LIVE, CI_HLEN, CI_N };
+enum { CI_ACT, CI_ACTO, CI_ITERS, CI_SWEEPS, CI_SEGLO, CI_SEGLEN, CI_LIVE, CI_HLEN, CI_ORD, CI_N };
 constexpr int kSepsNperMax = 512;  // S_eps element-kernel workgroups per XCD, at most
 }  // namespace
 
@@ -153,7 +153,11 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     // autotuner may pick
     int max_blk = t.nblk;
     for (const Tile& c : tile_candidates()) max_blk = std::max(max_blk, c.nblk);
-    get(part_, 3 * size_t(max_blk) * rp_);
+    // three partial-sum slots per column, five for the extrapolation's order
+    // control (float32 CG with two or more kept increments)
+    const int part_slots =
+        prm_.precision != SP_FP64 && prm_.extrapolate >= 2 ? std::max(3, k::kOrderProbes) : 3;
+    get(part_, size_t(part_slots) * size_t(max_blk) * rp_);
     if (poly) get(part2_, size_t(max_blk) * rp_);
     get(part_s_, size_t(8 * sp_.nper) * nres_p_);
     get(colf_, size_t(CF_N) * rp_ + nres_p_);
@@ -186,6 +190,8 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     if (ah_.p) k::fill_f64(ah_.p, 0.0, ah_.n, s_);
     k::fill_f64(colf_.p, 0.0, colf_.n, s_);
     k::fill_i32(coli_.p, 0, coli_.n, s_);
+    // every column starts at the full extrapolation order
+    k::fill_i32(coli_.p + size_t(CI_ORD) * rp_, prm_.extrapolate, size_t(rp_), s_);
     k::fill_i32(ring_.p, 0, ring_.n, s_);
     k::fill_f64(reinterpret_cast<double*>(stat_.p), 0.0, stat_.n, s_);
     k::fill_f64(lam_.p, 0.0, lam_.n, s_);
@@ -198,6 +204,9 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     a.tm = t;   // gathering kernels: replaced by the autotuner's picks
     a.t64 = t;
     a.tp = t;
+    // the extrapolation's order control samples about 8192 rows
+    a.probe_stride = std::max(1, n / 8192);
+    a.tprobe = make_tile((n + a.probe_stride - 1) / a.probe_stride, rp_, 64, 1, 64);
     a.W = mesh_->W;
     a.cols = mesh_->cols.p;
     a.M64 = mesh_->M64.p;
@@ -237,6 +246,7 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
     a.ct.seg_len = ci + CI_SEGLEN * rp_;
     a.ct.live = ci + CI_LIVE * rp_;
     a.hlen = ci + CI_HLEN * rp_;
+    a.ord = ci + CI_ORD * rp_;
     a.ct.res_lo = ci + CI_N * rp_;
     a.ct.res_len = ci + CI_N * rp_ + nres_p_;
     a.ct.res_live = ci + CI_N * rp_ + 2 * nres_p_;
@@ -642,6 +652,7 @@ void Solver::forget_history(int c_lo, int cnt) {
   if (cnt <= 0) return;
   std::fill(h_hlen_.begin() + c_lo, h_hlen_.begin() + c_lo + cnt, 0);
   k::fill_i32(args_.hlen + c_lo, 0, size_t(cnt), s_);
+  k::fill_i32(args_.ord + c_lo, prm_.extrapolate, size_t(cnt), s_);
 }
 
 void Solver::unpack_range(int c_lo, int Rq, double* d_dst) {
@@ -726,7 +737,9 @@ void Solver::heat_mixed() {
       ExtrapArgs e;
       e.n = use;
       for (int j = 0; j < use; ++j) e.x[j] = dh_[j];
-      k::extrap(args_, e, acc, s_);
+      SP_REQUIRE(q < 2 || size_t(k::kOrderProbes) * size_t(args_.tprobe.nchunk) * rp_ <= part_.n,
+                 SP_EINVAL, "extrapolation: partial-sum buffer too small for the order control");
+      k::extrap(args_, e, acc, q, s_);
       acct(4.0 * use + 4.0);
     }
     if (fast) {

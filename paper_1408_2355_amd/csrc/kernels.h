@@ -54,6 +54,8 @@ struct StepArgs {
             // float32 in mixed precision); same n, rp
   Tile t64;  // tiling of the kernels that gather float64 values (solve set-up,
              // norms, Rayleigh quotients); same n, rp
+  Tile tprobe;           // tiling over the sampled rows of the extrapolation's
+  int probe_stride = 1;  // order control (every probe_stride-th row)
   Tile tp;   // tiling of the polynomial preconditioner's pass (its own gather,
               // timed separately: its operand is the float32 r)
   int W;
@@ -83,6 +85,8 @@ struct StepArgs {
   CgCols cg;
   int* hlen = nullptr;  // per column: heat increments kept for the extrapolated
                         // start (0 .. extrapolate)
+  int* ord = nullptr;   // per column: order of its next extrapolation (0 ..
+                        // extrapolate), chosen from its increments' differences
   // Polynomial preconditioner of the CG (poly != 0): z = P r with
   // P = D^-1 (c0 I + c1 K D^-1), the Chebyshev polynomial of degree 1 for the
   // spectrum of D^-1 K applied to the Jacobi step, stored on K's pattern
@@ -222,7 +226,14 @@ void red_outer_prep(const StepArgs& a, int o, hipStream_t s);
 void outer_residual(const StepArgs& a, int o, double* r64, const float* d, hipStream_t s);
 // y = sum_{j < h_c} (-1)^j C(h_c, j+1) e.x[j] per live column c, h_c =
 // min(hlen[c], e.n); 0 on the others; y may be one of the sources
-void extrap(const StepArgs& a, const ExtrapArgs& e, float* y, hipStream_t s);
+// h_c = min(hlen[c], ord[c], e.n).  qmax >= 2: first the order control, on
+// a sample of rows: ord of every live column with two or more kept increments
+// is set to the order j of least backward difference D_j of its increments
+// (qmax when the differences still fall at the deepest one kept).  It writes
+// kOrderProbes slots of partial sums (tiling tprobe): a.part must hold
+// kOrderProbes x tprobe.nchunk x rp doubles.
+constexpr int kOrderProbes = 5;
+void extrap(const StepArgs& a, const ExtrapArgs& e, float* y, int qmax, hipStream_t s);
 // hlen[c] = live ? min(hlen[c] + 1, q) : 0 (after a heat solve)
 void hist_advance(const StepArgs& a, int q, hipStream_t s);
 void red_outer(const StepArgs& a, int o, hipStream_t s);

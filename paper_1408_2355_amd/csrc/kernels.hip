@@ -677,11 +677,12 @@ __global__ __launch_bounds__(kBlock) void k_materialize(StepArgs a, RingArgs ra,
 
 // Start guess of the heat solve, per column c: y = sum_{j<h} (-1)^j C(h, j+1)
 // x_j, the polynomial extrapolation through the column's last h heat
-// increments x_0 (newest), x_1, ..., with h = min(hlen[c], e.n); 0 on columns
-// that are not live or have no increment yet (a column admitted to a running
-// batch starts from its own state while the others keep their history).  y
-// may be one of the sources (each element is read before it is written, by
-// the same thread).  A source whose 4 coefficients are 0 is not read.
+// increments x_0 (newest), x_1, ..., with h = min(hlen[c], ord[c], e.n); 0 on
+// columns that are not live or have no increment yet (a column admitted to a
+// running batch starts from its own state while the others keep their
+// history).  y may be one of the sources (each element is read before it is
+// written, by the same thread).  A source whose 4 coefficients are 0 is not
+// read.
 __global__ __launch_bounds__(kBlock) void k_extrap(StepArgs a, ExtrapArgs e, float* y) {
   const Tile& t = a.ts;
   for (int ct = 0; ct < t.nct; ++ct) {
@@ -690,7 +691,7 @@ __global__ __launch_bounds__(kBlock) void k_extrap(StepArgs a, ExtrapArgs e, flo
     const int cb = 4 * g;
     float cf[kMaxExtrap][4];
     for (int j = 0; j < 4; ++j) {
-      const int h = a.ct.live[cb + j] ? min(a.hlen[cb + j], e.n) : 0;
+      const int h = a.ct.live[cb + j] ? min(min(a.hlen[cb + j], a.ord[cb + j]), e.n) : 0;
       int binom = 1;  // C(h, q + 1), built up from C(h, 0) = 1
       for (int q = 0; q < kMaxExtrap; ++q) {
         if (q < h) {
@@ -714,6 +715,67 @@ __global__ __launch_bounds__(kBlock) void k_extrap(StepArgs a, ExtrapArgs e, flo
       st4s(y + o, yv);
     });
   }
+}
+
+// Order control of the extrapolation, on a sample of rows (every
+// a.probe_stride-th row; tiling a.tprobe over the sample): per column, the
+// sums of squares of the backward differences D_j = sum_{i<=j} (-1)^i C(j, i)
+// x_i of the kept increments, j below their number (partial slots
+// 0..kMaxOrderProbe-1).  Extrapolating with order j neglects the j-th
+// difference at the next step, which |D_j| estimates.
+constexpr int kMaxOrderProbe = k::kOrderProbes;
+__global__ __launch_bounds__(kBlock) void k_extrap_probe(StepArgs a, ExtrapArgs e) {
+  const Tile& t = a.tprobe;
+  for (int ct = 0; ct < t.nct; ++ct) {
+    const int g = ct * t.tg + threadIdx.x % t.tg;
+    double s[kMaxOrderProbe][4] = {};
+    if (g < t.G) {
+      const int cb = 4 * g;
+      int nd[4], nread = 0;
+      for (int j = 0; j < 4; ++j) {
+        nd[j] = a.ct.live[cb + j] ? min(min(a.hlen[cb + j], e.n), kMaxOrderProbe) : 0;
+        nread = max(nread, nd[j]);
+      }
+      for_rows(t, [&](int srow) {
+        const size_t o = size_t(srow) * size_t(a.probe_stride) * t.rp + cb;
+        V4<float> xs[kMaxOrderProbe] = {};
+        for (int q = 0; q < nread; ++q) xs[q] = ld4s(e.x[q] + o);
+        // difference table in float64 (differences of float32 values are exact
+        // there): after pass k its first entry is D_k
+        for (int j = 0; j < 4; ++j) {
+          double d[kMaxOrderProbe];
+          for (int i = 0; i < kMaxOrderProbe; ++i) d[i] = i < nd[j] ? double(xs[i].v[j]) : 0.0;
+          s[0][j] += d[0] * d[0];
+          for (int k = 1; k < kMaxOrderProbe; ++k) {
+            for (int i = 0; i + k < kMaxOrderProbe; ++i) d[i] -= d[i + 1];
+            if (k < nd[j]) s[k][j] += d[0] * d[0];
+          }
+        }
+      });
+    }
+    block_store<kMaxOrderProbe>(t, s, a.part, blockIdx.x, ct);
+  }
+}
+
+// This step's extrapolation order per live column with at least two kept
+// increments: the j of least |D_j| (j below the number kept, ties to the
+// lower), or qmax when that is the deepest difference measured (the
+// differences are still falling).
+__global__ void k_red_extrap_order(StepArgs a, int n_kept, int qmax) {
+  const int c = red_col();
+  const Tile& t = a.tprobe;
+  const int nd = c < t.rp && a.ct.live[c] ? min(min(a.hlen[c], n_kept), kMaxOrderProbe) : 0;
+  double e[kMaxOrderProbe];
+  for (int d = 0; d < kMaxOrderProbe; ++d)
+    e[d] = red_sum(a.part + part_off(t, d), d < nd ? t.nchunk : 0, t.rp, c);
+  if (!red_lead() || nd < 2) return;
+  int best = 0;
+  bool finite = e[0] == e[0];
+  for (int d = 1; d < nd; ++d) {
+    finite &= e[d] == e[d];
+    if (e[d] < e[best]) best = d;
+  }
+  if (finite) a.ord[c] = best == nd - 1 ? qmax : best;
 }
 
 // After a heat solve: every live column has one more increment kept (at most
@@ -2608,7 +2670,12 @@ void outer_residual(const StepArgs& a, int o, double* r64, const float* d, hipSt
   SP_LAUNCH_CHECK();
 }
 
-void extrap(const StepArgs& a, const ExtrapArgs& e, float* y, hipStream_t s) {
+void extrap(const StepArgs& a, const ExtrapArgs& e, float* y, int qmax, hipStream_t s) {
+  if (qmax >= 2) {
+    hipLaunchKernelGGL(k_extrap_probe, dim3(a.tprobe.nblk), dim3(kBlock), 0, s, a, e);
+    hipLaunchKernelGGL(k_red_extrap_order, dim3(colblocks(a.tprobe)), dim3(kBlock), 0, s, a, e.n,
+                       qmax);
+  }
   hipLaunchKernelGGL(k_extrap, dim3(a.ts.nblk), dim3(kBlock), 0, s, a, e, y);
   SP_LAUNCH_CHECK();
 }

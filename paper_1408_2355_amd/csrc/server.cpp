@@ -87,7 +87,10 @@ int64_t Server::batch_bytes(const Mesh* m, const sp_params& p, int cap, int rcap
       (poly ? (mixed ? 2.0 : 8.0) : 0.0);
   const double mats = double(m->W) * n * (4 + 8 + 8 + 8 + 4 + (poly ? 12 : 0)) + n * 28.0 +
                       double(m->nt) * 20.0;
-  const double part = (poly ? 4.0 : 3.0) * 8.0 * cap * (n / 64.0 + 1.0);
+  // partial sums: 3 slots (5 with the extrapolation's order control), +1 for
+  // the polynomial preconditioner's pass
+  const double part = ((mixed && p.extrapolate >= 2 ? 5.0 : 3.0) + (poly ? 1.0 : 0.0)) * 8.0 * cap *
+                      (n / 64.0 + 1.0);
   // staging of request state (admission and retirement) and of labels
   const double stage = 8.0 * n * cap + 4.0 * n * rcap;
   return int64_t(n * cap * per_col + mats + part + stage + 64.0 * (cap + rcap) + (1 << 20));
