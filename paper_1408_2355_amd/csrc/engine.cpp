@@ -147,7 +147,10 @@ Solver::Solver(Mesh* mesh, const sp_params& prm, const BatchSpec& spec, const hi
         get(dbuf_[i], nv);
         dh_[i] = dbuf_[i].p;
       }
-      if (prm_.extrapolate) get(xg_, nv);
+      if (prm_.extrapolate) {
+        get(xg_, nv);
+        get(d0buf_, nv);
+      }
     }
     // partial sums: one row per workgroup, sized for the widest tiling the
     // autotuner may pick
@@ -764,6 +767,10 @@ void Solver::heat_mixed() {
   }
   int olast = 0;
   bool prepared = false;  // the last update wrote this sweep's inner start
+  // sweep 0 of a fast start expected to need another sweep keeps its
+  // correction in d0buf_ and leaves the iterate to the next sweep (one pass
+  // over u, x and dacc fewer); deferred: the iterate is not formed yet
+  bool deferred = false;
   for (int o = 0; o < prm_.max_outer; ++o) {
     if (!(fast && o == 0) && !prepared) {
       k::inner_init(args_, o, r64_.p, d32_.p, r32_.p, args_.poly ? nullptr : p16_.p, s_);
@@ -799,13 +806,23 @@ void Solver::heat_mixed() {
     // more than one sweep, the update writes the next sweep's start as well
     const bool polled = prm_.check_every > 0 && o + 1 < prm_.max_outer;
     const bool prep = polled && o + 1 < last_sweeps_;
-    const bool ubase = fast && o == 0;
+    const bool defer = fast && o == 0 && prep && d0buf_.p;
+    const bool formx = deferred;  // this sweep forms the iterate sweep 0 deferred
+    const bool ubase = (fast && o == 0 && !defer) || formx;
     args_.usc = ubase && u_pending_ ? args_.cg.isc : nullptr;
-    k::outer_update(args_, o, x, ubase ? u_.p : nullptr, r64_.p, d32_.p, acc, !polled,
-                    prep ? r32_.p : nullptr, prep && !args_.poly ? p16_.p : nullptr, s_);
-    acct(28.0 + (polled && !prep ? 0.0 : 8.0) + (acc ? 8.0 : 0.0) +
-             (prep ? (args_.poly ? 4.0 : 6.0) : 0.0),
-         mat_bytes(8.0, 1));
+    if (defer) {
+      k::outer_update(args_, o, nullptr, nullptr, r64_.p, d32_.p, nullptr, true, r32_.p,
+                      args_.poly ? nullptr : p16_.p, d0buf_.p, 1, s_);
+      acct(28.0 + (args_.poly ? 0.0 : 2.0), mat_bytes(8.0, 1));
+    } else {
+      k::outer_update(args_, o, x, ubase ? u_.p : nullptr, r64_.p, d32_.p, acc, !polled,
+                      prep ? r32_.p : nullptr, prep && !args_.poly ? p16_.p : nullptr,
+                      formx ? d0buf_.p : nullptr, formx ? 2 : 0, s_);
+      acct(28.0 + (polled && !prep ? 0.0 : 8.0) + (acc ? 8.0 : 0.0) +
+               (prep ? (args_.poly ? 4.0 : 6.0) : 0.0) + (formx ? 4.0 : 0.0),
+           mat_bytes(8.0, 1));
+    }
+    deferred = defer;
     args_.usc = nullptr;
     if (prep) {
       k::red_outer_prep(args_, o, s_);
@@ -822,6 +839,15 @@ void Solver::heat_mixed() {
         acct(20.0, mat_bytes(8.0, 1));
       }
     }
+  }
+  if (deferred) {
+    // the solve ended after the deferred sweep 0: form the iterate (no
+    // column is refining, so no residual work)
+    args_.usc = u_pending_ ? args_.cg.isc : nullptr;
+    k::outer_update(args_, olast, x, u_.p, r64_.p, d32_.p, acc, false, nullptr, nullptr,
+                    d0buf_.p, 2, s_);
+    acct(28.0);
+    args_.usc = nullptr;
   }
   last_sweeps_ = olast;
   k::flag_nonconv(args_, args_.oring + olast % kRing, s_);

@@ -212,6 +212,7 @@ class Solver {
   // columns [c_lo, c_lo + cnt) have no previous increment (all columns: n_prev_ = 0)
   void forget_history(int c_lo, int cnt);
   DevBuf<double> xg_;          // iterate of a solve started from u + g (u stays b's source)
+  DevBuf<float> d0buf_;        // sweep 0's correction while the iterate is deferred
   double* heat_x_ = nullptr;   // where the last heat solve left its result (u_ or xg_)
   bool small_ = false;         // whole steps in one workgroup (small batches)
   // refinement sweeps the last mixed heat solve took: sweep o's update also

@@ -216,9 +216,12 @@ void red_inner_init(const StepArgs& a, int o, hipStream_t s);
 // outer_residual before another sweep).  rn, pn (nullable, both or neither):
 // also the next sweep's inner start r = float(r64), p = D r (r64 stored);
 // reduce with red_outer_prep instead of red_outer
+// d0mode 1 (deferred iterate; x, ubase, dacc unused): d0 = d where the column
+// is refining, 0 on the other columns of live groups; d0mode 2 (ubase given):
+// x = ubase + dacc + d0 (+ d), dacc += d0 (+ d) on every live group.
 void outer_update(const StepArgs& a, int o, double* x, const double* ubase, double* r64,
-                  const float* d, float* dacc, bool store_r, float* rn, bf16_t* pn,
-                  hipStream_t s);
+                  const float* d, float* dacc, bool store_r, float* rn, bf16_t* pn, float* d0,
+                  int d0mode, hipStream_t s);
 // outer test of sweep o and, for the columns still refining, the scalars of
 // the inner start that outer_update(rn, pn) wrote
 void red_outer_prep(const StepArgs& a, int o, hipStream_t s);

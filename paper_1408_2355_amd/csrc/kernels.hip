@@ -1095,6 +1095,13 @@ __global__ void k_red_inner_init(StepArgs a, int oslot, int onext) {
 // refining), with its partials r.p and ||r||^2, so the sweep after this one
 // needs neither outer_residual nor inner_init (red_outer_prep reduces all
 // three); r64 must be stored then.
+// Deferred iterate (d0mode): when the solve is expected to need another
+// sweep, sweep 0 leaves x and dacc alone (d0mode 1: x, ubase, dacc unused)
+// and keeps its correction in d0 (0 where the column is not refining), and
+// the next sweep forms the iterate in ubase mode with d0 as one more addend
+// (d0mode 2): x = ((ubase + dacc) + d0) + d, dacc + d0 + d, the same sums in
+// the same order as forming x in sweep 0 and adding to it in sweep 1, with
+// one pass over u, x and dacc fewer.
 template <bool Prep>
 __global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot,
                                                          double* __restrict__ x,
@@ -1103,10 +1110,12 @@ __global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot,
                                                          const float* __restrict__ d,
                                                          float* __restrict__ dacc, int store_r,
                                                          float* __restrict__ rn,
-                                                         bf16_t* __restrict__ pn) {
+                                                         bf16_t* __restrict__ pn,
+                                                         float* __restrict__ d0, int d0mode) {
   // the next sweep's inner activity is counted afresh (red_outer_prep)
   if (Prep && blockIdx.x == 0 && threadIdx.x == 0) a.ring[0] = 0;
-  if (!ubase && a.oring[oslot] == 0) return;
+  // (d0mode 1 writes d0 on every live group, refining or not)
+  if (!ubase && d0mode != 1 && a.oring[oslot] == 0) return;
   const Tile& t = a.tm;
   for (int ct = 0; ct < t.nct; ++ct) {
   const int g = ct * t.tg + threadIdx.x % t.tg;
@@ -1122,7 +1131,7 @@ __global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot,
       anylive |= a.ct.live[c0 + j];
       if (a.usc) usc[j] = a.usc[c0 + j];
     }
-    if (any || (ubase && anylive)) {
+    if (any || ((ubase || d0mode == 1) && anylive)) {
       for_rows(t, [&](int row) {
         double kd[4] = {};
         float dd[4] = {};
@@ -1135,13 +1144,22 @@ __global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot,
           });
         const size_t o = size_t(row) * t.rp + c0;
         V4<float> av = {};
-        if (dacc) av = ld4g(dacc + o);
-        V4<double> xv;
-        if (ubase) {
-          const V4<double> ub = ld4g(ubase + o);
-          for (int j = 0; j < 4; ++j) xv.v[j] = mul_alone(ub.v[j], usc[j]) + double(av.v[j]);
-        } else {
-          xv = ld4g(x + o);
+        V4<double> xv = {};
+        if (d0mode != 1) {
+          if (dacc) av = ld4g(dacc + o);
+          if (ubase) {
+            const V4<double> ub = ld4g(ubase + o);
+            for (int j = 0; j < 4; ++j) xv.v[j] = mul_alone(ub.v[j], usc[j]) + double(av.v[j]);
+            if (d0mode == 2) {
+              const V4<float> e0 = ld4g(d0 + o);
+              for (int j = 0; j < 4; ++j) {
+                xv.v[j] += double(e0.v[j]);
+                av.v[j] += e0.v[j];
+              }
+            }
+          } else {
+            xv = ld4g(x + o);
+          }
         }
         V4<double> rv = {};
         if (any) rv = ld4g(r64 + o);
@@ -1153,9 +1171,15 @@ __global__ __launch_bounds__(kBlock) void k_outer_update(StepArgs a, int oslot,
             av.v[j] += dd[j];
           }
         }
-        st4g(x + o, xv);
+        if (d0mode == 1) {
+          V4<float> e0;
+          for (int j = 0; j < 4; ++j) e0.v[j] = act[j] ? dd[j] : 0.0f;
+          st4g(d0 + o, e0);
+        } else {
+          st4g(x + o, xv);
+          if (dacc && (any || d0mode == 2)) st4g(dacc + o, av);
+        }
         if (any && store_r) st4g(r64 + o, rv);
-        if (dacc && any) st4g(dacc + o, av);
         if constexpr (Prep) {
           if (any) {
             const float di = a.dinv32[row];
@@ -2648,14 +2672,14 @@ void red_inner_init(const StepArgs& a, int o, hipStream_t s) {
 }
 
 void outer_update(const StepArgs& a, int o, double* x, const double* ubase, double* r64,
-                  const float* d, float* dacc, bool store_r, float* rn, bf16_t* pn,
-                  hipStream_t s) {
+                  const float* d, float* dacc, bool store_r, float* rn, bf16_t* pn, float* d0,
+                  int d0mode, hipStream_t s) {
   if (rn)
     hipLaunchKernelGGL(k_outer_update<true>, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, o % kRing, x,
-                       ubase, r64, d, dacc, 1, rn, pn);
+                       ubase, r64, d, dacc, 1, rn, pn, d0, d0mode);
   else
     hipLaunchKernelGGL(k_outer_update<false>, dim3(a.tm.nblk), dim3(kBlock), 0, s, a, o % kRing,
-                       x, ubase, r64, d, dacc, int(store_r), nullptr, nullptr);
+                       x, ubase, r64, d, dacc, int(store_r), nullptr, nullptr, d0, d0mode);
   SP_LAUNCH_CHECK();
 }
 

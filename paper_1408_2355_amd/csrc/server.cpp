@@ -74,16 +74,17 @@ bool Server::compatible(const sp_params& a, const sp_params& b) {
 int64_t Server::batch_bytes(const Mesh* m, const sp_params& p, int cap, int rcap) {
   // state u and outer residual (float64) + CG vectors (float64 pair or
   // float32 quad, plus the rest of the float32 direction ring) and, for the
-  // extrapolated start, the float32 increments and a float64 iterate per
-  // element, the polynomial preconditioner's output, the float64/float32 K
-  // copies of this tau, the mesh matrices, partial sums and tables
+  // extrapolated start, the float32 increments, a float64 iterate and a
+  // float32 deferred correction per element, the polynomial preconditioner's
+  // output, the float64/float32 K copies of this tau, the mesh matrices,
+  // partial sums and tables
   const double n = double(m->n);
   const bool poly = p.precond == SP_PRECOND_CHEB1;
   // (float32 CG: d, r, q float32, the kPRing ring directions and z bf16)
   const bool mixed = p.precision != SP_FP64;
   const double per_col =
       16.0 + (mixed ? 12.0 + 2.0 * kPRing : 16.0) +
-      (mixed && p.extrapolate ? 8.0 + 4.0 * p.extrapolate : 0.0) +
+      (mixed && p.extrapolate ? 12.0 + 4.0 * p.extrapolate : 0.0) +
       (poly ? (mixed ? 2.0 : 8.0) : 0.0);
   const double mats = double(m->W) * n * (4 + 8 + 8 + 8 + 4 + (poly ? 12 : 0)) + n * 28.0 +
                       double(m->nt) * 20.0;
