@@ -118,3 +118,32 @@ def test_kernel_profile_classes(pc):
         assert kt[sp.SP_KERNEL_PRECOND][0] == n_iter and kt[sp.SP_KERNEL_PRECOND][2] > 0
     else:
         assert kt[sp.SP_KERNEL_PRECOND][0] == 0
+
+
+def test_deferred_iterate_when_the_solve_ends_early():
+    """A refinement sweep 0 predicted to be followed by another keeps its
+    correction and leaves the iterate to the next sweep; when the step then
+    converges after sweep 0 after all (a step with one sweep right after one
+    with two), a last update forms the iterate.  The run passes through such
+    steps and still matches the oracle."""
+    v, f = icosphere(5)
+    u0, ms = batch_u0(v.shape[0], [(65, 2, 4)])
+    eps = np.full(ms.size, 0.05)
+    tau = 2e-4
+    mesh = sp.Mesh(v, f)
+    prm = sp.params(tau, precision="mixed", n_steps=1, energy_every=0, cg_rtol=1e-10)
+    st = sp.State(mesh, prm, ms, eps, u0)
+    sweeps, steps, seen = [], 0, -1
+    while steps < 120 and (seen < 0 or steps < seen + 5):
+        s0 = st.stats()["outer_sweeps"]
+        st.step(1)
+        steps += 1
+        sweeps.append(st.stats()["outer_sweeps"] - s0)
+        if seen < 0 and len(sweeps) >= 2 and sweeps[-2] >= 2 and sweeps[-1] == 1:
+            seen = steps
+    u, k = st.read()
+    st.close()
+    mesh.close()
+    assert seen > 0, sweeps
+    ref = flow.run(flow.Problem(v, f, tau), u0[:4], [4], [0.05], k)
+    assert rel(u[:4], ref["u"]) < 1e-5
