@@ -46,3 +46,41 @@ def test_graph_replays_equal_eager_launches(monkeypatch):
         eager.close()
         graph.close()
         mesh.close()
+
+
+@pytest.mark.parametrize("every", [1, 3])
+def test_multi_step_call_equals_single_steps(every):
+    """Steps taken in calls of several steps (the CG blocks replayed from
+    graphs across step boundaries, the energies recorded at the cadence inside
+    the call) equal the same steps taken one call at a time, bit for bit:
+    states, energies, the energy history and the iteration counts (energy
+    every step and every third step)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    v, f = icosphere(4)
+    ms, eps = [4, 4], [0.05, 0.08]
+    u0 = uniform_u0(52, 1, 8, v.shape[0])
+    mesh = sp.Mesh(v, f)
+    prm = sp.params(1e-3, precision="mixed", n_steps=1, energy_every=every, cg_rtol=1e-10,
+                    check_every=8, extrapolate=5)
+    one = sp.State(mesh, prm, ms, eps, u0)
+    many = sp.State(mesh, prm, ms, eps, u0)
+    try:
+        print(f"multi-step call, energy every {every}", flush=True)
+        assert many.step(5) == sp.SP_OK and many.step(9) == sp.SP_OK
+        for _ in range(14):
+            assert one.step(1) == sp.SP_OK
+        assert np.array_equal(one.read()[0], many.read()[0])
+        assert all(np.array_equal(a, b) for a, b in zip(one.energy(), many.energy()))
+        for r in range(len(ms)):
+            ko, eo = one.history(r)
+            km, em = many.history(r)
+            assert np.array_equal(ko, km) and np.array_equal(eo, em)
+            # every step of the cadence is recorded once
+            assert set(range(every, 15, every)) <= set(km.tolist())
+        so, sm = one.stats(), many.stats()
+        assert so["cg_iters"] == sm["cg_iters"] and so["outer_sweeps"] == sm["outer_sweeps"]
+    finally:
+        one.close()
+        many.close()
+        mesh.close()
