@@ -442,7 +442,25 @@ void Solver::autotune() {
   // holds the largest count's partials).  With every workgroup resident the
   // XCD walks each restart tile's triangles together, so the corner rows
   // that neighbouring triangles share meet in L2.
-  if (sp_.ntile > 0) {
+  // The pick is cached with the restart layout (as the tilings are), so every
+  // state of the same batch runs the same S_eps kernel and partial-sum rows,
+  // and so gets the same energies bit for bit.
+  uint64_t lay = 1469598103934665603ull;  // FNV-1a over the restarts' columns
+  for (int r = 0; r < nres_p_; ++r)
+    for (int v : {h_res_lo_[r], h_res_len_[r]})
+      for (int b = 0; b < 4; ++b) {
+        lay ^= uint64_t((uint32_t(v) >> (8 * b)) & 0xffu);
+        lay *= 1099511628211ull;
+      }
+  const std::string skey = key + "_nt" + std::to_string(mesh_->nt) + "_seps" + std::to_string(lay);
+  const int seps_nper_max = std::max(1, std::min(kSepsNperMax, (sp_.nchunk + 7) / 8));
+  TuneChoice cached;
+  if (sp_.ntile > 0 && tune_lookup(skey, &cached) && (cached.tg_cap != 2 || sp_.lanes_ok) &&
+      cached.tg_cap >= 0 && cached.tg_cap <= 2 && cached.nper_cap >= 1 &&
+      cached.nper_cap <= seps_nper_max) {
+    sp_.direct = cached.tg_cap;
+    sp_.nper = cached.nper_cap;
+  } else if (sp_.ntile > 0) {
     hipEvent_t e0, e1;
     SP_HIP(hipEventCreate(&e0));
     SP_HIP(hipEventCreate(&e1));
@@ -480,6 +498,12 @@ void Solver::autotune() {
     sp_.nper = best_nper;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    TuneChoice pick;  // (kernel mode, workgroups per XCD) in the tiling fields
+    pick.tg_cap = best;
+    pick.passes = 1;
+    pick.nper_cap = best_nper;
+    pick.us = 500.0 * t_best;
+    tune_store(skey, pick);
   }
 }
 
